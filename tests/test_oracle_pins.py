@@ -1,0 +1,474 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, brute-force enumeration, a library routine in a special case where the
+method reduces to it, or an identity of the paper (Method section Eqs. (2)-(10),
+Appendix A).  A plausible slip (dropped term, wrong sign or index, transposed
+operand) breaks at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bmps, ed, hamiltonian, measure, network, philox, sampler, sr
+from oracle.lattice import MODEL_HUBBARD, Lattice
+
+# ---------------------------------------------------------------------------
+# Philox4x64-10 against NumPy's independent implementation.  NumPy advances
+# its counter before producing a block, so counter c there yields block c+1.
+
+
+@pytest.mark.parametrize("ctr,key", [
+    ((1, 0, 0, 0), (0, 0)),
+    ((5, 7, 9, 11), (123, 0)),
+    ((2 ** 64 - 1, 3, 2 ** 63, 17), (2 ** 64 - 5, 99)),
+    ((1000, 2, 287, 0), (20240905, 0)),
+])
+def test_philox_matches_numpy(ctr, key):
+    prev = list(ctr)
+    prev[0] = (prev[0] - 1) % 2 ** 64
+    if ctr[0] == 0:
+        prev[1] = (prev[1] - 1) % 2 ** 64
+    bg = np.random.Philox(counter=np.array(prev, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
+    ref = [int(bg.random_raw()) for _ in range(4)]
+    assert list(philox.philox4x64_10(ctr, key)) == ref
+
+
+def test_uniform_range_and_positional():
+    us = [philox.uniform(7, ch, g, s) for ch in range(3) for g in range(3) for s in range(20)]
+    assert all(0.0 <= u < 1.0 for u in us)
+    assert len(set(us)) == len(us)
+    assert philox.uniform(7, 2, 1, 5) == philox.uniform(7, 2, 1, 5)
+
+
+# ---------------------------------------------------------------------------
+# Exact contraction (Eq. 4)
+
+
+def test_exact_amplitude_product_state():
+    """D = 1: the network is a product of scalars T_i[S_i] (closed form)."""
+    lat = Lattice(3, 3, D=1, chi=1)
+    th = synth.theta_random_unit(3, 3, 1, 2, seed=3)
+    S = synth.configs_uniform(1, 9, 2, seed=4)[0]
+    want = 1.0
+    for r in range(3):
+        for c in range(3):
+            want *= lat.site_tensor(th, r, c)[S[lat.site(r, c)]].reshape(())
+    assert network.amplitude(lat, th, S) == pytest.approx(want, rel=1e-14)
+
+
+def test_exact_amplitude_2x2_brute_force():
+    """2x2, D = 3: explicit sum over the four internal bond indices."""
+    lat = Lattice(2, 2, D=3, chi=9)
+    th = synth.theta_random_unit(2, 2, 3, 2, seed=5)
+    for S in synth.configs_uniform(4, 4, 2, seed=6):
+        T = [lat.row_slices(th, S, r) for r in range(2)]
+        A, B = T[0]              # (0,0), (0,1)
+        C, Dm = T[1]             # (1,0), (1,1)
+        tot = 0.0
+        for h0, h1, v0, v1 in itertools.product(range(3), repeat=4):
+            tot += (A[0, 0, h0, v0] * B[h0, 0, 0, v1] *
+                    C[0, v0, h1, 0] * Dm[h1, v1, 0, 0])
+        assert network.amplitude(lat, th, S) == pytest.approx(tot, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Boundary MPS (P2) and the compression C_chi
+
+
+@pytest.mark.parametrize("L1,L2,D,chi", [(2, 2, 3, 3), (3, 3, 2, 4), (3, 3, 3, 9), (4, 4, 2, 4), (3, 4, 2, 4)])
+def test_boundary_mps_exact_at_large_chi(L1, L2, D, chi):
+    """chi >= D^floor(L2/2): no truncation, every strip equals the exact
+    amplitude (the 4x4, D=2, chi=4 case is the small cooling workload)."""
+    lat = Lattice(L1, L2, D=D, chi=chi)
+    th = synth.theta_random_unit(L1, L2, D, 2, seed=11)
+    for S in synth.configs_sector(3, lat.N, 2, seed=12):
+        ex = network.amplitude(lat, th, S)
+        tops = bmps.top_boundaries(lat, th, S, chi)
+        bots = bmps.bot_boundaries(lat, th, S, chi)
+        W = [lat.row_slices(th, S, r) for r in range(L1)]
+        for r in range(L1):
+            v = bmps.strip1(tops[r][0], W[r], bots[r + 1][0]) * math.exp(tops[r][1] + bots[r + 1][1])
+            assert v == pytest.approx(ex, rel=1e-11)
+        for r in range(L1 - 1):
+            v = bmps.strip2(tops[r][0], W[r], W[r + 1], bots[r + 2][0]) * math.exp(tops[r][1] + bots[r + 2][1])
+            assert v == pytest.approx(ex, rel=1e-11)
+        ev = measure.evaluate(lat, th, S, chi, want_O=False)
+        assert ev["log_abs"] == pytest.approx(math.log(abs(ex)), abs=1e-11)
+        assert ev["sign"] == (1 if ex > 0 else -1)
+
+
+def _mps_vector(A):
+    v = A[0]
+    for t in A[1:]:
+        v = np.tensordot(v, t, axes=(v.ndim - 1, 0))
+    return v.reshape(-1)
+
+
+def test_compress_two_sites_is_eckart_young():
+    """For two sites C_chi is the rank-chi truncated SVD of the 2-site matrix
+    (numpy.linalg.svd applied to the whole state)."""
+    rng = np.random.default_rng(0)
+    A = [rng.standard_normal((1, 5, 7)), rng.standard_normal((7, 6, 1))]
+    M = np.tensordot(A[0], A[1], axes=(2, 0)).reshape(5, 6)
+    U, s, Vt = np.linalg.svd(M)
+    k = 3
+    Mk = (U[:, :k] * s[:k]) @ Vt[:k]
+    out, ls = bmps.compress(A, k)
+    got = _mps_vector(out) * math.exp(ls)
+    np.testing.assert_allclose(got, Mk.reshape(-1), rtol=0, atol=1e-12 * np.abs(Mk).max())
+
+
+def test_compress_preserves_state_without_truncation_and_is_canonical():
+    rng = np.random.default_rng(1)
+    shapes = [(1, 3, 4), (4, 3, 5), (5, 2, 6), (6, 3, 2), (2, 3, 1)]
+    A = [rng.standard_normal(s) for s in shapes]
+    v = _mps_vector(A)
+    out, ls = bmps.compress(A, 100)
+    np.testing.assert_allclose(_mps_vector(out) * math.exp(ls), v, rtol=1e-12, atol=1e-12 * np.abs(v).max())
+    assert np.linalg.norm(out[0]) == pytest.approx(1.0, rel=1e-13)
+    for t in out[1:]:
+        a, p, b = t.shape
+        m = t.reshape(a, p * b)
+        np.testing.assert_allclose(m @ m.T, np.eye(a), atol=1e-13)
+    assert [t.shape for t in out] == bmps.bond_dims_after(shapes, 100)
+
+
+def test_compress_truncation_is_sequential_svd():
+    """Truncating only the last bond reduces to one SVD of the state matrix
+    split between sites (0..L-2 | L-1), chi >= every other Schmidt rank."""
+    rng = np.random.default_rng(2)
+    shapes = [(1, 2, 2), (2, 2, 4), (4, 3, 1)]
+    A = [rng.standard_normal(s) for s in shapes]
+    v = _mps_vector(A).reshape(4, 3)
+    U, s, Vt = np.linalg.svd(v)
+    k = 2
+    out, ls = bmps.compress(A, k)
+    np.testing.assert_allclose(_mps_vector(out).reshape(4, 3) * math.exp(ls),
+                               (U[:, :k] * s[:k]) @ Vt[:k], atol=1e-12)
+
+
+def test_compress_zero_state():
+    A = [np.zeros((1, 2, 2)), np.zeros((2, 2, 1))]
+    _, ls = bmps.compress(A, 2)
+    assert ls == -math.inf
+
+
+# ---------------------------------------------------------------------------
+# Local energy of the doubled generator (Eq. 3, Eq. 9)
+
+
+def _calH_row_from_dense(H, d, N, s, sp):
+    """Row (s, s') of calH = H (x) I + I (x) H^T, from the dense H."""
+    row = {}
+    for t in np.nonzero(H[s])[0]:
+        row[(int(t), sp)] = row.get((int(t), sp), 0.0) + H[s, t]
+    for tp in np.nonzero(H[:, sp])[0]:
+        row[(s, int(tp))] = row.get((s, int(tp)), 0.0) + H[tp, sp]
+    return row
+
+
+def _terms_row(lat, S):
+    diag, off = hamiltonian.terms(lat, S)
+    d, N = lat.d, lat.N
+
+    def idx(X):
+        s = sp = 0
+        for x in X:
+            s = s * d + lat.ket(x)
+            sp = sp * d + lat.bra(x)
+        return s, sp
+    row = {idx(S): diag}
+    for S2, coeff, _ in off:
+        k = idx(S2)
+        row[k] = row.get(k, 0.0) + coeff
+    return row
+
+
+def _check_terms_against_dense(lat, samples):
+    H = hamiltonian.dense_H(lat)
+    np.testing.assert_allclose(H, H.T)
+    for S in samples:
+        got = _terms_row(lat, S)
+        s = sp = 0
+        for x in S:
+            s = s * lat.d + lat.ket(x)
+            sp = sp * lat.d + lat.bra(x)
+        want = _calH_row_from_dense(H, lat.d, lat.N, s, sp)
+        keys = set(k for k, v in got.items() if v != 0.0) | set(k for k, v in want.items() if v != 0.0)
+        for k in keys:
+            assert got.get(k, 0.0) == pytest.approx(want.get(k, 0.0), abs=1e-14), (S, k)
+
+
+def test_terms_spin_j1j2_match_kronecker_H():
+    lat = Lattice(2, 3, D=1, chi=1, J1=1.0, J2=0.5)
+    _check_terms_against_dense(lat, network.all_configs(lat)[::7])
+
+
+def test_terms_hubbard_match_jordan_wigner_H():
+    """Jordan-Wigner signs of the hop terms vs fermion operators built as
+    Kronecker products with explicit sigma^z strings."""
+    lat = Lattice(2, 2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    rng = np.random.default_rng(3)
+    samples = rng.integers(0, 16, size=(600, 4))
+    _check_terms_against_dense(lat, samples)
+
+
+def test_ring_spectrum_closed_form():
+    """2x2 OBC Heisenberg = 4-site ring: E = (J/2)[S(S+1) - Sa(Sa+1) - Sb(Sb+1)]
+    with Sa, Sb the spins of the two diagonal pairs."""
+    lat = Lattice(2, 2, D=1, chi=1, J1=1.0)
+    ev = np.sort(ed.spin_spectrum(lat))
+    want = sorted([0.0] * 7 + [-2.0] + [-1.0] * 3 + [1.0] * 5)
+    np.testing.assert_allclose(ev, want, atol=1e-12)
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(hamiltonian.dense_H(lat))), want, atol=1e-12)
+
+
+def test_ed_sectors_match_dense_and_high_T_series():
+    """ED sectors vs dense Kronecker H; E(beta)/N = -(3/16) beta (N1 J1^2 +
+    N2 J2^2)/N + O(beta^2) (Tr H = 0, Tr (S_i.S_j)^2 / dim = 3/16)."""
+    lat = Lattice(3, 3, D=1, chi=1, J1=1.0, J2=0.5)
+    ev = np.sort(ed.spin_spectrum(lat))
+    np.testing.assert_allclose(ev, np.sort(np.linalg.eigvalsh(hamiltonian.dense_H(lat))), atol=1e-10)
+    assert abs(ev.sum()) < 1e-9
+    n1 = len(lat.bonds_h()) + len(lat.bonds_v())
+    n2 = len(lat.bonds_d())
+    b = 1e-4
+    slope = -(3.0 / 16.0) * (n1 * lat.J1 ** 2 + n2 * lat.J2 ** 2)
+    assert ed.thermal_energy(ev, b)[0] == pytest.approx(slope * b, rel=1e-3)
+
+
+def test_identity_state_closed_forms():
+    """P1: |I> has rho(S) = prod delta(s_i, s'_i); on diagonal S only the
+    diagonal of calH survives, E_loc(s,s) = 2 H_ss, and the |I|^2-weighted
+    mean of E_loc is 2 Tr H / dim (0 for Heisenberg)."""
+    lat = Lattice(2, 2, D=2, chi=4, J1=1.0, J2=0.5)
+    th = synth.theta_identity(2, 2, 2, 2)
+    H = hamiltonian.dense_H(lat)
+    tot = 0.0
+    for S in network.all_configs(lat):
+        diag = all(lat.ket(x) == lat.bra(x) for x in S)
+        a = network.amplitude(lat, th, S)
+        assert a == (1.0 if diag else 0.0)
+        if diag:
+            ev = measure.evaluate(lat, th, S, 4, want_O=False)
+            s = 0
+            for x in S:
+                s = s * 2 + lat.ket(x)
+            assert ev["e_loc"] == pytest.approx(2 * H[s, s], abs=1e-14)
+            tot += ev["e_loc"]
+    assert tot / 16 == pytest.approx(2 * np.trace(H) / 16, abs=1e-13)
+    assert tot == pytest.approx(0.0, abs=1e-12)
+
+
+def test_identity_state_hubbard_energy_per_site():
+    """P1 for Hubbard: E/N at beta = 0 is Tr H / (dim N) = U/4 - mu (= -2 for
+    U = 8, mu = 4), averaging 2 H_ss over the diagonal configurations."""
+    lat = Lattice(2, 2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    H = hamiltonian.dense_H(lat)
+    tot = 0.0
+    for s in itertools.product(range(4), repeat=4):
+        S = [x * 4 + x for x in s]
+        diag, off = hamiltonian.terms(lat, S)
+        # off-diagonal targets of a diagonal S are off-diagonal -> rho = 0
+        for S2, _, _ in off:
+            assert any(lat.ket(x) != lat.bra(x) for x in S2)
+        tot += diag
+    assert tot / 256 / (2 * lat.N) == pytest.approx(lat.U / 4 - lat.mu, abs=1e-13)
+    assert np.trace(H) / 256 / lat.N == pytest.approx(lat.U / 4 - lat.mu, abs=1e-13)
+
+
+def _enumerate(lat, th, chi):
+    rho = network.density_matrix(lat, th)
+    rows = []
+    for S in network.all_configs(lat):
+        a = network.amplitude(lat, th, S)
+        ev = measure.evaluate(lat, th, S, chi)
+        rows.append((S, a, ev))
+    return rho, rows
+
+
+@pytest.mark.parametrize("J2", [0.0, 0.5])
+def test_internal_energy_identity_by_enumeration(J2):
+    """P4, Eq. (in_en): sum |rho|^2 E_loc / sum |rho|^2 =
+    Tr(rho rho^T H + rho^T rho H) / Tr(rho rho^T) for an arbitrary PEPS."""
+    lat = Lattice(2, 2, D=2, chi=4, J1=1.0, J2=J2)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=21)
+    rho, rows = _enumerate(lat, th, 4)
+    H = hamiltonian.dense_H(lat)
+    w = np.array([a * a for _, a, _ in rows])
+    e = np.array([ev["e_loc"] for _, _, ev in rows])
+    lhs = float(w @ e / w.sum())
+    rhs = float(np.trace(rho @ rho.T @ H + rho.T @ rho @ H) / np.trace(rho @ rho.T))
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_log_derivative_finite_difference_and_euler():
+    """P3: rho_r is linear in every entry of row r (top[r-1], bot[r+1] do not
+    depend on it), so a central difference is exact up to round-off; and
+    sum_k theta_k O_k = 1 for every site of every sample.  Truncating chi."""
+    lat = Lattice(3, 3, D=3, chi=4)
+    th = synth.theta_random_unit(3, 3, 3, 2, seed=31)
+    S = synth.configs_sector(1, 9, 2, seed=32)[0]
+    ev = measure.evaluate(lat, th, S, 4)
+    full = measure.expand_O(lat, S, ev["O"])
+    poff, _ = lat.param_offsets()
+    ooff, _ = lat.orow_offsets()
+    for r in range(3):
+        for c in range(3):
+            i = lat.site(r, c)
+            bs = lat.block_size(r, c)
+            blk = lat.site_tensor(th, r, c)[S[i]].reshape(-1)
+            assert float(blk @ ev["O"][ooff[i]:ooff[i] + bs]) == pytest.approx(1.0, abs=1e-11)
+
+    def rho_r(theta, r):
+        tops = bmps.top_boundaries(lat, theta, S, 4)
+        bots = bmps.bot_boundaries(lat, theta, S, 4)
+        v = bmps.strip1(tops[r][0], lat.row_slices(theta, S, r), bots[r + 1][0])
+        return v * math.exp(tops[r][1] + bots[r + 1][1])
+
+    rng = np.random.default_rng(33)
+    h = 1e-6
+    for r in range(3):
+        base = rho_r(th, r)
+        for _ in range(4):
+            c = int(rng.integers(0, 3))
+            i = lat.site(r, c)
+            bs = lat.block_size(r, c)
+            k = poff[i] + int(S[i]) * bs + int(rng.integers(0, bs))
+            tp, tm = th.copy(), th.copy()
+            tp[k] += h
+            tm[k] -= h
+            fd = (rho_r(tp, r) - rho_r(tm, r)) / (2 * h) / base
+            assert fd == pytest.approx(full[k], rel=1e-6, abs=1e-8)
+
+
+def test_gradient_is_half_energy_gradient():
+    """P5: with exact averages over |rho|^2, g = (1/2) d E_var / d theta where
+    E_var = <rho|calH|rho>/<rho|rho>  (Eqs. 7, 9 and in_en)."""
+    lat = Lattice(2, 2, D=2, chi=4, J1=1.0, J2=0.3)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=41)
+    H = hamiltonian.dense_H(lat)
+
+    def evar(theta):
+        rho = network.density_matrix(lat, theta)
+        return float(np.trace(rho @ rho.T @ H + rho.T @ rho @ H) / np.trace(rho @ rho.T))
+
+    _, rows = _enumerate(lat, th, 4)
+    cfg = np.array([S for S, _, _ in rows])
+    w = np.array([a * a for _, a, _ in rows])
+    O = np.array([ev["O"] for _, _, ev in rows])
+    e = np.array([ev["e_loc"] for _, _, ev in rows])
+    Ofull = sr.dense_O(lat, cfg, O)
+    _, _, g = sr.sr_reductions(Ofull, e, weights=w)
+    rng = np.random.default_rng(42)
+    h = 1e-5
+    for k in rng.choice(lat.n_params, 6, replace=False):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (evar(tp) - evar(tm)) / (2 * h)
+        assert g[k] == pytest.approx(0.5 * fd, rel=1e-5, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Metropolis (P12, P13, P11)
+
+
+def test_identity_sweep_flips_every_site():
+    """P12: for |I> every exchange has R = 0 (rejected) and every diagonal
+    flip has |R| = 1 (accepted), so one sweep flips every site."""
+    lat = Lattice(3, 4, D=2, chi=4)
+    th = synth.theta_identity(3, 4, 2, 2)
+    S0 = synth.configs_diagonal(1, 12, 2, seed=51)[0].astype(np.int64)
+    res = sampler.sweep(lat, th, S0, 4, seed=1, chain=0, gsweep=0)
+    assert res["n_accept"][0] == 0 and res["n_accept"][2] == 0
+    assert res["n_accept"][1] == 12
+    want = [lat.merge(1 - lat.ket(x), 1 - lat.ket(x)) for x in S0]
+    assert list(res["S"]) == want
+
+
+def test_ratio_reciprocity_and_exactness():
+    """P13: R(S->S') R(S'->S) = 1 and, at exact chi, the strip ratio equals
+    the ratio of exact amplitudes."""
+    lat = Lattice(3, 3, D=2, chi=4)
+    th = synth.theta_random_unit(3, 3, 2, 2, seed=61)
+    S = synth.configs_sector(1, 9, 2, seed=62)[0].astype(np.int64)
+    for (a, b) in [((0, 0), (0, 1)), ((1, 1), (2, 1)), ((2, 0), (2, 1))]:
+        i, j = lat.site(*a), lat.site(*b)
+        S2 = S.copy()
+        S2[i], S2[j] = S[j], S[i]
+        r = min(a[0], b[0])
+        tops = bmps.top_boundaries(lat, th, S, 4)
+        bots = bmps.bot_boundaries(lat, th, S, 4)
+        if a[0] == b[0]:
+            f = lambda X: bmps.strip1(tops[r][0], lat.row_slices(th, X, r), bots[r + 1][0])
+        else:
+            f = lambda X: bmps.strip2(tops[r][0], lat.row_slices(th, X, r),
+                                      lat.row_slices(th, X, r + 1), bots[r + 2][0])
+        R1 = f(S2) / f(S)
+        R2 = f(S) / f(S2)
+        assert R1 * R2 == pytest.approx(1.0, rel=1e-13)
+        assert R1 == pytest.approx(network.amplitude(lat, th, S2) / network.amplitude(lat, th, S), rel=1e-11)
+
+
+@pytest.mark.slow
+def test_sampled_histogram_matches_rho_squared():
+    """P11: chi^2 test of the visited configurations against |rho|^2
+    restricted to the reachable set M(s) = M(s') (2x2, exact chi)."""
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=71)
+    reach = [S for S in network.all_configs(lat)
+             if sum(lat.ket(x) for x in S) == sum(lat.bra(x) for x in S)]
+    p = np.array([network.amplitude(lat, th, S) ** 2 for S in reach])
+    p /= p.sum()
+    index = {tuple(S): k for k, S in enumerate(reach)}
+    counts = np.zeros(len(reach))
+    n_chains, n_sweeps = 4, 1500
+    for ch in range(n_chains):
+        S = synth.configs_diagonal(1, 4, 2, seed=72 + ch)[0].astype(np.int64)
+        for k in range(n_sweeps):
+            S = sampler.sweep(lat, th, S, 4, seed=9, chain=ch, gsweep=k)["S"]
+            if k >= 20:
+                counts[index[tuple(S)]] += 1
+    n = counts.sum()
+    exp_ = p * n
+    mask = exp_ > 5
+    chi2 = float((((counts - exp_) ** 2)[mask] / exp_[mask]).sum())
+    dof = int(mask.sum()) - 1
+    # Successive sweeps are correlated; allow a generous factor over dof.
+    assert chi2 < 3.0 * dof + 30, (chi2, dof)
+
+
+# ---------------------------------------------------------------------------
+# SR (P9)
+
+
+def test_cg_matches_dense_solve_and_S_is_psd():
+    lat = Lattice(4, 4, D=2, chi=4)
+    n_p = lat.n_params
+    assert n_p == 576
+    rng = np.random.default_rng(81)
+    n_s = 96
+    configs = synth.configs_uniform(n_s, 16, 2, seed=82)
+    O = rng.standard_normal((n_s, lat.nnz))
+    e = rng.standard_normal(n_s)
+    Ofull = sr.dense_O(lat, configs, O)
+    Sm = sr.sr_matrix(Ofull)
+    np.testing.assert_allclose(Sm, Sm.T, atol=1e-14)
+    assert np.linalg.eigvalsh(Sm).min() > -1e-10
+    x = rng.standard_normal(n_p)
+    np.testing.assert_allclose(sr.sr_matvec(Ofull, x, 1e-4), Sm @ x + 1e-4 * x, rtol=1e-11, atol=1e-11)
+    sol = sr.sr_solve(lat, configs, O, e, tau=0.01, eps=1e-2, max_iter=2000, rtol=1e-12)
+    dense = sr.sr_solve_dense(lat, configs, O, e, tau=0.01, eps=1e-2)
+    np.testing.assert_allclose(sol["dtheta"], dense, rtol=1e-8, atol=1e-12)
+    assert not sol["breakdown"]
+    # gradient from its definition (Eq. 7) with explicit loops
+    eb = e.mean()
+    g = np.zeros(n_p)
+    for i in range(n_s):
+        g += Ofull[i] * (e[i] - eb) / n_s
+    np.testing.assert_allclose(sol["g"], g, rtol=1e-12, atol=1e-14)
