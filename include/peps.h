@@ -1,0 +1,161 @@
+/*
+ * peps.h -- C ABI of the MI355X thermal PEPS-VMC hot path.
+ *
+ * The method (arXiv 2409.05285, Method section): the thermal density matrix
+ * is vectorised (Eq. 2) into a PEPS with one merged physical index
+ * S_i = (s_i, s'_i) of dimension d^2 per site (Eq. 4), sampled by Markov-chain
+ * Monte Carlo with weight |rho_theta(S)|^2, evaluated per sample through
+ * boundary-MPS contraction of the single-layer network (boundary dimension
+ * chi, the paper's D_c), and cooled from beta = 0 by stochastic
+ * reconfiguration: (S + eps 1) dtheta = -tau g, solved by conjugate gradient
+ * with the separable metric (Eqs. 5-10).
+ *
+ * Conventions shared by every call
+ *   site (r, c), r = 0..L1-1 (top to bottom), c = 0..L2-1, i = r*L2 + c;
+ *   theta: sites in order i, each a block T_i[S][l][u][r][d] (row-major,
+ *     d^2 slices; a virtual leg that leaves the open lattice has dimension 1,
+ *     the others D); N_p = peps_param_count();
+ *   configuration: uint8 S_i = s*d + s' per site, [n][L1*L2];
+ *   O row of one sample: sites in order i, each a [l][u][r][d] block holding
+ *     d log rho / d T_i[S_i] (the other d^2-1 slices of the site are zero and
+ *     not stored); nnz = peps_orow_count();
+ *   spin digit s: 0 = up, 1 = down.  Hubbard digit s = n_up + 2 n_dn.
+ *
+ * Memory and streams.  Every pointer argument of the device calls is a
+ * device pointer unless stated otherwise; the caller owns all memory,
+ * including the workspace sized by peps_workspace_bytes().  Device calls
+ * enqueue on `stream` and return without synchronising; they allocate and
+ * free nothing.  Calls that share one workspace must not overlap.
+ *
+ * Errors.  Shape and argument errors are returned before anything is
+ * enqueued.  A failed launch returns PEPS_ERR_HIP.  Data-dependent failures
+ * (non-finite parameters, a zero amplitude, CG breakdown) are recorded in
+ * the device word `status` (0 = fine, otherwise a peps_status value, first
+ * failure wins), which the caller reads after its own synchronisation.
+ */
+#ifndef PEPS_H
+#define PEPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* peps_stream_t; /* a hipStream_t */
+
+typedef enum {
+  PEPS_OK = 0,
+  PEPS_ERR_ARG = -1,         /* bad shape, null pointer, out-of-range value   */
+  PEPS_ERR_UNSUPPORTED = -2, /* valid but beyond the compiled tile limits     */
+  PEPS_ERR_HIP = -3,         /* a HIP runtime call or launch failed           */
+  PEPS_ERR_WORKSPACE = -4,   /* ws_bytes smaller than peps_workspace_bytes()  */
+  PEPS_ERR_NONFINITE = -5,   /* NaN / Inf met in the data (device status)     */
+  PEPS_ERR_ZERO_AMPLITUDE = -6, /* a strip amplitude of a sample is exactly 0 */
+  PEPS_ERR_CG_BREAKDOWN = -7,   /* p^T A p <= 0 in conjugate gradient         */
+  PEPS_WARN_CG_NOT_CONVERGED = 1
+} peps_status;
+
+enum { PEPS_MODEL_HEISENBERG = 0, PEPS_MODEL_HUBBARD = 1 };
+enum { PEPS_PREC_FP64 = 0, PEPS_PREC_MIXED = 1 };
+enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3 };
+enum { PEPS_N_MOVE_TYPES = 3 }; /* horizontal exchange, site move, vertical exchange */
+
+typedef struct {
+  int32_t L1, L2;    /* rows, columns (open boundaries), each >= 2                */
+  int32_t d;         /* single-copy local dimension: 2 spin-1/2, 4 Hubbard        */
+  int32_t D, chi;    /* PEPS bond dimension; boundary-MPS dimension (D_c)          */
+  int32_t model;     /* PEPS_MODEL_*                                               */
+  double J1, J2;     /* Heisenberg couplings (Benchmark section, Eq. j1j2eq)       */
+  double t, U, mu;   /* Hubbard parameters (Benchmark section, Eq. hubbard_model)  */
+  int32_t precision; /* PEPS_PREC_*: FP64 throughout, or FP32 contractions with
+                        FP64 truncation / reductions / log-scales                  */
+  int32_t alpha;     /* sampling weight |rho|^alpha: 2, or 1 (Appendix A, Eq. A1)  */
+} peps_desc;
+
+/* ---- host, pure ------------------------------------------------------- */
+
+/* N_p: total number of parameters (Method section: theta_1..theta_{N_p}).
+   Returns -1 for an invalid descriptor. */
+int64_t peps_param_count(const peps_desc* desc);
+
+/* Entries stored per O row (one [l][u][r][d] block per site). -1 if invalid. */
+int64_t peps_orow_count(const peps_desc* desc);
+
+/* Proposal slots per sweep (each owns one uniform). -1 if invalid. */
+int64_t peps_slot_count(const peps_desc* desc);
+
+/* Workspace bytes for `what` = PEPS_WS_EVAL / _GRAD / _SWEEP (n = number of
+   chains or samples) or PEPS_WS_SR (n = number of samples N_s). */
+peps_status peps_workspace_bytes(const peps_desc* desc, int64_t n, int32_t what, size_t* bytes);
+
+/* Static text for a status code. */
+const char* peps_status_string(peps_status s);
+
+/* ---- device ------------------------------------------------------------- */
+
+/* Fixed-configuration evaluation (Method section, Eqs. 8-9 and in_en).
+   For each of the n configurations: log|psi| = log|rho_{L1-1}(S)| (the
+   top-down boundary-MPS amplitude), its sign (+1/-1) and the local energy
+   E_loc(S) = sum_S' calH_{SS'} rho(S')/rho(S) with calH = H(x)I + I(x)H^T
+   (Eq. 3), ratios taken from one-row strips (terms inside a row) or
+   two-row strips (terms across rows).
+   configs [n][N] uint8; log_abs [n] f64; sign [n] int8; e_loc [n] f64
+   (e_loc may be NULL); status: one device int32. */
+peps_status peps_eval_batch(const peps_desc* desc, const double* theta, int32_t n,
+                            const uint8_t* configs, double* log_abs, int8_t* sign,
+                            double* e_loc, int32_t* status, void* ws, size_t ws_bytes,
+                            peps_stream_t stream);
+
+/* Log-derivatives O_k(S) = d rho / d theta_k / rho (Method section, Eq. 8)
+   of n fixed configurations, one compressed row each: O_rows [n][nnz] f64.
+   The block of site (r, c) is the derivative of the one-row strip rho_r with
+   the boundaries top[r-1], bot[r+1] held fixed (they do not depend on row r).
+   log_abs may be NULL. */
+peps_status peps_grad_batch(const peps_desc* desc, const double* theta, int32_t n,
+                            const uint8_t* configs, double* O_rows, double* log_abs,
+                            int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
+
+/* n_sweeps Metropolis sweeps of n_chains independent chains (Method section:
+   MCMC over S; acceptance min(1, |R|^alpha)), each sweep followed by a
+   measurement of the final configuration.
+   Sweep order per row r: horizontal exchanges (ket then bra digit) on bonds
+   c = 0..L2-2 with one-row strip ratios; site moves c = 0..L2-1; if r < L1-1
+   vertical exchanges c = 0..L2-1 with two-row strip ratios; then the top
+   boundary of row r is recomputed.  The uniform of proposal slot q in global
+   sweep g of chain ch is Philox4x64-10 with counter (ch, g, q, 0) and key
+   (seed, 0): u = (w0 >> 11) * 2^-53; sweep k of this call has g = sweep0 + k.
+   configs [n_chains][N] in/out.  Per sweep k and chain ch (index k*n_chains+ch):
+   log_abs, sign, e_loc [n_sweeps*n_chains], O_rows [n_sweeps*n_chains][nnz];
+   any of these may be NULL (then not written).  n_accept [n_chains][3] int32
+   is incremented by the accepted moves of each type (may be NULL). */
+peps_status peps_sample_sweep(const peps_desc* desc, const double* theta, int32_t n_chains,
+                              uint8_t* configs, uint64_t seed, uint64_t sweep0, int32_t n_sweeps,
+                              double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
+                              int32_t* n_accept, int32_t* status, void* ws, size_t ws_bytes,
+                              peps_stream_t stream);
+
+/* Stochastic-reconfiguration update (Method section, Eqs. 5-7 and 10):
+   Ebar = <E>, obar = <O>, g = <O (E - Ebar)>, S x = <O (O.x - obar.x)>,
+   and (S + eps 1) dtheta = -tau g solved by conjugate gradient from
+   dtheta = 0, never forming S: each iteration applies O (gather) then O^T
+   (scatter).  Averages are uniform over the n_s samples, or weighted by
+   `weights` [n_s] (Appendix A, Eq. A1) when it is not NULL.  The residual
+   test ||r|| <= rtol ||b|| (b = -tau g) is taken before each iteration;
+   at most max_iter iterations.
+   configs [n_s][N] uint8; O_rows [n_s][nnz]; e_loc [n_s];
+   dtheta [N_p] out; g_out [N_p] out or NULL;
+   stats [4] device f64 out: Ebar, final ||r||, iterations, ||b||.
+   CG breakdown is reported in `status`. */
+peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* configs,
+                        const double* O_rows, const double* weights, const double* e_loc,
+                        double tau, double eps, int32_t max_iter, double rtol,
+                        double* dtheta, double* g_out, double* stats, int32_t* status,
+                        void* ws, size_t ws_bytes, peps_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEPS_H */

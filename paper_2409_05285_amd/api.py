@@ -1,0 +1,225 @@
+"""Python face of the C ABI, with the same names as include/peps.h.
+
+Tensors live on the current HIP device (torch is used for device memory
+and streams only).  Each call validates shapes, allocates outputs and a
+cached workspace, and enqueues the library call on torch's current stream.
+Device status words are returned as tensors; `check(status)` synchronises
+and raises on a recorded failure.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import LIB, PepsDesc, PepsError
+
+
+@dataclass(frozen=True)
+class Desc:
+    """Problem descriptor (peps_desc)."""
+    L1: int
+    L2: int
+    D: int
+    chi: int
+    d: int = 2
+    model: int = _lib.MODEL_HEISENBERG
+    J1: float = 1.0
+    J2: float = 0.0
+    t: float = 1.0
+    U: float = 0.0
+    mu: float = 0.0
+    precision: int = _lib.PREC_FP64
+    alpha: int = 2
+
+    def c(self):
+        return PepsDesc(self.L1, self.L2, self.d, self.D, self.chi, self.model, self.J1, self.J2, self.t,
+                        self.U, self.mu, self.precision, self.alpha)
+
+    @property
+    def N(self):
+        return self.L1 * self.L2
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _raise(code, where):
+    if code != _lib.PEPS_OK:
+        raise PepsError(code, where)
+
+
+def peps_param_count(desc: Desc) -> int:
+    n = LIB.peps_param_count(ctypes.byref(desc.c()))
+    _raise(0 if n >= 0 else -1, "peps_param_count")
+    return int(n)
+
+
+def peps_orow_count(desc: Desc) -> int:
+    n = LIB.peps_orow_count(ctypes.byref(desc.c()))
+    _raise(0 if n >= 0 else -1, "peps_orow_count")
+    return int(n)
+
+
+def peps_slot_count(desc: Desc) -> int:
+    n = LIB.peps_slot_count(ctypes.byref(desc.c()))
+    _raise(0 if n >= 0 else -1, "peps_slot_count")
+    return int(n)
+
+
+def peps_workspace_bytes(desc: Desc, n: int, what: int) -> int:
+    out = ctypes.c_size_t(0)
+    _raise(LIB.peps_workspace_bytes(ctypes.byref(desc.c()), int(n), int(what), ctypes.byref(out)),
+           "peps_workspace_bytes")
+    return int(out.value)
+
+
+class Workspace:
+    """Device workspace reused across calls (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_WS = {}
+
+
+def _ws(kind, nbytes, device):
+    w = _WS.setdefault(kind, Workspace())
+    return w.get(nbytes, device)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must be on the HIP device")
+
+
+def _theta(desc, theta):
+    if theta.dtype != torch.float64 or theta.dim() != 1 or theta.numel() != peps_param_count(desc):
+        raise ValueError("theta must be a float64 vector of length N_p")
+    return theta.contiguous()
+
+
+def _configs(desc, configs):
+    if configs.dtype != torch.uint8 or configs.dim() != 2 or configs.shape[1] != desc.N:
+        raise ValueError("configs must be uint8 [n, L1*L2]")
+    if not configs.is_contiguous():
+        raise ValueError("configs must be contiguous")
+    return configs
+
+
+def new_status(device):
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check(status, where="device"):
+    code = int(status.item())
+    if code != 0 and code != 1:
+        raise PepsError(code, where)
+    return code
+
+
+def peps_eval_batch(desc: Desc, theta, configs, want_e=True, status=None):
+    """(log_abs [n] f64, sign [n] i8, e_loc [n] f64 or None, status)."""
+    theta = _theta(desc, theta)
+    configs = _configs(desc, configs)
+    _check_dev(theta, configs)
+    n = configs.shape[0]
+    dev = theta.device
+    log_abs = torch.empty(n, dtype=torch.float64, device=dev)
+    sign = torch.empty(n, dtype=torch.int8, device=dev)
+    e_loc = torch.empty(n, dtype=torch.float64, device=dev) if want_e else None
+    status = new_status(dev) if status is None else status
+    nb = peps_workspace_bytes(desc, n, _lib.WS_EVAL)
+    ws = _ws("chain", nb, dev)
+    code = LIB.peps_eval_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(log_abs), _ptr(sign),
+                               _ptr(e_loc), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _raise(code, "peps_eval_batch")
+    return log_abs, sign, e_loc, status
+
+
+def peps_grad_batch(desc: Desc, theta, configs, status=None):
+    """(O_rows [n, nnz] f64, log_abs [n] f64, status)."""
+    theta = _theta(desc, theta)
+    configs = _configs(desc, configs)
+    _check_dev(theta, configs)
+    n = configs.shape[0]
+    dev = theta.device
+    O = torch.empty((n, peps_orow_count(desc)), dtype=torch.float64, device=dev)
+    log_abs = torch.empty(n, dtype=torch.float64, device=dev)
+    status = new_status(dev) if status is None else status
+    ws = _ws("chain", peps_workspace_bytes(desc, n, _lib.WS_GRAD), dev)
+    code = LIB.peps_grad_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(O), _ptr(log_abs),
+                               _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _raise(code, "peps_grad_batch")
+    return O, log_abs, status
+
+
+def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measure=True, want_O=True,
+                      n_accept=None, status=None, out=None):
+    """Runs n_sweeps sweeps in place on `configs`.  Returns a dict with
+    log_abs / sign / e_loc [n_sweeps, n] and O [n_sweeps, n, nnz] (when
+    measured), n_accept [n, 3] and status.  `out` may supply preallocated
+    output tensors with those keys."""
+    theta = _theta(desc, theta)
+    configs = _configs(desc, configs)
+    _check_dev(theta, configs)
+    n = configs.shape[0]
+    dev = theta.device
+    res = {} if out is None else dict(out)
+    if measure:
+        res.setdefault("log_abs", torch.empty((n_sweeps, n), dtype=torch.float64, device=dev))
+        res.setdefault("sign", torch.empty((n_sweeps, n), dtype=torch.int8, device=dev))
+        res.setdefault("e_loc", torch.empty((n_sweeps, n), dtype=torch.float64, device=dev))
+        if want_O:
+            res.setdefault("O", torch.empty((n_sweeps, n, peps_orow_count(desc)), dtype=torch.float64, device=dev))
+    if n_accept is None:
+        n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+    status = new_status(dev) if status is None else status
+    ws = _ws("chain", peps_workspace_bytes(desc, n, _lib.WS_SWEEP), dev)
+    code = LIB.peps_sample_sweep(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(seed), int(sweep0),
+                                 int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
+                                 _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(n_accept), _ptr(status),
+                                 _ptr(ws), ws.numel(), _stream())
+    _raise(code, "peps_sample_sweep")
+    res["n_accept"] = n_accept
+    res["status"] = status
+    return res
+
+
+def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, weights=None, want_g=True,
+                status=None):
+    """(dtheta [N_p], g [N_p] or None, stats [4] = (Ebar, |r|, iters, |b|), status)."""
+    configs = _configs(desc, configs)
+    n_s = configs.shape[0]
+    if O_rows.dtype != torch.float64 or O_rows.shape != (n_s, peps_orow_count(desc)) or not O_rows.is_contiguous():
+        raise ValueError("O_rows must be contiguous float64 [n_s, nnz]")
+    if e_loc.dtype != torch.float64 or e_loc.shape != (n_s,):
+        raise ValueError("e_loc must be float64 [n_s]")
+    _check_dev(configs, O_rows, e_loc, weights)
+    dev = O_rows.device
+    n_p = peps_param_count(desc)
+    dtheta = torch.empty(n_p, dtype=torch.float64, device=dev)
+    g = torch.empty(n_p, dtype=torch.float64, device=dev) if want_g else None
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    status = new_status(dev) if status is None else status
+    ws = _ws("sr", peps_workspace_bytes(desc, n_s, _lib.WS_SR), dev)
+    code = LIB.sr_cg_solve(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights),
+                           _ptr(e_loc.contiguous()), float(tau), float(eps), int(max_iter), float(rtol),
+                           _ptr(dtheta), _ptr(g), _ptr(stats), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _raise(code, "sr_cg_solve")
+    return dtheta, g, stats, status

@@ -1,0 +1,267 @@
+// C ABI of the library: descriptor validation, workspace layout, and the
+// launch sequences of the four device calls (declared in include/peps.h).
+#include <math.h>
+#include <string.h>
+
+#include "peps_common.hpp"
+#include "peps_kernels.hpp"
+
+using namespace peps;
+
+namespace {
+
+constexpr size_t LDS_LIMIT = 160 * 1024;   // gfx950 LDS per workgroup
+constexpr size_t STATIC_LDS_COMPRESS = 16 * 1024;
+
+bool desc_ok(const peps_desc* d) {
+  if (!d) return false;
+  if (d->L1 < 2 || d->L2 < 2 || d->L1 > MAX_L || d->L2 > MAX_L || d->L1 * d->L2 > MAX_SITES) return false;
+  if (d->D < 1 || d->chi < 1) return false;
+  if (d->model == PEPS_MODEL_HEISENBERG) {
+    if (d->d != 2) return false;
+  } else if (d->model == PEPS_MODEL_HUBBARD) {
+    if (d->d != 4) return false;
+  } else {
+    return false;
+  }
+  if (d->alpha != 1 && d->alpha != 2) return false;
+  if (d->precision != PEPS_PREC_FP64 && d->precision != PEPS_PREC_MIXED) return false;
+  if (!isfinite(d->J1) || !isfinite(d->J2) || !isfinite(d->t) || !isfinite(d->U) || !isfinite(d->mu)) return false;
+  return true;
+}
+
+Prob make_prob(const peps_desc* d) {
+  Prob P;
+  memset(&P, 0, sizeof(P));
+  P.L1 = d->L1;
+  P.L2 = d->L2;
+  P.N = d->L1 * d->L2;
+  P.d = d->d;
+  P.d2 = d->d * d->d;
+  P.D = d->D;
+  P.chi = d->chi;
+  P.model = d->model;
+  P.alpha = d->alpha;
+  P.nb_moves = d->model == PEPS_MODEL_HEISENBERG ? 2 : 4;
+  P.ns_moves = d->model == PEPS_MODEL_HEISENBERG ? 1 : 2;
+  P.n_slots = P.L1 * (P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2) + (P.L1 - 1) * P.nb_moves * P.L2;
+  P.J1 = d->J1;
+  P.J2 = d->J2;
+  P.t = d->t;
+  P.U = d->U;
+  P.mu = d->mu;
+  int64_t np = 0, nnz = 0;
+  for (int r = 0; r < P.L1; ++r)
+    for (int c = 0; c < P.L2; ++c) {
+      int bs = block_size(P, r, c);
+      nnz += bs;
+      np += (int64_t)P.d2 * bs;
+    }
+  P.nnz = nnz;
+  P.np = np;
+  const int64_t cd = (int64_t)P.chi * P.D;
+  P.TS = (int)(P.chi * P.D * P.chi);
+  P.BS = (int)(cd * P.D * cd);
+  P.ES = (int)(P.chi * P.D * P.D * P.chi);
+  P.XS = (int)(P.chi * P.chi * P.D * P.D * P.D);
+  auto pad = [](int64_t x) { return (x + 31) & ~(int64_t)31; };
+  int64_t off = 0;
+  P.off_top = off;   off += pad((int64_t)P.L1 * P.L2 * P.TS);
+  P.off_lstop = off; off += pad(P.L1);
+  P.off_bot = off;   off += pad((int64_t)P.L1 * P.L2 * P.TS);
+  P.off_lsbot = off; off += pad(P.L1);
+  P.off_B = off;     off += pad((int64_t)P.L2 * P.BS);
+  P.off_tmp = off;   off += pad(P.BS);
+  P.off_R = off;     off += pad((int64_t)(P.L2 + 1) * P.ES);
+  P.off_L = off;     off += pad(4 * (int64_t)P.ES);
+  P.off_X = off;     off += pad(2 * (int64_t)P.XS);
+  P.off_epart = off; off += pad(2 * P.L1 + 2);
+  P.chain_stride = off;
+  return P;
+}
+
+// Checks that the compiled tile limits hold for the device path.
+peps_status device_support(const peps_desc* d, const Prob& P) {
+  if (d->model != PEPS_MODEL_HEISENBERG) return PEPS_ERR_UNSUPPORTED;
+  if (d->precision != PEPS_PREC_FP64) return PEPS_ERR_UNSUPPORTED;
+  if ((int64_t)P.chi * P.D > 255) return PEPS_ERR_UNSUPPORTED;
+  if (compress_dyn_lds(P) + STATIC_LDS_COMPRESS > LDS_LIMIT) return PEPS_ERR_UNSUPPORTED;
+  return PEPS_OK;
+}
+
+#define HIP_TRY(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return PEPS_ERR_HIP; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int64_t peps_param_count(const peps_desc* d) {
+  if (!desc_ok(d)) return -1;
+  return make_prob(d).np;
+}
+
+int64_t peps_orow_count(const peps_desc* d) {
+  if (!desc_ok(d)) return -1;
+  return make_prob(d).nnz;
+}
+
+int64_t peps_slot_count(const peps_desc* d) {
+  if (!desc_ok(d)) return -1;
+  return make_prob(d).n_slots;
+}
+
+peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, size_t* bytes) {
+  if (!desc_ok(d) || !bytes || n < 0) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  switch (what) {
+    case PEPS_WS_EVAL:
+    case PEPS_WS_GRAD:
+    case PEPS_WS_SWEEP:
+      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double);
+      return PEPS_OK;
+    case PEPS_WS_SR:
+      *bytes = sr_workspace_bytes(P, n);
+      return PEPS_OK;
+    default:
+      return PEPS_ERR_ARG;
+  }
+}
+
+const char* peps_status_string(peps_status s) {
+  switch (s) {
+    case PEPS_OK: return "ok";
+    case PEPS_ERR_ARG: return "invalid argument or shape";
+    case PEPS_ERR_UNSUPPORTED: return "valid but beyond the compiled tile limits of the device path";
+    case PEPS_ERR_HIP: return "HIP runtime or launch failure";
+    case PEPS_ERR_WORKSPACE: return "workspace smaller than peps_workspace_bytes()";
+    case PEPS_ERR_NONFINITE: return "non-finite value in the data";
+    case PEPS_ERR_ZERO_AMPLITUDE: return "zero strip amplitude for a sample";
+    case PEPS_ERR_CG_BREAKDOWN: return "conjugate gradient breakdown (p^T A p <= 0)";
+    case PEPS_WARN_CG_NOT_CONVERGED: return "conjugate gradient reached max_iter";
+    default: return "unknown status";
+  }
+}
+
+static peps_status common_checks(const peps_desc* d, Prob& P, int64_t n, const void* theta, const void* configs,
+                                 void* ws, size_t ws_bytes, int what) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  if (n < 0 || n > (1 << 24)) return PEPS_ERR_ARG;
+  P = make_prob(d);
+  peps_status s = device_support(d, P);
+  if (s != PEPS_OK) return s;
+  if (n == 0) return PEPS_OK;
+  if (!configs || !ws || (what != PEPS_WS_SR && !theta)) return PEPS_ERR_ARG;
+  size_t need = 0;
+  peps_workspace_bytes(d, n, what, &need);
+  if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
+  return PEPS_OK;
+}
+
+static peps_status compress_all_bots(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
+                                     int32_t* status, hipStream_t st) {
+  for (int r = P.L1 - 1; r >= 1; --r) HIP_TRY(launch_compress(P, n, 1, r, theta, configs, ws, status, st));
+  return PEPS_OK;
+}
+
+static peps_status measure(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
+                           double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int64_t out_off,
+                           int32_t* status, hipStream_t st) {
+  const int want_e = e_loc != nullptr;
+  for (int r = 0; r < P.L1; ++r)
+    HIP_TRY(launch_meas1(P, n, r, theta, configs, ws, O_rows, want_e, status, st));
+  if (want_e)
+    for (int r = 0; r < P.L1 - 1; ++r) HIP_TRY(launch_meas2(P, n, r, theta, configs, ws, status, st));
+  HIP_TRY(launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, status, st));
+  return PEPS_OK;
+}
+
+peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
+                            double* log_abs, int8_t* sign, double* e_loc, int32_t* status, void* ws,
+                            size_t ws_bytes, peps_stream_t stream) {
+  Prob P;
+  peps_status s = common_checks(d, P, n, theta, configs, ws, ws_bytes, PEPS_WS_EVAL);
+  if (s != PEPS_OK || n == 0) return s;
+  if (!log_abs || !sign) return PEPS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  double* w = (double*)ws;
+  for (int r = 0; r <= P.L1 - 2; ++r) HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  s = compress_all_bots(P, n, theta, configs, w, status, st);
+  if (s != PEPS_OK) return s;
+  return measure(P, n, theta, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
+}
+
+peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
+                            double* O_rows, double* log_abs, int32_t* status, void* ws, size_t ws_bytes,
+                            peps_stream_t stream) {
+  Prob P;
+  peps_status s = common_checks(d, P, n, theta, configs, ws, ws_bytes, PEPS_WS_GRAD);
+  if (s != PEPS_OK || n == 0) return s;
+  if (!O_rows) return PEPS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  double* w = (double*)ws;
+  for (int r = 0; r <= P.L1 - 2; ++r) HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  s = compress_all_bots(P, n, theta, configs, w, status, st);
+  if (s != PEPS_OK) return s;
+  return measure(P, n, theta, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
+}
+
+peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n_chains, uint8_t* configs,
+                              uint64_t seed, uint64_t sweep0, int32_t n_sweeps, double* log_abs, int8_t* sign,
+                              double* e_loc, double* O_rows, int32_t* n_accept, int32_t* status, void* ws,
+                              size_t ws_bytes, peps_stream_t stream) {
+  Prob P;
+  peps_status s = common_checks(d, P, n_chains, theta, configs, ws, ws_bytes, PEPS_WS_SWEEP);
+  if (s != PEPS_OK || n_chains == 0) return s;
+  if (n_sweeps < 0) return PEPS_ERR_ARG;
+  const bool measure_any = log_abs || sign || e_loc || O_rows;
+  hipStream_t st = (hipStream_t)stream;
+  double* w = (double*)ws;
+  const int n = n_chains;
+  for (int k = 0; k < n_sweeps; ++k) {
+    const uint64_t g = sweep0 + (uint64_t)k;
+    if (k == 0) {
+      s = compress_all_bots(P, n, theta, configs, w, status, st);
+      if (s != PEPS_OK) return s;
+    }
+    for (int r = 0; r < P.L1; ++r) {
+      HIP_TRY(launch_moves1(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+      if (r < P.L1 - 1) {
+        HIP_TRY(launch_moves2(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+        HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+      }
+    }
+    if (k + 1 < n_sweeps || measure_any) {
+      s = compress_all_bots(P, n, theta, configs, w, status, st);
+      if (s != PEPS_OK) return s;
+    }
+    if (measure_any) {
+      const int64_t off = (int64_t)k * n;
+      s = measure(P, n, theta, configs, w, log_abs, sign, e_loc, O_rows ? O_rows + off * P.nnz : nullptr, off,
+                  status, st);
+      if (s != PEPS_OK) return s;
+    }
+  }
+  return PEPS_OK;
+}
+
+peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs, const double* O_rows,
+                        const double* weights, const double* e_loc, double tau, double eps, int32_t max_iter,
+                        double rtol, double* dtheta, double* g_out, double* stats, int32_t* status, void* ws,
+                        size_t ws_bytes, peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  if (n_s < 1 || max_iter < 0 || max_iter > SR_MAX_ITER || !isfinite(tau) || !isfinite(eps) || eps < 0.0 ||
+      !(rtol >= 0.0))
+    return PEPS_ERR_ARG;
+  if (!configs || !O_rows || !e_loc || !dtheta || !stats || !ws) return PEPS_ERR_ARG;
+  size_t need = sr_workspace_bytes(P, n_s);
+  if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
+  HIP_TRY(launch_sr(P, n_s, configs, O_rows, weights, e_loc, tau, eps, max_iter, rtol, dtheta, g_out, stats, status,
+                    ws, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
+}  // extern "C"

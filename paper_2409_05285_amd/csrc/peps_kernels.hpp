@@ -1,0 +1,32 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "peps_common.hpp"
+
+namespace peps {
+
+constexpr int SR_MAX_ITER = 4096;
+
+size_t compress_dyn_lds(const Prob& P);
+hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
+                           double* ws, int32_t* status, hipStream_t st);
+hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
+                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st);
+hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
+                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st);
+hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
+                        double* O_rows, int want_e, int32_t* status, hipStream_t st);
+hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
+                        int32_t* status, hipStream_t st);
+hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
+                           double* e_loc, int64_t out_off, int want_e, int32_t* status, hipStream_t st);
+
+size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
+hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
+                     const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
+                     double* g_out, double* stats, int32_t* status, void* ws, hipStream_t st);
+
+}  // namespace peps
