@@ -145,14 +145,40 @@ peps_status peps_sample_sweep(const peps_desc* desc, const double* theta, int32_
    test ||r|| <= rtol ||b|| (b = -tau g) is taken before each iteration;
    at most max_iter iterations.
    configs [n_s][N] uint8; O_rows [n_s][nnz]; e_loc [n_s];
-   dtheta [N_p] out; g_out [N_p] out or NULL;
+   dtheta [N_p] out; g_out [N_p] out or NULL; theta [N_p] in/out or NULL:
+   when given, the update theta <- theta + dtheta (Eq. 5) is applied too;
    stats [4] device f64 out: Ebar, final ||r||, iterations, ||b||.
-   CG breakdown is reported in `status`. */
+   CG breakdown is reported in `status` (theta is then left unchanged). */
 peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* configs,
                         const double* O_rows, const double* weights, const double* e_loc,
                         double tau, double eps, int32_t max_iter, double rtol,
-                        double* dtheta, double* g_out, double* stats, int32_t* status,
-                        void* ws, size_t ws_bytes, peps_stream_t stream);
+                        double* dtheta, double* g_out, double* theta, double* stats,
+                        int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
+
+/* ---- instrumentation (not part of the method) --------------------------- */
+
+/* Kernel classes timed by the profiler. */
+enum {
+  PEPS_K_COMPRESS = 0, /* boundary row absorption + QR/SVD truncation       */
+  PEPS_K_MOVES1 = 1,   /* Metropolis passes inside a row (one-row strips)   */
+  PEPS_K_MOVES2 = 2,   /* vertical exchanges (two-row strips)               */
+  PEPS_K_MEAS1 = 3,    /* O rows, in-row E_loc terms, log|psi|              */
+  PEPS_K_MEAS2 = 4,    /* cross-row E_loc terms                             */
+  PEPS_K_FINAL = 5,    /* per-sample outputs                                */
+  PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve call       */
+  PEPS_N_KCLASS = 7
+};
+
+/* Start (on = 1) or stop (on = 0) bracketing every launch of the calls
+   above with HIP events on the call's stream, and clear the accumulators.
+   Host only; the library keeps one global table. */
+void peps_profile_enable(int32_t on);
+
+/* Synchronise the recorded events and add, per kernel class, the summed
+   duration in milliseconds to ms[PEPS_N_KCLASS] and the number of timed
+   launches (sr_cg_solve counts as one) to launches[PEPS_N_KCLASS]; then
+   clear.  Returns PEPS_ERR_HIP if an event query failed. */
+peps_status peps_profile_read(double* ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -42,7 +42,7 @@ class PepsError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_05285_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2409_05285_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P = POINTER(PepsDesc)
     lib.peps_param_count.argtypes = [P]
@@ -66,11 +66,18 @@ def _load():
                                       c_void_p]
     lib.peps_sample_sweep.restype = c_int32
     lib.sr_cg_solve.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32,
-                                c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+                                c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                c_void_p]
     lib.sr_cg_solve.restype = c_int32
+    lib.peps_profile_enable.argtypes = [c_int32]
+    lib.peps_profile_enable.restype = None
+    lib.peps_profile_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
+    lib.peps_profile_read.restype = c_int32
     return lib
 
 
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
-           "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve"]
+           "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
+           "peps_profile_enable", "peps_profile_read"]
+KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

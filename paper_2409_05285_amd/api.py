@@ -202,17 +202,21 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
 
 
 def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, weights=None, want_g=True,
-                status=None):
-    """(dtheta [N_p], g [N_p] or None, stats [4] = (Ebar, |r|, iters, |b|), status)."""
+                theta=None, status=None):
+    """(dtheta [N_p], g [N_p] or None, stats [4] = (Ebar, |r|, iters, |b|), status).
+    When `theta` (float64 [N_p], device) is given it is updated in place:
+    theta += dtheta."""
     configs = _configs(desc, configs)
     n_s = configs.shape[0]
     if O_rows.dtype != torch.float64 or O_rows.shape != (n_s, peps_orow_count(desc)) or not O_rows.is_contiguous():
         raise ValueError("O_rows must be contiguous float64 [n_s, nnz]")
     if e_loc.dtype != torch.float64 or e_loc.shape != (n_s,):
         raise ValueError("e_loc must be float64 [n_s]")
-    _check_dev(configs, O_rows, e_loc, weights)
+    _check_dev(configs, O_rows, e_loc, weights, theta)
     dev = O_rows.device
     n_p = peps_param_count(desc)
+    if theta is not None and (theta.dtype != torch.float64 or theta.shape != (n_p,) or not theta.is_contiguous()):
+        raise ValueError("theta must be a contiguous float64 vector of length N_p")
     dtheta = torch.empty(n_p, dtype=torch.float64, device=dev)
     g = torch.empty(n_p, dtype=torch.float64, device=dev) if want_g else None
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
@@ -220,6 +224,20 @@ def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, we
     ws = _ws("sr", peps_workspace_bytes(desc, n_s, _lib.WS_SR), dev)
     code = LIB.sr_cg_solve(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights),
                            _ptr(e_loc.contiguous()), float(tau), float(eps), int(max_iter), float(rtol),
-                           _ptr(dtheta), _ptr(g), _ptr(stats), _ptr(status), _ptr(ws), ws.numel(), _stream())
+                           _ptr(dtheta), _ptr(g), _ptr(theta), _ptr(stats), _ptr(status), _ptr(ws), ws.numel(),
+                           _stream())
     _raise(code, "sr_cg_solve")
     return dtheta, g, stats, status
+
+
+def peps_profile_enable(on: bool):
+    """Bracket every library launch with HIP events (instrumentation)."""
+    LIB.peps_profile_enable(1 if on else 0)
+
+
+def peps_profile_read():
+    """{kernel class: (total ms, launches)} since the last read; synchronises."""
+    ms = (ctypes.c_double * len(_lib.KCLASS))()
+    cnt = (ctypes.c_int64 * len(_lib.KCLASS))()
+    _raise(LIB.peps_profile_read(ms, cnt), "peps_profile_read")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KCLASS)}

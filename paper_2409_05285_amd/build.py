@@ -1,6 +1,8 @@
 """Build the HIP library (libpeps.so) in-tree for gfx950.
 
-    python -m paper_2409_05285_amd.build
+    python paper_2409_05285_amd/build.py
+
+(Run it by path: importing the package itself requires the built library.)
 
 Every translation unit under csrc/ is compiled by hipcc for gfx950 only and
 linked into one shared library next to this file.  Packed-FP32 instruction

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "peps_common.hpp"
 #include "peps_kernels.hpp"
 
@@ -94,6 +96,41 @@ peps_status device_support(const peps_desc* d, const Prob& P) {
     if ((x) != hipSuccess) return PEPS_ERR_HIP; \
   } while (0)
 
+// Instrumentation: every launch of a kernel class bracketed by two events.
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+size_t g_used = 0;
+
+struct ProfScope {
+  int idx = -1;
+  hipStream_t st;
+  ProfScope(int cls, hipStream_t s) : st(s) {
+    if (!g_prof) return;
+    if (g_used == g_recs.size()) {
+      ProfRec r;
+      r.cls = cls;
+      if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+      g_recs.push_back(r);
+    }
+    idx = (int)g_used++;
+    g_recs[idx].cls = cls;
+    (void)hipEventRecord(g_recs[idx].a, st);
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(g_recs[idx].b, st);
+  }
+};
+
+#define TIMED(cls, call)            \
+  do {                              \
+    ProfScope _ps((cls), st);       \
+    HIP_TRY(call);                  \
+  } while (0)
+
 }  // namespace
 
 extern "C" {
@@ -162,7 +199,7 @@ static peps_status common_checks(const peps_desc* d, Prob& P, int64_t n, const v
 
 static peps_status compress_all_bots(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
                                      int32_t* status, hipStream_t st) {
-  for (int r = P.L1 - 1; r >= 1; --r) HIP_TRY(launch_compress(P, n, 1, r, theta, configs, ws, status, st));
+  for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 1, r, theta, configs, ws, status, st));
   return PEPS_OK;
 }
 
@@ -171,10 +208,10 @@ static peps_status measure(const Prob& P, int n, const double* theta, const uint
                            int32_t* status, hipStream_t st) {
   const int want_e = e_loc != nullptr;
   for (int r = 0; r < P.L1; ++r)
-    HIP_TRY(launch_meas1(P, n, r, theta, configs, ws, O_rows, want_e, status, st));
+    TIMED(PEPS_K_MEAS1, launch_meas1(P, n, r, theta, configs, ws, O_rows, want_e, status, st));
   if (want_e)
-    for (int r = 0; r < P.L1 - 1; ++r) HIP_TRY(launch_meas2(P, n, r, theta, configs, ws, status, st));
-  HIP_TRY(launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, status, st));
+    for (int r = 0; r < P.L1 - 1; ++r) TIMED(PEPS_K_MEAS2, launch_meas2(P, n, r, theta, configs, ws, status, st));
+  TIMED(PEPS_K_FINAL, launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, status, st));
   return PEPS_OK;
 }
 
@@ -187,7 +224,7 @@ peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!log_abs || !sign) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
-  for (int r = 0; r <= P.L1 - 2; ++r) HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
   return measure(P, n, theta, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
@@ -202,7 +239,7 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!O_rows) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
-  for (int r = 0; r <= P.L1 - 2; ++r) HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
   return measure(P, n, theta, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
@@ -227,10 +264,10 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       if (s != PEPS_OK) return s;
     }
     for (int r = 0; r < P.L1; ++r) {
-      HIP_TRY(launch_moves1(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+      TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
       if (r < P.L1 - 1) {
-        HIP_TRY(launch_moves2(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
-        HIP_TRY(launch_compress(P, n, 0, r, theta, configs, w, status, st));
+        TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+        TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
       }
     }
     if (k + 1 < n_sweeps || measure_any) {
@@ -249,8 +286,8 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
 
 peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs, const double* O_rows,
                         const double* weights, const double* e_loc, double tau, double eps, int32_t max_iter,
-                        double rtol, double* dtheta, double* g_out, double* stats, int32_t* status, void* ws,
-                        size_t ws_bytes, peps_stream_t stream) {
+                        double rtol, double* dtheta, double* g_out, double* theta, double* stats,
+                        int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream) {
   if (!desc_ok(d)) return PEPS_ERR_ARG;
   Prob P = make_prob(d);
   if (n_s < 1 || max_iter < 0 || max_iter > SR_MAX_ITER || !isfinite(tau) || !isfinite(eps) || eps < 0.0 ||
@@ -259,9 +296,31 @@ peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs,
   if (!configs || !O_rows || !e_loc || !dtheta || !stats || !ws) return PEPS_ERR_ARG;
   size_t need = sr_workspace_bytes(P, n_s);
   if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
-  HIP_TRY(launch_sr(P, n_s, configs, O_rows, weights, e_loc, tau, eps, max_iter, rtol, dtheta, g_out, stats, status,
-                    ws, (hipStream_t)stream));
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(PEPS_K_SR, launch_sr(P, n_s, configs, O_rows, weights, e_loc, tau, eps, max_iter, rtol, dtheta, g_out, theta,
+                             stats, status, ws, st));
   return PEPS_OK;
+}
+
+void peps_profile_enable(int32_t on) {
+  g_prof = on != 0;
+  g_used = 0;
+}
+
+peps_status peps_profile_read(double* ms, int64_t* launches) {
+  peps_status s = PEPS_OK;
+  for (size_t i = 0; i < g_used; ++i) {
+    float t = 0.f;
+    if (hipEventSynchronize(g_recs[i].b) != hipSuccess || hipEventElapsedTime(&t, g_recs[i].a, g_recs[i].b) != hipSuccess) {
+      s = PEPS_ERR_HIP;
+      continue;
+    }
+    const int c = g_recs[i].cls;
+    if (ms) ms[c] += t;
+    if (launches) launches[c] += 1;
+  }
+  g_used = 0;
+  return s;
 }
 
 }  // extern "C"

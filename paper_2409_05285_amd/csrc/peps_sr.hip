@@ -69,7 +69,10 @@ __global__ void __launch_bounds__(SR_NT) k_sr_weights(SrDev D, const double* wei
     es += wi * D.e[i];
   }
   es = block_sum(es, red);
-  if (tid == 0) D.misc[0] = es;
+  if (tid == 0) {
+    D.misc[0] = es;
+    D.misc[4] = 0.0;  // breakdown flag
+  }
 }
 
 // Fixed-order weighted mean of y (single block): misc[2] = sum_i w_i y_i.
@@ -181,6 +184,7 @@ __global__ void __launch_bounds__(SR_NT) k_sr_update(SrDev D, int it, int32_t* s
   if (!(pAp > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       D.scal[it * 4 + 2] = pAp;
+      D.misc[4] = 1.0;
       set_status(status, PEPS_ERR_CG_BREAKDOWN);
     }
     return;
@@ -239,6 +243,13 @@ __global__ void k_sr_stats(SrDev D, int max_iter, double* stats, int32_t* status
   stats[2] = (double)it;
   stats[3] = D.misc[1];
   if (!isfinite(D.misc[0]) || !isfinite(D.misc[1])) set_status(status, PEPS_ERR_NONFINITE);
+}
+
+// theta += dtheta unless the solve broke down.
+__global__ void __launch_bounds__(SR_NT) k_sr_apply(SrDev D, double* theta) {
+  if (D.misc[4] != 0.0) return;
+  for (int64_t k = (int64_t)blockIdx.x * SR_NT + threadIdx.x; k < D.np; k += (int64_t)D.n_red * SR_NT)
+    theta[k] += D.x[k];
 }
 
 // Column maps of the compressed O rows.
@@ -314,7 +325,7 @@ size_t sr_workspace_bytes(const Prob& P, int64_t n_s) {
 
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
                      const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
-                     double* g_out, double* stats, int32_t* status, void* ws, hipStream_t st) {
+                     double* g_out, double* theta, double* stats, int32_t* status, void* ws, hipStream_t st) {
   SrDev D;
   size_t b = 0;
   sr_layout(P, n_s, D, &b, (char*)ws);
@@ -346,6 +357,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
     hipLaunchKernelGGL(k_sr_direction, dim3(D.n_red), dim3(SR_NT), 0, st, D, it, rtol, max_iter);
   }
   hipLaunchKernelGGL(k_sr_stats, dim3(1), dim3(64), 0, st, D, max_iter, stats, status);
+  if (theta) hipLaunchKernelGGL(k_sr_apply, dim3(D.n_red), dim3(SR_NT), 0, st, D, theta);
   return hipGetLastError();
 }
 
