@@ -125,6 +125,14 @@ struct ProfScope {
   }
 };
 
+// Row compression: the register-resident kernel where its tile limits
+// allow, else the LDS kernel.
+hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
+                        double* ws, int32_t* status, hipStream_t st) {
+  if (compress2_supported(P)) return launch_compress2(P, n, dir, r, theta, configs, ws, status, st);
+  return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
+}
+
 #define TIMED(cls, call)            \
   do {                              \
     ProfScope _ps((cls), st);       \
@@ -199,7 +207,7 @@ static peps_status common_checks(const peps_desc* d, Prob& P, int64_t n, const v
 
 static peps_status compress_all_bots(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
                                      int32_t* status, hipStream_t st) {
-  for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 1, r, theta, configs, ws, status, st));
+  for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 1, r, theta, configs, ws, status, st));
   return PEPS_OK;
 }
 
@@ -224,7 +232,7 @@ peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!log_abs || !sign) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
-  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
   return measure(P, n, theta, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
@@ -239,7 +247,7 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!O_rows) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
-  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
+  for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
   return measure(P, n, theta, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
@@ -267,7 +275,7 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
       if (r < P.L1 - 1) {
         TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
-        TIMED(PEPS_K_COMPRESS, launch_compress(P, n, 0, r, theta, configs, w, status, st));
+        TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
       }
     }
     if (k + 1 < n_sweeps || measure_any) {

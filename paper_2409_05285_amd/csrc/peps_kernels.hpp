@@ -11,6 +11,9 @@ namespace peps {
 constexpr int SR_MAX_ITER = 4096;
 
 size_t compress_dyn_lds(const Prob& P);
+bool compress2_supported(const Prob& P);
+hipError_t launch_compress2(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
+                            double* ws, int32_t* status, hipStream_t st);
 hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                            double* ws, int32_t* status, hipStream_t st);
 hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,

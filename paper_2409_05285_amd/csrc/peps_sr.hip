@@ -27,6 +27,9 @@ struct SrDev {
   const int32_t* base;   // [nnz]
   const int32_t* bsz;    // [nnz]
   const int32_t* site;   // [nnz]
+  const int32_t* soff;   // [N] O-row offset of each site
+  const int32_t* spoff;  // [N] parameter offset of each site
+  const int32_t* sbs;    // [N] block size of each site
   double* w;             // [n_s] normalised weights
   double* y;             // [n_s]
   double* zpart;         // [n_chunks][np]
@@ -85,7 +88,9 @@ __global__ void __launch_bounds__(SR_NT) k_sr_ymean(SrDev D, int it) {
   if (threadIdx.x == 0) D.misc[2] = s;
 }
 
-// y_i = O_i . v (one wavefront per sample row).
+// y_i = O_i . v (one wavefront per sample row).  The row is walked site by
+// site: the block of site s is contiguous in O_i and, for the sample's slice
+// S_i(s), contiguous in v, so both reads are coalesced.
 __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, int it) {
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
   const int lane = threadIdx.x & 63;
@@ -94,7 +99,11 @@ __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, i
   const double* o = D.O + row * D.nnz;
   const uint8_t* S = D.configs + row * D.N;
   double s = 0.0;
-  for (int64_t e = lane; e < D.nnz; e += 64) s += o[e] * v[D.base[e] + (int64_t)S[D.site[e]] * D.bsz[e]];
+  for (int st = 0; st < D.N; ++st) {
+    const int oo = D.soff[st], bs = D.sbs[st];
+    const double* vb = v + D.spoff[st] + (int64_t)S[st] * bs;
+    for (int e = lane; e < bs; e += 64) s += o[oo + e] * vb[e];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) D.y[row] = s;
 }
@@ -253,10 +262,17 @@ __global__ void __launch_bounds__(SR_NT) k_sr_apply(SrDev D, double* theta) {
 }
 
 // Column maps of the compressed O rows.
-__global__ void k_sr_colmap(Prob P, int32_t* base, int32_t* bsz, int32_t* site) {
+__global__ void k_sr_colmap(Prob P, int32_t* base, int32_t* bsz, int32_t* site, int32_t* soff, int32_t* spoff,
+                            int32_t* sbs) {
   __shared__ Geo geo;
   if (threadIdx.x == 0) build_geo(P, geo);
   __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) {
+      soff[i] = geo.ooff[i];
+      spoff[i] = geo.poff[i];
+      sbs[i] = block_size(P, i / P.L2, i % P.L2);
+    }
   for (int i = blockIdx.x; i < P.N; i += gridDim.x) {
     const int r = i / P.L2, c = i % P.L2;
     const int bs = block_size(P, r, c);
@@ -291,6 +307,8 @@ static void sr_layout(const Prob& P, int64_t n_s, SrDev& D, size_t* bytes, char*
   auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
   size_t o_base = take(sizeof(int32_t) * P.nnz), o_bsz = take(sizeof(int32_t) * P.nnz),
          o_site = take(sizeof(int32_t) * P.nnz);
+  size_t o_soff = take(sizeof(int32_t) * P.N), o_spoff = take(sizeof(int32_t) * P.N),
+         o_sbs = take(sizeof(int32_t) * P.N);
   size_t o_w = take(sizeof(double) * n_s), o_y = take(sizeof(double) * n_s);
   size_t o_z = take(sizeof(double) * (size_t)D.n_chunks * P.np);
   size_t o_r = take(sizeof(double) * P.np), o_p = take(sizeof(double) * P.np), o_ap = take(sizeof(double) * P.np);
@@ -303,6 +321,9 @@ static void sr_layout(const Prob& P, int64_t n_s, SrDev& D, size_t* bytes, char*
     D.base = (const int32_t*)(ws + o_base);
     D.bsz = (const int32_t*)(ws + o_bsz);
     D.site = (const int32_t*)(ws + o_site);
+    D.soff = (const int32_t*)(ws + o_soff);
+    D.spoff = (const int32_t*)(ws + o_spoff);
+    D.sbs = (const int32_t*)(ws + o_sbs);
     D.w = (double*)(ws + o_w);
     D.y = (double*)(ws + o_y);
     D.zpart = (double*)(ws + o_z);
@@ -336,7 +357,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
   if (g_out) D.g = g_out;
   const int cb = (int)((P.nnz + SR_NT - 1) / SR_NT);
   hipLaunchKernelGGL(k_sr_colmap, dim3(P.N < 1024 ? P.N : 1024), dim3(256), 0, st, P, (int32_t*)D.base,
-                     (int32_t*)D.bsz, (int32_t*)D.site);
+                     (int32_t*)D.bsz, (int32_t*)D.site, (int32_t*)D.soff, (int32_t*)D.spoff, (int32_t*)D.sbs);
   hipLaunchKernelGGL(k_sr_weights, dim3(1), dim3(SR_NT), 0, st, D, weights);
   auto scatter = [&](int mode, int it) {
     if (P.d2 == 4)
