@@ -1,4 +1,5 @@
-// Workgroup-level strip contractions in FP64 (one workgroup = one chain).
+// Workgroup-level strip contractions (one workgroup = one chain), each a
+// chain of small GEMMs on MFMA 16x16x4 tiles.
 //
 // Index names: a / a2 = bonds of the top boundary MPS, b / b2 = bonds of the
 // bottom boundary MPS, l / r = horizontal PEPS bonds, u / d = vertical PEPS
@@ -6,7 +7,10 @@
 //   boundary tensors T[a][u][a2] (top) and B[b][d][b2] (bottom),
 //   site slices W[l][u][r][d],
 //   one-row environments E[a][l][b], two-row environments E[a][l1][l2][b].
-// Every stage writes a full intermediate, then synchronises the workgroup.
+// Every stage C = A B is a GEMM whose operands are addressed through
+// two-level index maps (a fused index i = (i1, i2) maps to i1 s1 + i2 s2),
+// so no operand is ever permuted in memory.  Stages are separated by a
+// workgroup barrier; intermediates live in the chain's workspace.
 #pragma once
 
 #include "peps_common.hpp"
@@ -16,284 +20,173 @@ namespace peps {
 struct Dim3 { int n0, n1, n2; };
 struct Dim4 { int n0, n1, n2, n3; };
 
-// One column of a one-row strip from the left:
-//   out[a2][r][b2] = sum L[a][l][b] T[a][u][a2] W[l][u][r][d] B[b][d][b2]
-__device__ inline void lstep1(double* out, const double* L, const double* T, Dim3 tD,
-                              const double* W, Dim4 wD, const double* B, Dim3 bD,
-                              double* X0, double* X1) {
-  const int tid = threadIdx.x;
-  const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
-  const int nl = wD.n0, nr = wD.n2, nd = wD.n3;
-  const int nb = bD.n0, nb2 = bD.n2;
-  // X0[l][b][u][a2] = sum_a L[a][l][b] T[a][u][a2]
-  const int n0 = nl * nb * nu * na2;
-  for (int idx = tid; idx < n0; idx += NT) {
-    int a2 = idx % na2, t = idx / na2;
-    int u = t % nu; t /= nu;
-    int b = t % nb, l = t / nb;
-    double s = 0.0;
-    for (int a = 0; a < na; ++a) s += L[(a * nl + l) * nb + b] * T[(a * nu + u) * na2 + a2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // X1[b][a2][r][d] = sum_{l,u} X0[l][b][u][a2] W[l][u][r][d]
-  const int n1 = nb * na2 * nr * nd;
-  for (int idx = tid; idx < n1; idx += NT) {
-    int dd = idx % nd, t = idx / nd;
-    int rr = t % nr; t /= nr;
-    int a2 = t % na2, b = t / na2;
-    double s = 0.0;
-    for (int l = 0; l < nl; ++l)
-      for (int u = 0; u < nu; ++u)
-        s += X0[((l * nb + b) * nu + u) * na2 + a2] * W[((l * nu + u) * nr + rr) * nd + dd];
-    X1[idx] = s;
-  }
-  __syncthreads();
-  // out[a2][r][b2] = sum_{b,d} X1[b][a2][r][d] B[b][d][b2]
-  const int n2 = na2 * nr * nb2;
-  for (int idx = tid; idx < n2; idx += NT) {
-    int b2 = idx % nb2, t = idx / nb2;
-    int rr = t % nr, a2 = t / nr;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b)
-      for (int dd = 0; dd < nd; ++dd)
-        s += X1[((b * na2 + a2) * nr + rr) * nd + dd] * B[(b * nd + dd) * nb2 + b2];
-    out[idx] = s;
+// i -> (i / n2) * s1 + (i % n2) * s2
+struct Map2 {
+  int n2, s1, s2;
+  __device__ inline int operator()(int i) const { return (i / n2) * s1 + (i % n2) * s2; }
+};
+__device__ inline Map2 mstride(int s) { return Map2{1, s, 0}; }   // i -> i * s
+__device__ inline Map2 mid() { return Map2{1, 1, 0}; }            // i -> i
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// MFMA 16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator register v of lane l holds C[row(l, v)][l % 16].
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  __device__ static inline acc run(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  __device__ static inline acc run(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// C(m, n) = sum_k A(m, k) B(k, n) for m < M, n < N, k < K, with
+//   A(m, k) = A[am(m) + ak(k)], B(k, n) = B[bk(k) + bn(n)], C at cm(m) + cn(n).
+// Tiles of 16 x 16 are dealt round-robin to the waves of the workgroup.
+// Ends with a workgroup barrier.
+template <typename T>
+__device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn,
+                               int M, int N, int K) {
+  using MF = Mfma<T>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) << 4, n0 = (t % tn) << 4;
+    const int m = m0 + li, n = n0 + li;
+    const bool mv = m < M, nv = n < N;
+    const int ao = mv ? am(m) : 0, bo = nv ? bn(n) : 0;
+    typename MF::acc c = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kv = k < K;
+      const T a = (mv && kv) ? A[ao + ak(k)] : T(0);
+      const T b = (nv && kv) ? B[bk(k) + bo] : T(0);
+      c = MF::run(a, b, c);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + MF::row(lane, v);
+      if (row < M && nv) C[cm(row) + cn(n)] = c[v];
+    }
   }
   __syncthreads();
 }
 
-// One column of a one-row strip from the right:
-//   out[a][l][b] = sum T[a][u][a2] W[l][u][r][d] B[b][d][b2] R[a2][r][b2]
-__device__ inline void rstep1(double* out, const double* R, const double* T, Dim3 tD,
-                              const double* W, Dim4 wD, const double* B, Dim3 bD,
-                              double* X0, double* X1) {
-  const int tid = threadIdx.x;
+template <typename T>
+__device__ inline void wg_gemm_rm(T* C, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn, int M, int N,
+                                  int K) {
+  wg_gemm<T>(C, mstride(N), mid(), A, am, ak, B, bk, bn, M, N, K);
+}
+
+// One column of a one-row strip from the left:
+//   out[a2][r][b2] = sum L[a][l][b] T[a][u][a2] W[l][u][r][d] B[b][d][b2]
+template <typename T>
+__device__ inline void lstep1(T* out, const T* L, const T* Tt, Dim3 tD, const T* W, Dim4 wD, const T* B, Dim3 bD,
+                              T* X0, T* X1) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl = wD.n0, nr = wD.n2, nd = wD.n3;
   const int nb = bD.n0, nb2 = bD.n2;
-  // X0[b][d][a2][r] = sum_b2 B[b][d][b2] R[a2][r][b2]
-  const int n0 = nb * nd * na2 * nr;
-  for (int idx = tid; idx < n0; idx += NT) {
-    int rr = idx % nr, t = idx / nr;
-    int a2 = t % na2; t /= na2;
-    int dd = t % nd, b = t / nd;
-    double s = 0.0;
-    for (int b2 = 0; b2 < nb2; ++b2) s += B[(b * nd + dd) * nb2 + b2] * R[(a2 * nr + rr) * nb2 + b2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // X1[l][u][b][a2] = sum_{r,d} W[l][u][r][d] X0[b][d][a2][r]
-  const int n1 = nl * nu * nb * na2;
-  for (int idx = tid; idx < n1; idx += NT) {
-    int a2 = idx % na2, t = idx / na2;
-    int b = t % nb; t /= nb;
-    int u = t % nu, l = t / nu;
-    double s = 0.0;
-    for (int rr = 0; rr < nr; ++rr)
-      for (int dd = 0; dd < nd; ++dd)
-        s += W[((l * nu + u) * nr + rr) * nd + dd] * X0[((b * nd + dd) * na2 + a2) * nr + rr];
-    X1[idx] = s;
-  }
-  __syncthreads();
-  // out[a][l][b] = sum_{u,a2} T[a][u][a2] X1[l][u][b][a2]
-  const int n2 = na * nl * nb;
-  for (int idx = tid; idx < n2; idx += NT) {
-    int b = idx % nb, t = idx / nb;
-    int l = t % nl, a = t / nl;
-    double s = 0.0;
-    for (int u = 0; u < nu; ++u)
-      for (int a2 = 0; a2 < na2; ++a2)
-        s += T[(a * nu + u) * na2 + a2] * X1[((l * nu + u) * nb + b) * na2 + a2];
-    out[idx] = s;
-  }
-  __syncthreads();
+  // X0[(l b)][(u a2)] = sum_a L[a][(l b)] T[a][(u a2)]
+  wg_gemm_rm<T>(X0, L, mid(), mstride(nl * nb), Tt, mstride(nu * na2), mid(), nl * nb, nu * na2, na);
+  // X1[(b a2)][(r d)] = sum_{l,u} X0[l][b][u][a2] W[(l u)][(r d)]
+  wg_gemm_rm<T>(X1, X0, Map2{na2, nu * na2, 1}, Map2{nu, nb * nu * na2, na2}, W, mstride(nr * nd), mid(),
+                nb * na2, nr * nd, nl * nu);
+  // out[(a2 r)][b2] = sum_{b,d} X1[b][a2][r][d] B[(b d)][b2]
+  wg_gemm_rm<T>(out, X1, mstride(nd), Map2{nd, na2 * nr * nd, 1}, B, mstride(nb2), mid(), na2 * nr, nb2, nb * nd);
+}
+
+// One column of a one-row strip from the right:
+//   out[a][l][b] = sum T[a][u][a2] W[l][u][r][d] B[b][d][b2] R[a2][r][b2]
+template <typename T>
+__device__ inline void rstep1(T* out, const T* R, const T* Tt, Dim3 tD, const T* W, Dim4 wD, const T* B, Dim3 bD,
+                              T* X0, T* X1) {
+  const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
+  const int nl = wD.n0, nr = wD.n2, nd = wD.n3;
+  const int nb = bD.n0, nb2 = bD.n2;
+  // X0[(b d)][(a2 r)] = sum_b2 B[(b d)][b2] R[(a2 r)][b2]
+  wg_gemm_rm<T>(X0, B, mstride(nb2), mid(), R, mid(), mstride(nb2), nb * nd, na2 * nr, nb2);
+  // X1[(l u)][(b a2)] = sum_{r,d} W[(l u)][(r d)] X0[b][d][a2][r]
+  wg_gemm_rm<T>(X1, W, mstride(nr * nd), mid(), X0, Map2{nd, 1, na2 * nr}, Map2{na2, nd * na2 * nr, nr}, nl * nu,
+                nb * na2, nr * nd);
+  // out[a][(l b)] = sum_{u,a2} T[a][(u a2)] X1[l][u][b][a2]
+  wg_gemm_rm<T>(out, Tt, mstride(nu * na2), mid(), X1, Map2{na2, nb * na2, 1}, Map2{nb, nu * nb * na2, na2}, na,
+                nl * nb, nu * na2);
 }
 
 // One column of a two-row strip from the left:
 //   out[a2][r1][r2][b2] = sum L[a][l1][l2][b] T[a][u][a2] W1[l1][u][r1][d1]
 //                             W2[l2][d1][r2][d2] B[b][d2][b2]
-__device__ inline void lstep2(double* out, const double* L, const double* T, Dim3 tD,
-                              const double* W1, Dim4 w1, const double* W2, Dim4 w2,
-                              const double* B, Dim3 bD, double* X0, double* X1) {
-  const int tid = threadIdx.x;
+template <typename T>
+__device__ inline void lstep2(T* out, const T* L, const T* Tt, Dim3 tD, const T* W1, Dim4 w1, const T* W2, Dim4 w2,
+                              const T* B, Dim3 bD, T* X0, T* X1) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl1 = w1.n0, nr1 = w1.n2, nd1 = w1.n3;
   const int nl2 = w2.n0, nr2 = w2.n2, nd2 = w2.n3;
   const int nb = bD.n0, nb2 = bD.n2;
-  // X0[l1][l2][b][u][a2] = sum_a L[a][l1][l2][b] T[a][u][a2]
-  const int n0 = nl1 * nl2 * nb * nu * na2;
-  for (int idx = tid; idx < n0; idx += NT) {
-    int a2 = idx % na2, t = idx / na2;
-    int u = t % nu; t /= nu;
-    int b = t % nb; t /= nb;
-    int l2 = t % nl2, l1 = t / nl2;
-    double s = 0.0;
-    for (int a = 0; a < na; ++a)
-      s += L[((a * nl1 + l1) * nl2 + l2) * nb + b] * T[(a * nu + u) * na2 + a2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // X1[l2][b][a2][r1][d1] = sum_{l1,u} X0[l1][l2][b][u][a2] W1[l1][u][r1][d1]
-  const int n1 = nl2 * nb * na2 * nr1 * nd1;
-  for (int idx = tid; idx < n1; idx += NT) {
-    int d1 = idx % nd1, t = idx / nd1;
-    int r1 = t % nr1; t /= nr1;
-    int a2 = t % na2; t /= na2;
-    int b = t % nb, l2 = t / nb;
-    double s = 0.0;
-    for (int l1 = 0; l1 < nl1; ++l1)
-      for (int u = 0; u < nu; ++u)
-        s += X0[(((l1 * nl2 + l2) * nb + b) * nu + u) * na2 + a2] * W1[((l1 * nu + u) * nr1 + r1) * nd1 + d1];
-    X1[idx] = s;
-  }
-  __syncthreads();
-  // X0[b][a2][r1][r2][d2] = sum_{l2,d1} X1[l2][b][a2][r1][d1] W2[l2][d1][r2][d2]
-  const int n2 = nb * na2 * nr1 * nr2 * nd2;
-  for (int idx = tid; idx < n2; idx += NT) {
-    int d2 = idx % nd2, t = idx / nd2;
-    int r2 = t % nr2; t /= nr2;
-    int r1 = t % nr1; t /= nr1;
-    int a2 = t % na2, b = t / na2;
-    double s = 0.0;
-    for (int l2 = 0; l2 < nl2; ++l2)
-      for (int d1 = 0; d1 < nd1; ++d1)
-        s += X1[(((l2 * nb + b) * na2 + a2) * nr1 + r1) * nd1 + d1] * W2[((l2 * nd1 + d1) * nr2 + r2) * nd2 + d2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // out[a2][r1][r2][b2] = sum_{b,d2} X0[b][a2][r1][r2][d2] B[b][d2][b2]
-  const int n3 = na2 * nr1 * nr2 * nb2;
-  for (int idx = tid; idx < n3; idx += NT) {
-    int b2 = idx % nb2, t = idx / nb2;
-    int r2 = t % nr2; t /= nr2;
-    int r1 = t % nr1, a2 = t / nr1;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b)
-      for (int d2 = 0; d2 < nd2; ++d2)
-        s += X0[(((b * na2 + a2) * nr1 + r1) * nr2 + r2) * nd2 + d2] * B[(b * nd2 + d2) * nb2 + b2];
-    out[idx] = s;
-  }
-  __syncthreads();
+  // X0[(l1 l2 b)][(u a2)] = sum_a L[a][(l1 l2 b)] T[a][(u a2)]
+  wg_gemm_rm<T>(X0, L, mid(), mstride(nl1 * nl2 * nb), Tt, mstride(nu * na2), mid(), nl1 * nl2 * nb, nu * na2, na);
+  // X1[(l2 b a2)][(r1 d1)] = sum_{l1,u} X0[l1][(l2 b)][u][a2] W1[(l1 u)][(r1 d1)]
+  wg_gemm_rm<T>(X1, X0, Map2{na2, nu * na2, 1}, Map2{nu, nl2 * nb * nu * na2, na2}, W1, mstride(nr1 * nd1), mid(),
+                nl2 * nb * na2, nr1 * nd1, nl1 * nu);
+  // X0[(b a2 r1)][(r2 d2)] = sum_{l2,d1} X1[l2][(b a2 r1)][d1] W2[(l2 d1)][(r2 d2)]
+  wg_gemm_rm<T>(X0, X1, mstride(nd1), Map2{nd1, nb * na2 * nr1 * nd1, 1}, W2, mstride(nr2 * nd2), mid(),
+                nb * na2 * nr1, nr2 * nd2, nl2 * nd1);
+  // out[(a2 r1 r2)][b2] = sum_{b,d2} X0[b][(a2 r1 r2)][d2] B[(b d2)][b2]
+  wg_gemm_rm<T>(out, X0, mstride(nd2), Map2{nd2, na2 * nr1 * nr2 * nd2, 1}, B, mstride(nb2), mid(),
+                na2 * nr1 * nr2, nb2, nb * nd2);
 }
 
 // One column of a two-row strip from the right:
 //   out[a][l1][l2][b] = sum T[a][u][a2] W1[l1][u][r1][d1] W2[l2][d1][r2][d2]
 //                           B[b][d2][b2] R[a2][r1][r2][b2]
-__device__ inline void rstep2(double* out, const double* R, const double* T, Dim3 tD,
-                              const double* W1, Dim4 w1, const double* W2, Dim4 w2,
-                              const double* B, Dim3 bD, double* X0, double* X1) {
-  const int tid = threadIdx.x;
+template <typename T>
+__device__ inline void rstep2(T* out, const T* R, const T* Tt, Dim3 tD, const T* W1, Dim4 w1, const T* W2, Dim4 w2,
+                              const T* B, Dim3 bD, T* X0, T* X1) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl1 = w1.n0, nr1 = w1.n2, nd1 = w1.n3;
   const int nl2 = w2.n0, nr2 = w2.n2, nd2 = w2.n3;
   const int nb = bD.n0, nb2 = bD.n2;
-  // X0[b][d2][a2][r1][r2] = sum_b2 B[b][d2][b2] R[a2][r1][r2][b2]
-  const int n0 = nb * nd2 * na2 * nr1 * nr2;
-  for (int idx = tid; idx < n0; idx += NT) {
-    int r2 = idx % nr2, t = idx / nr2;
-    int r1 = t % nr1; t /= nr1;
-    int a2 = t % na2; t /= na2;
-    int d2 = t % nd2, b = t / nd2;
-    double s = 0.0;
-    for (int b2 = 0; b2 < nb2; ++b2)
-      s += B[(b * nd2 + d2) * nb2 + b2] * R[((a2 * nr1 + r1) * nr2 + r2) * nb2 + b2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // X1[l2][d1][b][a2][r1] = sum_{r2,d2} W2[l2][d1][r2][d2] X0[b][d2][a2][r1][r2]
-  const int n1 = nl2 * nd1 * nb * na2 * nr1;
-  for (int idx = tid; idx < n1; idx += NT) {
-    int r1 = idx % nr1, t = idx / nr1;
-    int a2 = t % na2; t /= na2;
-    int b = t % nb; t /= nb;
-    int d1 = t % nd1, l2 = t / nd1;
-    double s = 0.0;
-    for (int r2 = 0; r2 < nr2; ++r2)
-      for (int d2 = 0; d2 < nd2; ++d2)
-        s += W2[((l2 * nd1 + d1) * nr2 + r2) * nd2 + d2] * X0[(((b * nd2 + d2) * na2 + a2) * nr1 + r1) * nr2 + r2];
-    X1[idx] = s;
-  }
-  __syncthreads();
-  // X0[l1][u][l2][b][a2] = sum_{r1,d1} W1[l1][u][r1][d1] X1[l2][d1][b][a2][r1]
-  const int n2 = nl1 * nu * nl2 * nb * na2;
-  for (int idx = tid; idx < n2; idx += NT) {
-    int a2 = idx % na2, t = idx / na2;
-    int b = t % nb; t /= nb;
-    int l2 = t % nl2; t /= nl2;
-    int u = t % nu, l1 = t / nu;
-    double s = 0.0;
-    for (int r1 = 0; r1 < nr1; ++r1)
-      for (int d1 = 0; d1 < nd1; ++d1)
-        s += W1[((l1 * nu + u) * nr1 + r1) * nd1 + d1] * X1[(((l2 * nd1 + d1) * nb + b) * na2 + a2) * nr1 + r1];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // out[a][l1][l2][b] = sum_{u,a2} T[a][u][a2] X0[l1][u][l2][b][a2]
-  const int n3 = na * nl1 * nl2 * nb;
-  for (int idx = tid; idx < n3; idx += NT) {
-    int b = idx % nb, t = idx / nb;
-    int l2 = t % nl2; t /= nl2;
-    int l1 = t % nl1, a = t / nl1;
-    double s = 0.0;
-    for (int u = 0; u < nu; ++u)
-      for (int a2 = 0; a2 < na2; ++a2)
-        s += T[(a * nu + u) * na2 + a2] * X0[(((l1 * nu + u) * nl2 + l2) * nb + b) * na2 + a2];
-    out[idx] = s;
-  }
-  __syncthreads();
+  // X0[(b d2)][(a2 r1 r2)] = sum_b2 B[(b d2)][b2] R[(a2 r1 r2)][b2]
+  wg_gemm_rm<T>(X0, B, mstride(nb2), mid(), R, mid(), mstride(nb2), nb * nd2, na2 * nr1 * nr2, nb2);
+  // X1[(l2 d1)][(b a2 r1)] = sum_{r2,d2} W2[(l2 d1)][(r2 d2)] X0[b][d2][(a2 r1)][r2]
+  wg_gemm_rm<T>(X1, W2, mstride(nr2 * nd2), mid(), X0, Map2{nd2, 1, na2 * nr1 * nr2},
+                Map2{na2 * nr1, nd2 * na2 * nr1 * nr2, nr2}, nl2 * nd1, nb * na2 * nr1, nr2 * nd2);
+  // X0[(l1 u)][(l2 b a2)] = sum_{r1,d1} W1[(l1 u)][(r1 d1)] X1[l2][d1][(b a2)][r1]
+  wg_gemm_rm<T>(X0, W1, mstride(nr1 * nd1), mid(), X1, Map2{nd1, 1, nb * na2 * nr1},
+                Map2{nb * na2, nd1 * nb * na2 * nr1, nr1}, nl1 * nu, nl2 * nb * na2, nr1 * nd1);
+  // out[a][(l1 l2 b)] = sum_{u,a2} T[a][(u a2)] X0[l1][u][(l2 b)][a2]
+  wg_gemm_rm<T>(out, Tt, mstride(nu * na2), mid(), X0, Map2{na2, nl2 * nb * na2, 1},
+                Map2{nl2 * nb, nu * nl2 * nb * na2, na2}, na, nl1 * nl2 * nb, nu * na2);
 }
 
 // Environment of one site in a one-row strip (the strip is linear in W):
 //   env[l][u][r][d] = sum L[a][l][b] T[a][u][a2] B[b][d][b2] R[a2][r][b2]
-__device__ inline void site_env1(double* env, const double* L, const double* T, Dim3 tD,
-                                 const double* B, Dim3 bD, const double* R, int nl, int nr,
-                                 double* X0, double* X1) {
-  const int tid = threadIdx.x;
+template <typename T>
+__device__ inline void site_env1(T* env, const T* L, const T* Tt, Dim3 tD, const T* B, Dim3 bD, const T* R, int nl,
+                                 int nr, T* X0, T* X1) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nb = bD.n0, nd = bD.n1, nb2 = bD.n2;
-  // X0[l][b][u][a2] = sum_a L[a][l][b] T[a][u][a2]
-  const int n0 = nl * nb * nu * na2;
-  for (int idx = tid; idx < n0; idx += NT) {
-    int a2 = idx % na2, t = idx / na2;
-    int u = t % nu; t /= nu;
-    int b = t % nb, l = t / nb;
-    double s = 0.0;
-    for (int a = 0; a < na; ++a) s += L[(a * nl + l) * nb + b] * T[(a * nu + u) * na2 + a2];
-    X0[idx] = s;
-  }
-  __syncthreads();
-  // X1[l][u][a2][d][b2] = sum_b X0[l][b][u][a2] B[b][d][b2]
-  const int n1 = nl * nu * na2 * nd * nb2;
-  for (int idx = tid; idx < n1; idx += NT) {
-    int b2 = idx % nb2, t = idx / nb2;
-    int dd = t % nd; t /= nd;
-    int a2 = t % na2; t /= na2;
-    int u = t % nu, l = t / nu;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += X0[((l * nb + b) * nu + u) * na2 + a2] * B[(b * nd + dd) * nb2 + b2];
-    X1[idx] = s;
-  }
-  __syncthreads();
-  // env[l][u][r][d] = sum_{a2,b2} X1[l][u][a2][d][b2] R[a2][r][b2]
-  const int n2 = nl * nu * nr * nd;
-  for (int idx = tid; idx < n2; idx += NT) {
-    int dd = idx % nd, t = idx / nd;
-    int rr = t % nr; t /= nr;
-    int u = t % nu, l = t / nu;
-    double s = 0.0;
-    for (int a2 = 0; a2 < na2; ++a2)
-      for (int b2 = 0; b2 < nb2; ++b2)
-        s += X1[(((l * nu + u) * na2 + a2) * nd + dd) * nb2 + b2] * R[(a2 * nr + rr) * nb2 + b2];
-    env[idx] = s;
-  }
-  __syncthreads();
+  // X0[(l b)][(u a2)] = sum_a L[a][(l b)] T[a][(u a2)]
+  wg_gemm_rm<T>(X0, L, mid(), mstride(nl * nb), Tt, mstride(nu * na2), mid(), nl * nb, nu * na2, na);
+  // X1[(l u a2)][(d b2)] = sum_b X0[l][b][(u a2)] B[b][(d b2)]
+  wg_gemm_rm<T>(X1, X0, Map2{nu * na2, nb * nu * na2, 1}, mstride(nu * na2), B, mstride(nd * nb2), mid(),
+                nl * nu * na2, nd * nb2, nb);
+  // env[(l u)][r][d] = sum_{a2,b2} X1[(l u)][a2][d][b2] R[a2][r][b2]   (rows (l u d), cols r)
+  wg_gemm<T>(env, Map2{nd, nr * nd, 1}, mstride(nd), X1, Map2{nd, na2 * nd * nb2, nb2}, Map2{nb2, nd * nb2, 1}, R,
+             Map2{nb2, nr * nb2, 1}, mstride(nb2), nl * nu * nd, nr, na2 * nb2);
 }
 
 // sum_i x[i] y[i], identical on every thread.
-__device__ inline double wg_dot(const double* x, const double* y, int n, double* red) {
+template <typename T>
+__device__ inline double wg_dot(const T* x, const T* y, int n, double* red) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) s += x[i] * y[i];
+  for (int i = threadIdx.x; i < n; i += NT) s += (double)x[i] * (double)y[i];
   return wg_sum(s, red);
 }
 
