@@ -198,7 +198,7 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
 }  // namespace
 
 template <int DP>
-__global__ void __launch_bounds__(NTC) k_compress2(Prob P, int dir, int r, const double* __restrict__ theta,
+__global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, const double* __restrict__ theta,
                                                      const uint8_t* __restrict__ configs, double* ws,
                                                      int32_t* status) {
   __shared__ double qv[2][QR_ROWS_MAX];
@@ -325,63 +325,61 @@ __global__ void __launch_bounds__(NTC) k_compress2(Prob P, int dir, int r, const
     const int m = sa[c] * sp[c], n = sb[c];
     const int k = m < n ? m : n;
     // ---- factorisation ----
-    for (int jb = 0; jb < k; jb += QR_CPW) {
+    for (int j = 0; j < k; ++j) {
+      const int bf = j & 1;
+      const int cj = j % QR_CPW;               // column of j inside its wave
+      if (wv_id == j / QR_CPW) {               // owner wave of column j
+        double x[QR_RPL];
 #pragma unroll
-      for (int cj = 0; cj < QR_CPW; ++cj) {
-        const int j = jb + cj;
-        if (j < k) {
-          const int bf = j & 1;
-          if (wv_id == (jb / QR_CPW)) {          // owner wave of column j
-            double ps = 0.0, aj = 0.0;
+        for (int i = 0; i < QR_RPL; ++i) {
+          double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int row = r0 + i;
-              const double x = av[i][cj];
-              ps += row > j ? x * x : 0.0;
-              aj += row == j ? x : 0.0;
-            }
-            const double sigma2 = wave_sum(ps);
-            const double alpha = wave_sum(aj);
-            double tau = 0.0, scale = 0.0, beta = alpha;
-            if (sigma2 > 0.0) {
-              const double nrm = sqrt(alpha * alpha + sigma2);
-              beta = alpha >= 0.0 ? -nrm : nrm;
-              tau = (beta - alpha) / beta;
-              scale = 1.0 / (alpha - beta);
-            }
+          for (int cc = 0; cc < QR_CPW; ++cc) t = cc == cj ? av[i][cc] : t;
+          x[i] = t;
+        }
+        double ps = 0.0, aj = 0.0;
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int row = r0 + i;
-              const double x = av[i][cj];
-              const double v = row > j ? x * scale : (row == j ? 1.0 : 0.0);
-              qv[bf][row] = v;
-              av[i][cj] = row > j ? v : (row == j ? beta : x);
-            }
-            if (lane == 0) { qtau[bf] = tau; taus[j] = tau; }
-          }
-          __syncthreads();
-          const double tau = qtau[bf];
-          if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < n) {
-            double v[QR_RPL];
+        for (int i = 0; i < QR_RPL; ++i) {
+          const int row = r0 + i;
+          ps += row > j ? x[i] * x[i] : 0.0;
+          aj += row == j ? x[i] : 0.0;
+        }
+        const double sigma2 = wave_sum(ps);
+        const double alpha = wave_sum(aj);
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (sigma2 > 0.0) {
+          const double nrm = sqrt(alpha * alpha + sigma2);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
-            double wsum[QR_CPW];
+        for (int i = 0; i < QR_RPL; ++i) {
+          const int row = r0 + i;
+          const double v = row > j ? x[i] * scale : (row == j ? 1.0 : 0.0);
+          qv[bf][row] = v;
+          const double nx = row > j ? v : (row == j ? beta : x[i]);
 #pragma unroll
-            for (int cc = 0; cc < QR_CPW; ++cc) {
-              double s = 0.0;
+          for (int cc = 0; cc < QR_CPW; ++cc) av[i][cc] = cc == cj ? nx : av[i][cc];
+        }
+        if (lane == 0) { qtau[bf] = tau; taus[j] = tau; }
+      }
+      __syncthreads();
+      const double tau = qtau[bf];
+      if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < n) {
+        double v[QR_RPL];
 #pragma unroll
-              for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
-              wsum[cc] = s;
-            }
+        for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
 #pragma unroll
-            for (int cc = 0; cc < QR_CPW; ++cc) {
-              const int cl = c0 + cc;
-              if (cl > j && cl < n) {        // uniform over the wave
-                const double tw = tau * wave_sum(wsum[cc]);
+        for (int cc = 0; cc < QR_CPW; ++cc) {
+          const int cl = c0 + cc;
+          if (cl > j && cl < n) {        // uniform over the wave
+            double s = 0.0;
 #pragma unroll
-                for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
-              }
-            }
+            for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
+            const double tw = tau * wave_sum(s);
+#pragma unroll
+            for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
           }
         }
       }
@@ -398,52 +396,46 @@ __global__ void __launch_bounds__(NTC) k_compress2(Prob P, int dir, int r, const
         }
     }
     // ---- explicit thin Q (m x k) by backward accumulation ----
-    for (int jb = ((k - 1) / QR_CPW) * QR_CPW; jb >= 0; jb -= QR_CPW) {
+    for (int j = k - 1; j >= 0; --j) {
+      const int bf = j & 1;
+      const int cj = j % QR_CPW;
+      const double tau = taus[j];
+      const bool own = wv_id == j / QR_CPW;
+      if (own) {
 #pragma unroll
-      for (int cjr = 0; cjr < QR_CPW; ++cjr) {
-        const int cj = QR_CPW - 1 - cjr;
-        const int j = jb + cj;
-        if (j < k) {
-          const int bf = j & 1;
-          const double tau = taus[j];
-          if (wv_id == (jb / QR_CPW)) {
+        for (int i = 0; i < QR_RPL; ++i) {
+          const int row = r0 + i;
+          double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int row = r0 + i;
-              qv[bf][row] = row > j ? av[i][cj] : (row == j ? 1.0 : 0.0);
-            }
+          for (int cc = 0; cc < QR_CPW; ++cc) t = cc == cj ? av[i][cc] : t;
+          qv[bf][row] = row > j ? t : (row == j ? 1.0 : 0.0);
+        }
+      }
+      __syncthreads();
+      if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < k) {
+        double v[QR_RPL];
+#pragma unroll
+        for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
+#pragma unroll
+        for (int cc = 0; cc < QR_CPW; ++cc) {
+          const int cl = c0 + cc;
+          if (cl > j && cl < k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
+            const double tw = tau * wave_sum(s);
+#pragma unroll
+            for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
           }
-          __syncthreads();
-          if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < k) {
-            double v[QR_RPL];
+        }
+      }
+      if (own) {
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
-            double wsum[QR_CPW];
+        for (int i = 0; i < QR_RPL; ++i) {
+          const int row = r0 + i;
 #pragma unroll
-            for (int cc = 0; cc < QR_CPW; ++cc) {
-              double s = 0.0;
-#pragma unroll
-              for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
-              wsum[cc] = s;
-            }
-#pragma unroll
-            for (int cc = 0; cc < QR_CPW; ++cc) {
-              const int cl = c0 + cc;
-              if (cl > j && cl < k) {
-                const double tw = tau * wave_sum(wsum[cc]);
-#pragma unroll
-                for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
-              }
-            }
-          }
-          if (wv_id == (jb / QR_CPW)) {
-#pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int row = r0 + i;
-              const double x = av[i][cj];
-              av[i][cj] = row < j ? 0.0 : (row == j ? 1.0 - tau : -tau * x);
-            }
-          }
+          for (int cc = 0; cc < QR_CPW; ++cc)
+            if (cc == cj) av[i][cc] = row < j ? 0.0 : (row == j ? 1.0 - tau : -tau * av[i][cc]);
         }
       }
     }
