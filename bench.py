@@ -10,6 +10,15 @@ Metric: samples per second (one sample = one chain's sweep + measurement).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--cg-iters 200]
 
+Both precisions run the same K steps from the same state: FP64 throughout,
+and mixed (FP32 MFMA strip contractions with FP64 QR/SVD, reductions and
+SR).  The energy error is |E_mixed - E_fp64| / |E_fp64| of the mean local
+energy over the same samples and parameters, taken on a cooled state (the
+beta = 0 identity plus noise after --cool-steps FP64 SR steps) and reported
+also on the random-tensor state of the timed run.  `value` is the mixed
+path's rate when the cooled-state error is within --tol, else the FP64
+rate.
+
 Prints one JSON line.  The CPU baseline is the FP64 oracle (tests only,
 never the product path) timed on a bounded sample on this host.
 """
@@ -164,38 +173,13 @@ def cpu_baseline(L1, L2, D, chi, seed_theta, seed, cg_iters, target_core_s=20.0)
 
 
 # ---------------------------------------------------------------------------
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--L", type=int, default=8)
-    ap.add_argument("--D", type=int, default=4)
-    ap.add_argument("--chi", type=int, default=16)
-    ap.add_argument("--chains", type=int, default=1024)
-    ap.add_argument("--cg-iters", type=int, default=200)
-    ap.add_argument("--tau", type=float, default=0.02)
-    ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
-              "path is a design note, not an implemented mode", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_2409_05285_amd as p
-    import synth
-
-    dev = torch.device("cuda:0")
-    L1 = L2 = args.L
-    D, chi, n = args.D, args.chi, args.chains
-    desc = p.Desc(L1, L2, D, chi)
-    seed_theta, seed = 102, 20240905
-    theta = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
-    configs = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
+def run_path(p, torch, desc, theta0, configs0, args, seed):
+    """Times args.steps steps of one precision from the given state; returns
+    timings, the per-class kernel profile and the final state."""
+    dev = theta0.device
+    n = configs0.shape[0]
+    theta = theta0.clone()
+    configs = configs0.clone()
     nnz = p.peps_orow_count(desc)
     out = {
         "log_abs": torch.empty((1, n), dtype=torch.float64, device=dev),
@@ -212,14 +196,15 @@ def main():
         res = p.peps_sample_sweep(desc, theta, configs, seed, gsweep[0], 1, n_accept=n_accept, status=status,
                                   out=out)
         gsweep[0] += 1
-        dth, g, stats, _ = p.sr_cg_solve(desc, configs, res["O"][0], res["e_loc"][0], args.tau, args.eps,
-                                         args.cg_iters, 1e-10, want_g=False, theta=theta, status=status)
+        _, _, stats, _ = p.sr_cg_solve(desc, configs, res["O"][0], res["e_loc"][0], args.tau, args.eps,
+                                       args.cg_iters, 1e-10, want_g=False, theta=theta, status=status)
         last["stats"] = stats
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     p.check(status, "warmup")
+    n_accept.zero_()
 
     p.peps_profile_enable(True)
     torch.cuda.synchronize()
@@ -235,14 +220,123 @@ def main():
     prof = p.peps_profile_read()
     p.peps_profile_enable(False)
     p.check(status, "timed steps")
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
-    samples_per_s = n / (ms_per_step / 1e3)
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    st = last["stats"].cpu().numpy()
+    acc = n_accept.cpu().numpy().sum(axis=0) / (n * args.steps)
+    return {"ms_per_step": ms_per_step, "samples_per_s": n / (ms_per_step / 1e3), "wall": wall, "prof": prof,
+            "stats": st, "accept": acc, "theta": theta, "configs": configs}
+
+
+def energy_error(p, torch, desc64, descmx, theta, configs):
+    """Local energies of the same samples and parameters from both
+    precisions: relative error of the mean energy, the same error in units
+    of the mean |E_loc| and of the Monte Carlo standard error, and per-sample
+    relative errors (scale max(|E_i|, mean |E|))."""
+    import numpy as np
+    _, _, e64, s1 = p.peps_eval_batch(desc64, theta, configs)
+    _, _, emx, s2 = p.peps_eval_batch(descmx, theta, configs)
+    torch.cuda.synchronize()
+    p.check(s1, "fp64 eval")
+    p.check(s2, "mixed eval")
+    e64 = e64.cpu().numpy()
+    emx = emx.cpu().numpy()
+    dE = abs(emx.mean() - e64.mean())
+    rel = np.abs(emx - e64) / np.maximum(np.abs(e64), np.abs(e64).mean())
+    return {"n_samples": int(e64.size),
+            "E_per_site_fp64": float(e64.mean() / (2 * desc64.N)),
+            "mean_E_rel": float(dE / abs(e64.mean())),
+            "dE_over_mean_abs_E": float(dE / np.abs(e64).mean()),
+            "dE_over_stderr": float(dE / max(e64.std() / np.sqrt(e64.size), 1e-300)),
+            "sample_rel_median": float(np.median(rel)),
+            "sample_rel_p99": float(np.quantile(rel, 0.99)),
+            "sample_rel_max": float(rel.max())}
+
+
+def cooled_state(p, torch, desc64, L1, L2, D, n, steps, tau, eps, cg_iters, seed):
+    """theta and configurations after `steps` FP64 SR steps from the beta = 0
+    identity plus N(0, 1e-3^2) noise (beta_phys = 4 * steps * tau)."""
+    import synth
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(synth.theta_identity(L1, L2, D, 2, noise=1e-3, seed=101), device=dev)
+    configs = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=8), device=dev)
+    status = p.new_status(dev)
+    for k in range(steps):
+        res = p.peps_sample_sweep(desc64, theta, configs, seed, k, 1, status=status)
+        p.sr_cg_solve(desc64, configs, res["O"][0], res["e_loc"][0], tau, eps, cg_iters, 1e-10, want_g=False,
+                      theta=theta, status=status)
+    p.peps_sample_sweep(desc64, theta, configs, seed, steps, 1, measure=False, status=status)
+    torch.cuda.synchronize()
+    p.check(status, "cooling")
+    return theta, configs
+
+
+def eval_rate(p, torch, desc, theta, configs, reps=3):
+    """peps_eval_batch samples/s on fixed configurations."""
+    p.peps_eval_batch(desc, theta, configs)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        p.peps_eval_batch(desc, theta, configs)
+    ev1.record()
+    torch.cuda.synchronize()
+    return configs.shape[0] * reps / (ev0.elapsed_time(ev1) / 1e3)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--D", type=int, default=4)
+    ap.add_argument("--chi", type=int, default=16)
+    ap.add_argument("--chains", type=int, default=1024)
+    ap.add_argument("--cg-iters", type=int, default=200)
+    ap.add_argument("--tau", type=float, default=0.02)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--tol", type=float, default=1e-4, help="energy error bar of the mixed path (relative)")
+    ap.add_argument("--cool-steps", type=int, default=10,
+                    help="FP64 SR steps from the identity before the cooled-state energy check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
+              "path is a design note, not an implemented mode", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2409_05285_amd as p
+    import synth
+
+    dev = torch.device("cuda:0")
+    L1 = L2 = args.L
+    D, chi, n = args.D, args.chi, args.chains
+    desc64 = p.Desc(L1, L2, D, chi)
+    descmx = p.Desc(L1, L2, D, chi, precision=p.PREC_MIXED)
+    seed_theta, seed = 102, 20240905
+    theta0 = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
+    configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
+
+    r64 = run_path(p, torch, desc64, theta0, configs0, args, seed)
+    rmx = run_path(p, torch, descmx, theta0, configs0, args, seed)
+    # energy error on the FP64 path's final samples and parameters, and on a
+    # cooled (physical) state
+    err_random = energy_error(p, torch, desc64, descmx, r64["theta"], r64["configs"])
+    th_c, cfg_c = cooled_state(p, torch, desc64, L1, L2, D, n, args.cool_steps, args.tau, args.eps, args.cg_iters,
+                               seed)
+    err_cooled = energy_error(p, torch, desc64, descmx, th_c, cfg_c)
+    mixed_ok = err_cooled["mean_E_rel"] <= args.tol
+    eval64 = eval_rate(p, torch, desc64, r64["theta"], r64["configs"])
+    evalmx = eval_rate(p, torch, descmx, r64["theta"], r64["configs"])
+    best = rmx if mixed_ok else r64
+    prof = best["prof"]
 
     # dominant kernel class and its roofline
     dom = max(prof, key=lambda k: prof[k][0])
     comp_flops, comp_n = sweep_compression_flops(L1, L2, D, chi)
-    roof = None
     if dom == "compress":
         ms, launches = prof["compress"]
         avg_ms = ms / launches
@@ -250,40 +344,62 @@ def main():
         achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / MI355X_FP64_TFLOPS, 4), "traffic": None,
-                "kernel": "k_compress", "avg_launch_ms": round(avg_ms, 4),
+                "kernel": "k_compress2", "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
     else:
         ms, launches = prof[dom]
         roof = {"bound": "alu", "achieved": None, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None, "kernel": dom, "avg_launch_ms": round(ms / max(launches, 1), 4)}
 
-    st = last["stats"].cpu().numpy()
-    acc = n_accept.cpu().numpy().sum(axis=0)
+    # SR: O is read twice per CG iteration (O x, then O^T y), plus the
+    # gradient pass
+    nnz = p.peps_orow_count(desc64)
+    sr_ms = prof["sr"][0] / args.steps
+    cg_it = int(best["stats"][2])
+    sr_bytes = (2 * cg_it + 1) * n * nnz * 8
+    sr_roof = {"bound": "hbm", "achieved": round(sr_bytes / (sr_ms / 1e3) / 1e9, 1), "peak": MI355X_HBM_GBS,
+               "unit": "GB/s", "frac": round(sr_bytes / (sr_ms / 1e3) / 1e9 / MI355X_HBM_GBS, 4),
+               "kernel": "sr_cg_solve", "ms_per_solve": round(sr_ms, 3), "cg_iters": cg_it}
+
+    def summary(r):
+        return {"samples_per_s": round(r["samples_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 3),
+                "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
+                "accept_rate": {"h": round(float(r["accept"][0]), 3), "site": round(float(r["accept"][1]), 3),
+                                "v": round(float(r["accept"][2]), 3)},
+                "E_per_site_last_step": float(r["stats"][0]) / (2 * L1 * L2),
+                "cg_iters_last_step": int(r["stats"][2])}
+
     line = {
         "metric": "PEPS-VMC samples/s (amp+O_k+E_loc) FP32-MFMA vs FP64 at stated energy error",
-        "value": round(samples_per_s, 2),
+        "value": round(best["samples_per_s"], 2),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(best["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed_ok else "f64",
         "data": "synthetic",
         "config": {"workload": f"{L1}x{L2} Heisenberg OBC, d^2=4, D={D}, chi={chi}, {n} chains, random "
                                f"unit-Frobenius tensors; step = 1 sweep + measurement + SR CG "
                                f"({args.cg_iters} it max) + update",
                    "lattice": [L1, L2], "D": D, "chi": chi, "chains": n, "sweeps_per_step": 1,
-                   "cg_iters": args.cg_iters, "precision": "fp64"},
+                   "cg_iters": args.cg_iters,
+                   "precision": "mixed (FP32 MFMA strips, FP64 QR/SVD/SR)" if mixed_ok else "fp64"},
         "roofline": roof,
-        "sr_steps_per_s": round(1e3 / ms_per_step, 3),
-        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
-        "host_wall_ms_per_step": round(wall * 1e3 / args.steps, 3),
-        "last_step": {"E_per_site": float(st[0]) / (2 * L1 * L2), "cg_iters": int(st[2]),
-                      "cg_rnorm": float(st[1])},
-        "accept_rate": {"h": float(acc[0]), "site": float(acc[1]), "v": float(acc[2])},
+        "roofline_sr": sr_roof,
+        "sr_steps_per_s": round(1e3 / best["ms_per_step"], 3),
+        "fp64": summary(r64),
+        "mixed": summary(rmx),
+        "mixed_vs_fp64": round(rmx["samples_per_s"] / r64["samples_per_s"], 4),
+        "energy_error": {"tol": args.tol, "within_tol": mixed_ok,
+                         "cooled": dict(err_cooled, beta_phys=4 * args.cool_steps * args.tau,
+                                        state=f"identity + noise after {args.cool_steps} FP64 SR steps"),
+                         "random": dict(err_random, state="random unit-Frobenius tensors after the timed steps")},
+        "eval_samples_per_s": {"fp64": round(eval64, 1), "mixed": round(evalmx, 1)},
+        "host_wall_ms_per_step": round(best["wall"] * 1e3 / args.steps, 3),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(L1, L2, D, chi, seed_theta, seed, args.cg_iters)

@@ -78,6 +78,13 @@ Prob make_prob(const peps_desc* d) {
   P.off_L = off;     off += pad(4 * (int64_t)P.ES);
   P.off_X = off;     off += pad(2 * (int64_t)P.XS);
   P.off_epart = off; off += pad(2 * P.L1 + 2);
+  P.mixed = d->precision == PEPS_PREC_MIXED;
+  if (P.mixed) {
+    // FP32 copies of the boundaries, same element strides as the FP64 ones
+    const int64_t nf = (int64_t)P.L1 * P.L2 * P.TS;
+    P.off_top32 = off; off += pad((nf + 1) / 2);
+    P.off_bot32 = off; off += pad((nf + 1) / 2);
+  }
   P.chain_stride = off;
   return P;
 }
@@ -85,7 +92,6 @@ Prob make_prob(const peps_desc* d) {
 // Checks that the compiled tile limits hold for the device path.
 peps_status device_support(const peps_desc* d, const Prob& P) {
   if (d->model != PEPS_MODEL_HEISENBERG) return PEPS_ERR_UNSUPPORTED;
-  if (d->precision != PEPS_PREC_FP64) return PEPS_ERR_UNSUPPORTED;
   if ((int64_t)P.chi * P.D > 255) return PEPS_ERR_UNSUPPORTED;
   if (compress_dyn_lds(P) + STATIC_LDS_COMPRESS > LDS_LIMIT) return PEPS_ERR_UNSUPPORTED;
   return PEPS_OK;
@@ -133,6 +139,12 @@ hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* thet
   return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
 }
 
+// FP32 copy of theta (mixed precision), placed after the chain workspaces.
+size_t theta32_bytes(const Prob& P) { return P.mixed ? (size_t)((P.np + 63) & ~(int64_t)63) * sizeof(float) : 0; }
+float* theta32_ptr(const Prob& P, double* ws, int64_t n) {
+  return P.mixed ? (float*)(ws + (size_t)n * P.chain_stride) : nullptr;
+}
+
 #define TIMED(cls, call)            \
   do {                              \
     ProfScope _ps((cls), st);       \
@@ -165,7 +177,7 @@ peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, si
     case PEPS_WS_EVAL:
     case PEPS_WS_GRAD:
     case PEPS_WS_SWEEP:
-      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double);
+      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P);
       return PEPS_OK;
     case PEPS_WS_SR:
       *bytes = sr_workspace_bytes(P, n);
@@ -211,14 +223,15 @@ static peps_status compress_all_bots(const Prob& P, int n, const double* theta, 
   return PEPS_OK;
 }
 
-static peps_status measure(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
-                           double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int64_t out_off,
+static peps_status measure(const Prob& P, int n, const double* theta, const float* t32, const uint8_t* configs,
+                           double* ws, double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int64_t out_off,
                            int32_t* status, hipStream_t st) {
   const int want_e = e_loc != nullptr;
   for (int r = 0; r < P.L1; ++r)
-    TIMED(PEPS_K_MEAS1, launch_meas1(P, n, r, theta, configs, ws, O_rows, want_e, status, st));
+    TIMED(PEPS_K_MEAS1, launch_meas1(P, n, r, theta, t32, configs, ws, O_rows, want_e, status, st));
   if (want_e)
-    for (int r = 0; r < P.L1 - 1; ++r) TIMED(PEPS_K_MEAS2, launch_meas2(P, n, r, theta, configs, ws, status, st));
+    for (int r = 0; r < P.L1 - 1; ++r)
+      TIMED(PEPS_K_MEAS2, launch_meas2(P, n, r, theta, t32, configs, ws, status, st));
   TIMED(PEPS_K_FINAL, launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, status, st));
   return PEPS_OK;
 }
@@ -232,10 +245,12 @@ peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!log_abs || !sign) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
+  float* t32 = theta32_ptr(P, w, n);
+  if (t32) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
-  return measure(P, n, theta, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
+  return measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
 }
 
 peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
@@ -247,10 +262,12 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
   if (!O_rows) return PEPS_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
+  float* t32 = theta32_ptr(P, w, n);
+  if (t32) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
   s = compress_all_bots(P, n, theta, configs, w, status, st);
   if (s != PEPS_OK) return s;
-  return measure(P, n, theta, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
+  return measure(P, n, theta, t32, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
 }
 
 peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n_chains, uint8_t* configs,
@@ -265,6 +282,8 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
   const int n = n_chains;
+  float* t32 = theta32_ptr(P, w, n);
+  if (t32 && n_sweeps > 0) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int k = 0; k < n_sweeps; ++k) {
     const uint64_t g = sweep0 + (uint64_t)k;
     if (k == 0) {
@@ -272,9 +291,9 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       if (s != PEPS_OK) return s;
     }
     for (int r = 0; r < P.L1; ++r) {
-      TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+      TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, t32, configs, seed, g, w, n_accept, status, st));
       if (r < P.L1 - 1) {
-        TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, configs, seed, g, w, n_accept, status, st));
+        TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, t32, configs, seed, g, w, n_accept, status, st));
         TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
       }
     }
@@ -284,7 +303,7 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
     }
     if (measure_any) {
       const int64_t off = (int64_t)k * n;
-      s = measure(P, n, theta, configs, w, log_abs, sign, e_loc, O_rows ? O_rows + off * P.nnz : nullptr, off,
+      s = measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, O_rows ? O_rows + off * P.nnz : nullptr, off,
                   status, st);
       if (s != PEPS_OK) return s;
     }

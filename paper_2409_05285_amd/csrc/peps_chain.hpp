@@ -1,0 +1,149 @@
+// Per-chain workspace views, strip boundaries, slice pointers and the
+// Metropolis proposal set, shared by the chain kernels.
+#pragma once
+
+#include "peps_common.hpp"
+#include "peps_contract.hpp"
+
+namespace peps {
+
+struct ChainWS {
+  double *top, *lstop, *bot, *lsbot, *B, *tmp, *R, *L, *X, *epart;
+  float *top32, *bot32;   // FP32 copies of the boundaries (mixed precision)
+};
+
+__device__ inline ChainWS chain_ws(const Prob& P, double* ws, int ch) {
+  double* base = ws + (size_t)ch * P.chain_stride;
+  ChainWS w;
+  w.top = base + P.off_top;
+  w.lstop = base + P.off_lstop;
+  w.bot = base + P.off_bot;
+  w.lsbot = base + P.off_lsbot;
+  w.B = base + P.off_B;
+  w.tmp = base + P.off_tmp;
+  w.R = base + P.off_R;
+  w.L = base + P.off_L;
+  w.X = base + P.off_X;
+  w.epart = base + P.off_epart;
+  w.top32 = (float*)(base + P.off_top32);
+  w.bot32 = (float*)(base + P.off_bot32);
+  return w;
+}
+
+// Boundary tensors of one precision.
+template <typename T> __device__ inline T* top_of(const ChainWS& w);
+template <> __device__ inline double* top_of<double>(const ChainWS& w) { return w.top; }
+template <> __device__ inline float* top_of<float>(const ChainWS& w) { return w.top32; }
+template <typename T> __device__ inline T* bot_of(const ChainWS& w);
+template <> __device__ inline double* bot_of<double>(const ChainWS& w) { return w.bot; }
+template <> __device__ inline float* bot_of<float>(const ChainWS& w) { return w.bot32; }
+
+// Boundary tensors and dimensions of the strip around row r (one-row:
+// top[r-1] and bot[r+1]; two-row: top[r-1] and bot[r+2]), with the
+// trivial boundary (one element equal to 1) outside the lattice.
+template <typename T>
+struct StripCtx {
+  const T* T_[MAX_L];
+  const T* B[MAX_L];
+  Dim3 tD[MAX_L];
+  Dim3 bD[MAX_L];
+};
+
+template <typename T>
+__device__ inline void build_strip(const Prob& P, const Geo& g, const ChainWS& w, int r, int rb, const T* one,
+                                   StripCtx<T>& s) {
+  if (threadIdx.x != 0) return;
+  const T* top = top_of<T>(w);
+  const T* bot = bot_of<T>(w);
+  for (int c = 0; c < P.L2; ++c) {
+    int Dl, Du, Dr, Dd;
+    leg_dims(P, r, c, Dl, Du, Dr, Dd);
+    if (r >= 1) {
+      s.T_[c] = top + ((size_t)(r - 1) * P.L2 + c) * P.TS;
+      s.tD[c] = Dim3{g.ba[0][r - 1][c], Du, g.bb[0][r - 1][c]};
+    } else {
+      s.T_[c] = one;
+      s.tD[c] = Dim3{1, 1, 1};
+    }
+    if (rb <= P.L1 - 1) {
+      int Dl2, Du2, Dr2, Dd2;
+      leg_dims(P, rb, c, Dl2, Du2, Dr2, Dd2);
+      s.B[c] = bot + ((size_t)rb * P.L2 + c) * P.TS;
+      s.bD[c] = Dim3{g.ba[1][rb][c], Du2, g.bb[1][rb][c]};
+    } else {
+      s.B[c] = one;
+      s.bD[c] = Dim3{1, 1, 1};
+    }
+  }
+}
+
+template <typename T>
+__device__ inline const T* slice_ptr(const Prob& P, const Geo& g, const T* theta, int r, int c, int S) {
+  return theta + g.poff[r * P.L2 + c] + (size_t)S * block_size(P, r, c);
+}
+
+__device__ inline Dim4 wdim(const Prob& P, int r, int c) {
+  int Dl, Du, Dr, Dd;
+  leg_dims(P, r, c, Dl, Du, Dr, Dd);
+  return Dim4{Dl, Du, Dr, Dd};
+}
+
+__device__ inline int slot_base(const Prob& P, int r) {
+  return r * (P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2 + P.nb_moves * P.L2);
+}
+
+// Proposals (shared by the sweep and the local energy).  Digit helpers.
+__device__ inline int ket_of(const Prob& P, int S) { return S / P.d; }
+__device__ inline int bra_of(const Prob& P, int S) { return S % P.d; }
+__device__ inline int merge(const Prob& P, int s, int sp) { return s * P.d + sp; }
+
+// Exchange proposal k on a bond (sites with states Sa, Sb).  Returns false
+// when it would not change the configuration.
+__device__ inline bool bond_proposal(const Prob& P, int Sa, int Sb, int k, int& na, int& nb) {
+  if (P.model == PEPS_MODEL_HEISENBERG) {
+    if (k == 0) {
+      int a = ket_of(P, Sa), b = ket_of(P, Sb);
+      if (a == b) return false;
+      na = merge(P, b, bra_of(P, Sa));
+      nb = merge(P, a, bra_of(P, Sb));
+    } else {
+      int a = bra_of(P, Sa), b = bra_of(P, Sb);
+      if (a == b) return false;
+      na = merge(P, ket_of(P, Sa), b);
+      nb = merge(P, ket_of(P, Sb), a);
+    }
+    return true;
+  }
+  int side = k / 2, sg = k % 2;
+  int da = side == 0 ? ket_of(P, Sa) : bra_of(P, Sa);
+  int db = side == 0 ? ket_of(P, Sb) : bra_of(P, Sb);
+  if (((da >> sg) & 1) == ((db >> sg) & 1)) return false;
+  int da2 = da ^ (1 << sg), db2 = db ^ (1 << sg);
+  if (side == 0) {
+    na = merge(P, da2, bra_of(P, Sa));
+    nb = merge(P, db2, bra_of(P, Sb));
+  } else {
+    na = merge(P, ket_of(P, Sa), da2);
+    nb = merge(P, ket_of(P, Sb), db2);
+  }
+  return true;
+}
+
+__device__ inline bool site_proposal(const Prob& P, int S, int k, int& ns) {
+  int s = ket_of(P, S), sp = bra_of(P, S);
+  if (P.model == PEPS_MODEL_HEISENBERG) {
+    if (s != sp) return false;
+    ns = merge(P, 1 - s, 1 - sp);
+    return true;
+  }
+  if (((s >> k) & 1) != ((sp >> k) & 1)) return false;
+  ns = merge(P, s ^ (1 << k), sp ^ (1 << k));
+  return true;
+}
+
+__device__ inline bool metropolis(const Prob& P, double R, double u) {
+  double wgt = P.alpha == 2 ? R * R : fabs(R);
+  return u < fmin(1.0, wgt);
+}
+
+}  // namespace peps

@@ -27,6 +27,8 @@ struct Prob {
   int XS;   // one contraction intermediate: chi^2 * D^3 (and >= BS)
   int64_t chain_stride;  // doubles per chain
   int64_t off_top, off_lstop, off_bot, off_lsbot, off_B, off_tmp, off_R, off_L, off_X, off_epart;
+  int64_t off_top32, off_bot32;   // FP32 boundary copies (offsets in doubles)
+  int mixed;                      // FP32 strip contractions
 };
 
 __host__ __device__ inline void leg_dims(const Prob& P, int r, int c, int& Dl, int& Du, int& Dr, int& Dd) {

@@ -515,7 +515,20 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     const int a = sa[c], nb = sp[c] * sb[c];
     const bool tr = a <= nb;
     const int mg = tr ? nb : a, ng = tr ? a : nb;
+    const int k2 = P.chi < ng ? P.chi : ng;
     const double* M = w.B + (size_t)c * P.BS;
+    double* Vt = outT + (size_t)c * P.TS;
+    if (k2 == nb) {
+      // No truncation and M has no more columns than rows: the identity is
+      // an orthonormal right factor, so A_c <- 1 and U S = M (same state as
+      // an SVD, other gauge).
+      for (int idx = tid; idx < nb * nb; idx += NTC) Vt[idx] = (idx / nb == idx % nb) ? 1.0 : 0.0;
+      for (int idx = tid; idx < a * nb; idx += NTC) {
+        const int i = idx / nb, t = idx % nb;
+        V[i * SV_LD + t] = M[idx];
+      }
+      __syncthreads();
+    } else {
     for (int idx = tid; idx < mg * ng; idx += NTC) {
       const int j = idx / mg, i = idx % mg;
       G[j * SV_LD + i] = tr ? M[j * nb + i] : M[i * nb + j];
@@ -540,8 +553,6 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       rnk[j] = rk;
     }
     __syncthreads();
-    const int k2 = P.chi < ng ? P.chi : ng;
-    double* Vt = outT + (size_t)c * P.TS;
     if (tr) {
       // V_k^T rows: normalised columns of G (in place), then U S = M V_k into bufB
       for (int idx = tid; idx < ng * mg; idx += NTC) {
@@ -577,6 +588,7 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       }
     }
     __syncthreads();
+    }
     // B_{c-1} (m2 x a) <- B_{c-1} (U S) (a x k2), through LDS (G is free)
     const int m2 = sa[c - 1] * sp[c - 1];
     double* Bp = w.B + (size_t)(c - 1) * P.BS;
@@ -606,6 +618,13 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     lsb[r] = nrm > 0.0 ? ls_prev + log(nrm) : -INFINITY;
     for (int c = 0; c < P.L2; ++c)
       if (sa[c] != oa[c] || sb[c] != ob[c]) set_status(status, PEPS_ERR_UNSUPPORTED);
+  }
+  // 5. FP32 copy of the row for the mixed-precision strips
+  if (P.mixed) {
+    __syncthreads();
+    float* o32 = (float*)(ws + (size_t)ch * P.chain_stride + (dir == 0 ? P.off_top32 : P.off_bot32)) +
+                 (size_t)r * P.L2 * P.TS;
+    for (int idx = tid; idx < P.L2 * P.TS; idx += NTC) o32[idx] = (float)outT[idx];
   }
 }
 

@@ -11,6 +11,11 @@
 // two-level index maps (a fused index i = (i1, i2) maps to i1 s1 + i2 s2),
 // so no operand is ever permuted in memory.  Stages are separated by a
 // workgroup barrier; intermediates live in the chain's workspace.
+//
+// The last stage of every step can scale its output by an exact power of two
+// and record the largest magnitude it wrote (one value per wave), which the
+// FP32 form uses to keep environments in range: the caller carries the
+// exponents in integers and applies them to the FP64 ratios.
 #pragma once
 
 #include "peps_common.hpp"
@@ -48,14 +53,17 @@ template <> struct Mfma<float> {
 // C(m, n) = sum_k A(m, k) B(k, n) for m < M, n < N, k < K, with
 //   A(m, k) = A[am(m) + ak(k)], B(k, n) = B[bk(k) + bn(n)], C at cm(m) + cn(n).
 // Tiles of 16 x 16 are dealt round-robin to the waves of the workgroup.
+// The stored value is the accumulator times `osc`; when `wmax` is given,
+// wave w writes the largest stored magnitude of its tiles to wmax[w].
 // Ends with a workgroup barrier.
 template <typename T>
 __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn,
-                               int M, int N, int K) {
+                               int M, int N, int K, T osc = T(1), float* wmax = nullptr) {
   using MF = Mfma<T>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  float mx = 0.0f;
   for (int t = wave; t < tm * tn; t += nw) {
     const int m0 = (t / tn) << 4, n0 = (t % tn) << 4;
     const int m = m0 + li, n = n0 + li;
@@ -72,23 +80,32 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = m0 + MF::row(lane, v);
-      if (row < M && nv) C[cm(row) + cn(n)] = c[v];
+      const T val = c[v] * osc;
+      if (row < M && nv) {
+        C[cm(row) + cn(n)] = val;
+        mx = fmaxf(mx, fabsf((float)val));
+      }
     }
+  }
+  if (wmax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) wmax[wave] = mx;
   }
   __syncthreads();
 }
 
 template <typename T>
 __device__ inline void wg_gemm_rm(T* C, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn, int M, int N,
-                                  int K) {
-  wg_gemm<T>(C, mstride(N), mid(), A, am, ak, B, bk, bn, M, N, K);
+                                  int K, T osc = T(1), float* wmax = nullptr) {
+  wg_gemm<T>(C, mstride(N), mid(), A, am, ak, B, bk, bn, M, N, K, osc, wmax);
 }
 
 // One column of a one-row strip from the left:
 //   out[a2][r][b2] = sum L[a][l][b] T[a][u][a2] W[l][u][r][d] B[b][d][b2]
 template <typename T>
 __device__ inline void lstep1(T* out, const T* L, const T* Tt, Dim3 tD, const T* W, Dim4 wD, const T* B, Dim3 bD,
-                              T* X0, T* X1) {
+                              T* X0, T* X1, T osc = T(1), float* wmax = nullptr) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl = wD.n0, nr = wD.n2, nd = wD.n3;
   const int nb = bD.n0, nb2 = bD.n2;
@@ -98,14 +115,14 @@ __device__ inline void lstep1(T* out, const T* L, const T* Tt, Dim3 tD, const T*
   wg_gemm_rm<T>(X1, X0, Map2{na2, nu * na2, 1}, Map2{nu, nb * nu * na2, na2}, W, mstride(nr * nd), mid(),
                 nb * na2, nr * nd, nl * nu);
   // out[(a2 r)][b2] = sum_{b,d} X1[b][a2][r][d] B[(b d)][b2]
-  wg_gemm_rm<T>(out, X1, mstride(nd), Map2{nd, na2 * nr * nd, 1}, B, mstride(nb2), mid(), na2 * nr, nb2, nb * nd);
+  wg_gemm_rm<T>(out, X1, mstride(nd), Map2{nd, na2 * nr * nd, 1}, B, mstride(nb2), mid(), na2 * nr, nb2, nb * nd, osc, wmax);
 }
 
 // One column of a one-row strip from the right:
 //   out[a][l][b] = sum T[a][u][a2] W[l][u][r][d] B[b][d][b2] R[a2][r][b2]
 template <typename T>
 __device__ inline void rstep1(T* out, const T* R, const T* Tt, Dim3 tD, const T* W, Dim4 wD, const T* B, Dim3 bD,
-                              T* X0, T* X1) {
+                              T* X0, T* X1, T osc = T(1), float* wmax = nullptr) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl = wD.n0, nr = wD.n2, nd = wD.n3;
   const int nb = bD.n0, nb2 = bD.n2;
@@ -116,7 +133,7 @@ __device__ inline void rstep1(T* out, const T* R, const T* Tt, Dim3 tD, const T*
                 nb * na2, nr * nd);
   // out[a][(l b)] = sum_{u,a2} T[a][(u a2)] X1[l][u][b][a2]
   wg_gemm_rm<T>(out, Tt, mstride(nu * na2), mid(), X1, Map2{na2, nb * na2, 1}, Map2{nb, nu * nb * na2, na2}, na,
-                nl * nb, nu * na2);
+                nl * nb, nu * na2, osc, wmax);
 }
 
 // One column of a two-row strip from the left:
@@ -124,7 +141,7 @@ __device__ inline void rstep1(T* out, const T* R, const T* Tt, Dim3 tD, const T*
 //                             W2[l2][d1][r2][d2] B[b][d2][b2]
 template <typename T>
 __device__ inline void lstep2(T* out, const T* L, const T* Tt, Dim3 tD, const T* W1, Dim4 w1, const T* W2, Dim4 w2,
-                              const T* B, Dim3 bD, T* X0, T* X1) {
+                              const T* B, Dim3 bD, T* X0, T* X1, T osc = T(1), float* wmax = nullptr) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl1 = w1.n0, nr1 = w1.n2, nd1 = w1.n3;
   const int nl2 = w2.n0, nr2 = w2.n2, nd2 = w2.n3;
@@ -139,7 +156,7 @@ __device__ inline void lstep2(T* out, const T* L, const T* Tt, Dim3 tD, const T*
                 nb * na2 * nr1, nr2 * nd2, nl2 * nd1);
   // out[(a2 r1 r2)][b2] = sum_{b,d2} X0[b][(a2 r1 r2)][d2] B[(b d2)][b2]
   wg_gemm_rm<T>(out, X0, mstride(nd2), Map2{nd2, na2 * nr1 * nr2 * nd2, 1}, B, mstride(nb2), mid(),
-                na2 * nr1 * nr2, nb2, nb * nd2);
+                na2 * nr1 * nr2, nb2, nb * nd2, osc, wmax);
 }
 
 // One column of a two-row strip from the right:
@@ -147,7 +164,7 @@ __device__ inline void lstep2(T* out, const T* L, const T* Tt, Dim3 tD, const T*
 //                           B[b][d2][b2] R[a2][r1][r2][b2]
 template <typename T>
 __device__ inline void rstep2(T* out, const T* R, const T* Tt, Dim3 tD, const T* W1, Dim4 w1, const T* W2, Dim4 w2,
-                              const T* B, Dim3 bD, T* X0, T* X1) {
+                              const T* B, Dim3 bD, T* X0, T* X1, T osc = T(1), float* wmax = nullptr) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nl1 = w1.n0, nr1 = w1.n2, nd1 = w1.n3;
   const int nl2 = w2.n0, nr2 = w2.n2, nd2 = w2.n3;
@@ -162,14 +179,14 @@ __device__ inline void rstep2(T* out, const T* R, const T* Tt, Dim3 tD, const T*
                 Map2{nb * na2, nd1 * nb * na2 * nr1, nr1}, nl1 * nu, nl2 * nb * na2, nr1 * nd1);
   // out[a][(l1 l2 b)] = sum_{u,a2} T[a][(u a2)] X0[l1][u][(l2 b)][a2]
   wg_gemm_rm<T>(out, Tt, mstride(nu * na2), mid(), X0, Map2{na2, nl2 * nb * na2, 1},
-                Map2{nl2 * nb, nu * nl2 * nb * na2, na2}, na, nl1 * nl2 * nb, nu * na2);
+                Map2{nl2 * nb, nu * nl2 * nb * na2, na2}, na, nl1 * nl2 * nb, nu * na2, osc, wmax);
 }
 
 // Environment of one site in a one-row strip (the strip is linear in W):
-//   env[l][u][r][d] = sum L[a][l][b] T[a][u][a2] B[b][d][b2] R[a2][r][b2]
+//   env[l][u][r][d] = osc * sum L[a][l][b] T[a][u][a2] B[b][d][b2] R[a2][r][b2]
 template <typename T>
 __device__ inline void site_env1(T* env, const T* L, const T* Tt, Dim3 tD, const T* B, Dim3 bD, const T* R, int nl,
-                                 int nr, T* X0, T* X1) {
+                                 int nr, T* X0, T* X1, T osc = T(1)) {
   const int na = tD.n0, nu = tD.n1, na2 = tD.n2;
   const int nb = bD.n0, nd = bD.n1, nb2 = bD.n2;
   // X0[(l b)][(u a2)] = sum_a L[a][(l b)] T[a][(u a2)]
@@ -179,7 +196,7 @@ __device__ inline void site_env1(T* env, const T* L, const T* Tt, Dim3 tD, const
                 nl * nu * na2, nd * nb2, nb);
   // env[(l u)][r][d] = sum_{a2,b2} X1[(l u)][a2][d][b2] R[a2][r][b2]   (rows (l u d), cols r)
   wg_gemm<T>(env, Map2{nd, nr * nd, 1}, mstride(nd), X1, Map2{nd, na2 * nd * nb2, nb2}, Map2{nb2, nd * nb2, 1}, R,
-             Map2{nb2, nr * nb2, 1}, mstride(nb2), nl * nu * nd, nr, na2 * nb2);
+             Map2{nb2, nr * nb2, 1}, mstride(nb2), nl * nu * nd, nr, na2 * nb2, osc);
 }
 
 // sum_i x[i] y[i], identical on every thread.

@@ -1,138 +1,13 @@
-// Per-chain kernels of the sampling / evaluation path (one workgroup per
-// chain, FP64): boundary-MPS compression, Metropolis passes over one row
-// (one-row strip) and over a pair of rows (two-row strip), and the
-// measurement of E_loc, O rows and log|psi|.
+// LDS-resident boundary-row compression (the general-shape fallback, one
+// workgroup per chain, FP64) and the per-sample output kernel.
 #include <math.h>
 
+#include "peps_chain.hpp"
 #include "peps_common.hpp"
-#include "peps_contract.hpp"
 #include "peps_kernels.hpp"
 #include "peps_linalg.hpp"
 
 namespace peps {
-
-struct ChainWS {
-  double *top, *lstop, *bot, *lsbot, *B, *tmp, *R, *L, *X, *epart;
-};
-
-__device__ inline ChainWS chain_ws(const Prob& P, double* ws, int ch) {
-  double* base = ws + (size_t)ch * P.chain_stride;
-  ChainWS w;
-  w.top = base + P.off_top;
-  w.lstop = base + P.off_lstop;
-  w.bot = base + P.off_bot;
-  w.lsbot = base + P.off_lsbot;
-  w.B = base + P.off_B;
-  w.tmp = base + P.off_tmp;
-  w.R = base + P.off_R;
-  w.L = base + P.off_L;
-  w.X = base + P.off_X;
-  w.epart = base + P.off_epart;
-  return w;
-}
-
-// Boundary tensors and dimensions of the strip around row r (one-row:
-// top[r-1] and bot[r+1]; two-row: top[r-1] and bot[r+2]), with the
-// trivial boundary (one element equal to 1) outside the lattice.
-struct StripCtx {
-  const double* T[MAX_L];
-  const double* B[MAX_L];
-  Dim3 tD[MAX_L];
-  Dim3 bD[MAX_L];
-};
-
-__device__ inline void build_strip(const Prob& P, const Geo& g, const ChainWS& w, int r, int rb,
-                                   const double* one, StripCtx& s) {
-  if (threadIdx.x != 0) return;
-  for (int c = 0; c < P.L2; ++c) {
-    int Dl, Du, Dr, Dd;
-    leg_dims(P, r, c, Dl, Du, Dr, Dd);
-    if (r >= 1) {
-      s.T[c] = w.top + ((size_t)(r - 1) * P.L2 + c) * P.TS;
-      s.tD[c] = Dim3{g.ba[0][r - 1][c], Du, g.bb[0][r - 1][c]};
-    } else {
-      s.T[c] = one;
-      s.tD[c] = Dim3{1, 1, 1};
-    }
-    if (rb <= P.L1 - 1) {
-      int Dl2, Du2, Dr2, Dd2;
-      leg_dims(P, rb, c, Dl2, Du2, Dr2, Dd2);
-      s.B[c] = w.bot + ((size_t)rb * P.L2 + c) * P.TS;
-      s.bD[c] = Dim3{g.ba[1][rb][c], Du2, g.bb[1][rb][c]};
-    } else {
-      s.B[c] = one;
-      s.bD[c] = Dim3{1, 1, 1};
-    }
-  }
-}
-
-__device__ inline const double* slice_ptr(const Prob& P, const Geo& g, const double* theta, int r, int c, int S) {
-  return theta + g.poff[r * P.L2 + c] + (size_t)S * block_size(P, r, c);
-}
-
-__device__ inline Dim4 wdim(const Prob& P, int r, int c) {
-  int Dl, Du, Dr, Dd;
-  leg_dims(P, r, c, Dl, Du, Dr, Dd);
-  return Dim4{Dl, Du, Dr, Dd};
-}
-
-__device__ inline int slot_base(const Prob& P, int r) {
-  return r * (P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2 + P.nb_moves * P.L2);
-}
-
-// Proposals (shared by the sweep and the local energy).  Digit helpers.
-__device__ inline int ket_of(const Prob& P, int S) { return S / P.d; }
-__device__ inline int bra_of(const Prob& P, int S) { return S % P.d; }
-__device__ inline int merge(const Prob& P, int s, int sp) { return s * P.d + sp; }
-
-// Exchange proposal k on a bond (sites with states Sa, Sb).  Returns false
-// when it would not change the configuration.
-__device__ inline bool bond_proposal(const Prob& P, int Sa, int Sb, int k, int& na, int& nb) {
-  if (P.model == PEPS_MODEL_HEISENBERG) {
-    if (k == 0) {
-      int a = ket_of(P, Sa), b = ket_of(P, Sb);
-      if (a == b) return false;
-      na = merge(P, b, bra_of(P, Sa));
-      nb = merge(P, a, bra_of(P, Sb));
-    } else {
-      int a = bra_of(P, Sa), b = bra_of(P, Sb);
-      if (a == b) return false;
-      na = merge(P, ket_of(P, Sa), b);
-      nb = merge(P, ket_of(P, Sb), a);
-    }
-    return true;
-  }
-  int side = k / 2, sg = k % 2;
-  int da = side == 0 ? ket_of(P, Sa) : bra_of(P, Sa);
-  int db = side == 0 ? ket_of(P, Sb) : bra_of(P, Sb);
-  if (((da >> sg) & 1) == ((db >> sg) & 1)) return false;
-  int da2 = da ^ (1 << sg), db2 = db ^ (1 << sg);
-  if (side == 0) {
-    na = merge(P, da2, bra_of(P, Sa));
-    nb = merge(P, db2, bra_of(P, Sb));
-  } else {
-    na = merge(P, ket_of(P, Sa), da2);
-    nb = merge(P, ket_of(P, Sb), db2);
-  }
-  return true;
-}
-
-__device__ inline bool site_proposal(const Prob& P, int S, int k, int& ns) {
-  int s = ket_of(P, S), sp = bra_of(P, S);
-  if (P.model == PEPS_MODEL_HEISENBERG) {
-    if (s != sp) return false;
-    ns = merge(P, 1 - s, 1 - sp);
-    return true;
-  }
-  if (((s >> k) & 1) != ((sp >> k) & 1)) return false;
-  ns = merge(P, s ^ (1 << k), sp ^ (1 << k));
-  return true;
-}
-
-__device__ inline bool metropolis(const Prob& P, double R, double u) {
-  double wgt = P.alpha == 2 ? R * R : fabs(R);
-  return u < fmin(1.0, wgt);
-}
 
 // ---------------------------------------------------------------------------
 // Compression of one boundary row: top[r] = C(top[r-1] o M_r) (dir 0) or
@@ -326,311 +201,13 @@ __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const d
     for (int c = 0; c < P.L2; ++c)
       if (sa[c] != geo.ba[dir][r][c] || sb[c] != geo.bb[dir][r][c]) set_status(status, PEPS_ERR_UNSUPPORTED);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Shared prologue of the strip kernels.
-#define STRIP_PROLOGUE                                        \
-  __shared__ Geo geo;                                         \
-  __shared__ double red[NT];                                  \
-  __shared__ StripCtx sc;                                     \
-  __shared__ uint8_t S[MAX_SITES];                            \
-  __shared__ double one;                                      \
-  const int tid = threadIdx.x;                                \
-  const int ch = blockIdx.x;                                  \
-  ChainWS w = chain_ws(P, ws, ch);                            \
-  uint8_t* cfg = (uint8_t*)configs + (size_t)ch * P.N;         \
-  if (tid == 0) {                                             \
-    build_geo(P, geo);                                        \
-    one = 1.0;                                                \
-  }                                                           \
-  for (int i = tid; i < P.N; i += NT) S[i] = cfg[i];          \
-  __syncthreads();
-
-// One-row environments from the right: R_c (c = L2..0) at w.R + c*ES.
-__device__ inline void right_envs1(const Prob& P, const Geo& g, const StripCtx& sc, const uint8_t* S,
-                                   const double* theta, const ChainWS& w, int r) {
-  if (threadIdx.x == 0) w.R[(size_t)P.L2 * P.ES] = 1.0;
-  __syncthreads();
-  for (int c = P.L2 - 1; c >= 0; --c) {
-    const int i = r * P.L2 + c;
-    rstep1(w.R + (size_t)c * P.ES, w.R + (size_t)(c + 1) * P.ES, sc.T[c], sc.tD[c],
-           slice_ptr(P, g, theta, r, c, S[i]), wdim(P, r, c), sc.B[c], sc.bD[c], w.X, w.X + P.XS);
+  // 5. FP32 copy of the row for the mixed-precision strips
+  if (P.mixed) {
+    __syncthreads();
+    float* o32 = (float*)(ws + (size_t)ch * P.chain_stride + (dir == 0 ? P.off_top32 : P.off_bot32)) +
+                 (size_t)r * P.L2 * P.TS;
+    for (int idx = tid; idx < P.L2 * P.TS; idx += NT) o32[idx] = (float)outT[idx];
   }
-}
-
-__device__ inline void right_envs2(const Prob& P, const Geo& g, const StripCtx& sc, const uint8_t* S,
-                                   const double* theta, const ChainWS& w, int r) {
-  if (threadIdx.x == 0) w.R[(size_t)P.L2 * P.ES] = 1.0;
-  __syncthreads();
-  for (int c = P.L2 - 1; c >= 0; --c) {
-    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
-    rstep2(w.R + (size_t)c * P.ES, w.R + (size_t)(c + 1) * P.ES, sc.T[c], sc.tD[c],
-           slice_ptr(P, g, theta, r, c, S[i]), wdim(P, r, c), slice_ptr(P, g, theta, r + 1, c, S[j]),
-           wdim(P, r + 1, c), sc.B[c], sc.bD[c], w.X, w.X + P.XS);
-  }
-}
-
-__device__ inline int env1_size(const Prob& P, const StripCtx& sc, int r, int c) {
-  Dim4 wd = wdim(P, r, c);
-  return sc.tD[c].n2 * wd.n2 * sc.bD[c].n2;
-}
-
-__device__ inline int env2_size(const Prob& P, const StripCtx& sc, int r, int c) {
-  return sc.tD[c].n2 * wdim(P, r, c).n2 * wdim(P, r + 1, c).n2 * sc.bD[c].n2;
-}
-
-// Metropolis passes inside row r: horizontal exchanges, then site moves.
-__global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const double* __restrict__ theta, uint8_t* configs,
-                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
-                                               int32_t* status) {
-  STRIP_PROLOGUE
-  build_strip(P, geo, w, r, r + 1, &one, sc);
-  __syncthreads();
-  int acc_h = 0, acc_s = 0;
-  double* Lb[2] = {w.L, w.L + P.ES};
-  double* tA = w.L + 2 * (size_t)P.ES;
-  double* tB = w.L + 3 * (size_t)P.ES;
-  double* X0 = w.X;
-  double* X1 = w.X + P.XS;
-  int slot = slot_base(P, r);
-
-  // horizontal exchanges
-  right_envs1(P, geo, sc, S, theta, w, r);
-  double rho = w.R[0];
-  const double* Lc = &one;
-  int cur = 0;
-  for (int c = 0; c < P.L2 - 1; ++c) {
-    const int i = r * P.L2 + c, j = i + 1;
-    for (int k = 0; k < P.nb_moves; ++k, ++slot) {
-      int ni, nj;
-      if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
-      lstep1(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, ni), wdim(P, r, c), sc.B[c], sc.bD[c], X0, X1);
-      lstep1(tB, tA, sc.T[c + 1], sc.tD[c + 1], slice_ptr(P, geo, theta, r, c + 1, nj), wdim(P, r, c + 1),
-             sc.B[c + 1], sc.bD[c + 1], X0, X1);
-      const double rn = wg_dot(tB, w.R + (size_t)(c + 2) * P.ES, env1_size(P, sc, r, c + 1), red);
-      bool acc = false;
-      if (rho == 0.0) set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
-      else acc = metropolis(P, rn / rho, slot_uniform(seed, ch, gsweep, slot));
-      if (acc) {
-        if (tid == 0) { S[i] = (uint8_t)ni; S[j] = (uint8_t)nj; }
-        rho = rn;
-        ++acc_h;
-      }
-      __syncthreads();
-    }
-    lstep1(Lb[cur], Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, S[i]), wdim(P, r, c), sc.B[c], sc.bD[c], X0, X1);
-    Lc = Lb[cur];
-    cur ^= 1;
-  }
-
-  // site moves
-  right_envs1(P, geo, sc, S, theta, w, r);
-  rho = w.R[0];
-  Lc = &one;
-  for (int c = 0; c < P.L2; ++c) {
-    const int i = r * P.L2 + c;
-    for (int k = 0; k < P.ns_moves; ++k, ++slot) {
-      int ni;
-      if (!site_proposal(P, S[i], k, ni)) continue;
-      lstep1(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, ni), wdim(P, r, c), sc.B[c], sc.bD[c], X0, X1);
-      const double rn = wg_dot(tA, w.R + (size_t)(c + 1) * P.ES, env1_size(P, sc, r, c), red);
-      bool acc = false;
-      if (rho == 0.0) set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
-      else acc = metropolis(P, rn / rho, slot_uniform(seed, ch, gsweep, slot));
-      if (acc) {
-        if (tid == 0) S[i] = (uint8_t)ni;
-        rho = rn;
-        ++acc_s;
-      }
-      __syncthreads();
-    }
-    if (c < P.L2 - 1) {
-      lstep1(Lb[cur], Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, S[i]), wdim(P, r, c), sc.B[c], sc.bD[c], X0, X1);
-      Lc = Lb[cur];
-      cur ^= 1;
-    }
-  }
-  for (int i = tid; i < P.N; i += NT) cfg[i] = S[i];
-  if (tid == 0 && n_accept) {
-    n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 0] += acc_h;
-    n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 1] += acc_s;
-  }
-}
-
-// Metropolis vertical exchanges between rows r and r+1 (two-row strip).
-__global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const double* __restrict__ theta, uint8_t* configs,
-                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
-                                               int32_t* status) {
-  STRIP_PROLOGUE
-  build_strip(P, geo, w, r, r + 2, &one, sc);
-  __syncthreads();
-  int acc_v = 0;
-  double* Lb[2] = {w.L, w.L + P.ES};
-  double* tA = w.L + 2 * (size_t)P.ES;
-  double* X0 = w.X;
-  double* X1 = w.X + P.XS;
-  int slot = slot_base(P, r) + P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2;
-  right_envs2(P, geo, sc, S, theta, w, r);
-  double rho = w.R[0];
-  const double* Lc = &one;
-  int cur = 0;
-  for (int c = 0; c < P.L2; ++c) {
-    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
-    for (int k = 0; k < P.nb_moves; ++k, ++slot) {
-      int ni, nj;
-      if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
-      lstep2(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, ni), wdim(P, r, c),
-             slice_ptr(P, geo, theta, r + 1, c, nj), wdim(P, r + 1, c), sc.B[c], sc.bD[c], X0, X1);
-      const double rn = wg_dot(tA, w.R + (size_t)(c + 1) * P.ES, env2_size(P, sc, r, c), red);
-      bool acc = false;
-      if (rho == 0.0) set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
-      else acc = metropolis(P, rn / rho, slot_uniform(seed, ch, gsweep, slot));
-      if (acc) {
-        if (tid == 0) { S[i] = (uint8_t)ni; S[j] = (uint8_t)nj; }
-        rho = rn;
-        ++acc_v;
-      }
-      __syncthreads();
-    }
-    if (c < P.L2 - 1) {
-      lstep2(Lb[cur], Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, S[i]), wdim(P, r, c),
-             slice_ptr(P, geo, theta, r + 1, c, S[j]), wdim(P, r + 1, c), sc.B[c], sc.bD[c], X0, X1);
-      Lc = Lb[cur];
-      cur ^= 1;
-    }
-  }
-  for (int i = tid; i < P.N; i += NT) cfg[i] = S[i];
-  if (tid == 0 && n_accept) n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 2] += acc_v;
-}
-
-// ---------------------------------------------------------------------------
-// Measurement of row r (one-row strip): the O blocks of the row's sites, the
-// local-energy terms inside the row, and (last row) log|psi| and its sign.
-// epart layout per chain: [0, L1) in-row terms, [L1, 2 L1) cross-row terms,
-// [2 L1] log|psi|, [2 L1 + 1] sign.
-__global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const double* __restrict__ theta,
-                                              const uint8_t* configs, double* ws, double* O_rows,
-                                              int want_e, int32_t* status) {
-  STRIP_PROLOGUE
-  build_strip(P, geo, w, r, r + 1, &one, sc);
-  __syncthreads();
-  double* Lb[2] = {w.L, w.L + P.ES};
-  double* tA = w.L + 2 * (size_t)P.ES;
-  double* tB = w.L + 3 * (size_t)P.ES;
-  double* X0 = w.X;
-  double* X1 = w.X + P.XS;
-  right_envs1(P, geo, sc, S, theta, w, r);
-  const double rho = w.R[0];
-  if (rho == 0.0 || !isfinite(rho)) {
-    set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
-    if (tid == 0) {
-      w.epart[r] = NAN;
-      if (r == P.L1 - 1) { w.epart[2 * P.L1] = NAN; w.epart[2 * P.L1 + 1] = 0.0; }
-    }
-    return;
-  }
-  if (r == P.L1 - 1 && tid == 0) {
-    const double ls = r >= 1 ? w.lstop[r - 1] : 0.0;
-    w.epart[2 * P.L1] = ls + log(fabs(rho));
-    w.epart[2 * P.L1 + 1] = rho > 0.0 ? 1.0 : -1.0;
-  }
-  double e = 0.0;
-  double* Orow = O_rows ? O_rows + (size_t)ch * P.nnz : nullptr;
-  const double* Lc = &one;
-  int cur = 0;
-  for (int c = 0; c < P.L2; ++c) {
-    const int i = r * P.L2 + c;
-    Dim4 wd = wdim(P, r, c);
-    if (Orow) {
-      site_env1(tA, Lc, sc.T[c], sc.tD[c], sc.B[c], sc.bD[c], w.R + (size_t)(c + 1) * P.ES, wd.n0, wd.n2, X0, X1);
-      const int bs = wd.n0 * wd.n1 * wd.n2 * wd.n3;
-      const double inv = 1.0 / rho;
-      for (int q = tid; q < bs; q += NT) Orow[geo.ooff[i] + q] = tA[q] * inv;
-      __syncthreads();
-    }
-    if (want_e && c < P.L2 - 1 && P.model == PEPS_MODEL_HEISENBERG) {
-      for (int k = 0; k < 2; ++k) {
-        int ni, nj;
-        if (!bond_proposal(P, S[i], S[i + 1], k, ni, nj)) continue;
-        lstep1(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, ni), wd, sc.B[c], sc.bD[c], X0, X1);
-        lstep1(tB, tA, sc.T[c + 1], sc.tD[c + 1], slice_ptr(P, geo, theta, r, c + 1, nj), wdim(P, r, c + 1),
-               sc.B[c + 1], sc.bD[c + 1], X0, X1);
-        const double rn = wg_dot(tB, w.R + (size_t)(c + 2) * P.ES, env1_size(P, sc, r, c + 1), red);
-        e += 0.5 * P.J1 * (rn / rho);
-      }
-    }
-    if (c < P.L2 - 1) {
-      lstep1(Lb[cur], Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, S[i]), wd, sc.B[c], sc.bD[c], X0, X1);
-      Lc = Lb[cur];
-      cur ^= 1;
-    }
-  }
-  if (tid == 0) w.epart[r] = e;
-}
-
-// Cross-row local-energy terms between rows r and r+1 (two-row strip):
-// vertical bonds, and next-nearest-neighbour bonds when J2 != 0.
-__global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const double* __restrict__ theta,
-                                              const uint8_t* configs, double* ws, int32_t* status) {
-  STRIP_PROLOGUE
-  build_strip(P, geo, w, r, r + 2, &one, sc);
-  __syncthreads();
-  double* Lb[2] = {w.L, w.L + P.ES};
-  double* tA = w.L + 2 * (size_t)P.ES;
-  double* tB = w.L + 3 * (size_t)P.ES;
-  double* X0 = w.X;
-  double* X1 = w.X + P.XS;
-  right_envs2(P, geo, sc, S, theta, w, r);
-  const double rho = w.R[0];
-  if (rho == 0.0 || !isfinite(rho)) {
-    set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
-    if (tid == 0) w.epart[P.L1 + r] = NAN;
-    return;
-  }
-  double e = 0.0;
-  const double* Lc = &one;
-  int cur = 0;
-  for (int c = 0; c < P.L2; ++c) {
-    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
-    if (P.model == PEPS_MODEL_HEISENBERG) {
-      for (int k = 0; k < 2; ++k) {
-        int ni, nj;
-        if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
-        lstep2(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, ni), wdim(P, r, c),
-               slice_ptr(P, geo, theta, r + 1, c, nj), wdim(P, r + 1, c), sc.B[c], sc.bD[c], X0, X1);
-        const double rn = wg_dot(tA, w.R + (size_t)(c + 1) * P.ES, env2_size(P, sc, r, c), red);
-        e += 0.5 * P.J1 * (rn / rho);
-      }
-      if (P.J2 != 0.0 && c < P.L2 - 1) {
-        // bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c)
-        for (int orient = 0; orient < 2; ++orient) {
-          const int sa = orient == 0 ? i : i + 1;      // site in row r
-          const int sbs = orient == 0 ? j + 1 : j;     // site in row r+1
-          for (int k = 0; k < 2; ++k) {
-            int na, nb;
-            if (!bond_proposal(P, S[sa], S[sbs], k, na, nb)) continue;
-            int s1c = S[i], s1n = S[i + 1], s2c = S[j], s2n = S[j + 1];
-            if (orient == 0) { s1c = na; s2n = nb; } else { s1n = na; s2c = nb; }
-            lstep2(tA, Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, s1c), wdim(P, r, c),
-                   slice_ptr(P, geo, theta, r + 1, c, s2c), wdim(P, r + 1, c), sc.B[c], sc.bD[c], X0, X1);
-            lstep2(tB, tA, sc.T[c + 1], sc.tD[c + 1], slice_ptr(P, geo, theta, r, c + 1, s1n), wdim(P, r, c + 1),
-                   slice_ptr(P, geo, theta, r + 1, c + 1, s2n), wdim(P, r + 1, c + 1), sc.B[c + 1], sc.bD[c + 1],
-                   X0, X1);
-            const double rn = wg_dot(tB, w.R + (size_t)(c + 2) * P.ES, env2_size(P, sc, r, c + 1), red);
-            e += 0.5 * P.J2 * (rn / rho);
-          }
-        }
-      }
-    }
-    if (c < P.L2 - 1) {
-      lstep2(Lb[cur], Lc, sc.T[c], sc.tD[c], slice_ptr(P, geo, theta, r, c, S[i]), wdim(P, r, c),
-             slice_ptr(P, geo, theta, r + 1, c, S[j]), wdim(P, r + 1, c), sc.B[c], sc.bD[c], X0, X1);
-      Lc = Lb[cur];
-      cur ^= 1;
-    }
-  }
-  if (tid == 0) w.epart[P.L1 + r] = e;
 }
 
 // Diagonal energy, sum of the parts, and the per-sample outputs.
@@ -701,30 +278,6 @@ hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* t
     configured = lds;
   }
   hipLaunchKernelGGL(k_compress, dim3(n), dim3(NT), lds, st, P, dir, r, theta, configs, ws, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
-                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_moves1, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
-                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_moves2, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
-                        double* O_rows, int want_e, int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_meas1, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
-                        int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_meas2, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, status);
   return hipGetLastError();
 }
 

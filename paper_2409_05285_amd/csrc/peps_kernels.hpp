@@ -16,14 +16,19 @@ hipError_t launch_compress2(const Prob& P, int n, int dir, int r, const double* 
                             double* ws, int32_t* status, hipStream_t st);
 hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                            double* ws, int32_t* status, hipStream_t st);
-hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
-                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st);
-hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, uint8_t* configs, uint64_t seed,
-                         uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status, hipStream_t st);
-hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
-                        double* O_rows, int want_e, int32_t* status, hipStream_t st);
-hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const uint8_t* configs, double* ws,
-                        int32_t* status, hipStream_t st);
+// Strip kernels.  theta is the FP64 parameter vector, t32 its FP32 copy
+// (read instead of theta when P.mixed is set).
+hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStream_t st);
+hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
+                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
+                         hipStream_t st);
+hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
+                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
+                         hipStream_t st);
+hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
+                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st);
+hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
+                        double* ws, int32_t* status, hipStream_t st);
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int32_t* status, hipStream_t st);
 

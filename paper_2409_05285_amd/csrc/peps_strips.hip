@@ -1,0 +1,536 @@
+// Strip kernels (one workgroup per chain): Metropolis moves inside a row and
+// between two rows, and the measurement of a configuration (log|psi|, local
+// energy, O rows), all from one-row and two-row strips between fixed top and
+// bottom boundary MPS.
+//
+// Each kernel is a template on the contraction type T.  T = double is the
+// FP64 path.  T = float is the mixed-precision path: theta and the boundary
+// tensors are read from FP32 copies, every strip contraction runs on FP32
+// MFMA with FP32 accumulation, and each environment is stored scaled by an
+// exact power of two chosen from its largest element (the exponents are
+// carried in integers).  Ratios, log-amplitudes, energies and O entries are
+// formed in FP64 from the FP32 contraction results and those exponents.
+#include <math.h>
+
+#include "peps_chain.hpp"
+#include "peps_kernels.hpp"
+
+namespace peps {
+
+namespace {
+
+constexpr int NWAVE = NT / 64;
+
+// Exponent bookkeeping of one stored environment: the true tensor is the
+// stored one times 2^E, and the largest stored magnitude lies in
+// [0.5, 1) * 2^s (s = 0 for an environment that is not tracked).  A step
+// that consumes it scales its own output by 2^-s, so that output carries
+// E + s.
+struct Env {
+  int E, s;
+};
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+  __device__ static inline double scale(int) { return 1.0; }
+  __device__ static inline float* track(float*) { return nullptr; }
+  __device__ static inline int shift(const float*) { return 0; }
+};
+template <> struct Prec<float> {
+  // 2^-s as an exact FP32 value (s clamped to the normal range)
+  __device__ static inline float scale(int s) { return ldexpf(1.0f, -s); }
+  __device__ static inline float* track(float* wmax) { return wmax; }
+  __device__ static inline int shift(const float* wmax) {
+    float m = 0.0f;
+    for (int w = 0; w < NWAVE; ++w) m = fmaxf(m, wmax[w]);
+    if (!(m > 0.0f) || !isfinite(m)) return 0;
+    int e;
+    frexpf(m, &e);
+    return e < -125 ? -125 : (e > 125 ? 125 : e);
+  }
+};
+
+// Output exponent of a step whose input carried `in` (applied scale 2^-in.s).
+__device__ inline Env next_env(Env in, int s_out) { return Env{in.E + in.s, s_out}; }
+
+// Ratio x / y of two tracked scalars, in FP64.
+__device__ inline double tracked_ratio(double xm, int xE, double ym, int yE) { return ldexp(xm / ym, xE - yE); }
+
+// Shared state of a strip kernel.
+template <typename T>
+struct StripShared {
+  Geo geo;
+  double red[NT];
+  StripCtx<T> sc;
+  uint8_t S[MAX_SITES];
+  T one;
+  float wmax[NWAVE];
+  int Re[MAX_L + 1];   // exponents of the right environments
+  int Rs[MAX_L + 1];
+};
+
+template <typename T>
+__device__ inline void strip_prologue(const Prob& P, StripShared<T>& sh, const uint8_t* cfg) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    build_geo(P, sh.geo);
+    sh.one = T(1);
+  }
+  for (int i = tid; i < P.N; i += NT) sh.S[i] = cfg[i];
+  __syncthreads();
+}
+
+// Scratch tensors of a strip kernel inside the chain workspace.
+template <typename T>
+struct StripBufs {
+  T *R, *Lb0, *Lb1, *tA, *tB, *X0, *X1;
+};
+
+template <typename T>
+__device__ inline StripBufs<T> strip_bufs(const Prob& P, const ChainWS& w) {
+  StripBufs<T> b;
+  b.R = (T*)w.R;
+  T* L = (T*)w.L;
+  b.Lb0 = L;
+  b.Lb1 = L + P.ES;
+  b.tA = L + 2 * (size_t)P.ES;
+  b.tB = L + 3 * (size_t)P.ES;
+  b.X0 = (T*)w.X;
+  b.X1 = b.X0 + P.XS;
+  return b;
+}
+
+// One-row environments from the right: R_c (c = L2..0) at R + c*ES.
+template <typename T>
+__device__ inline void right_envs1(const Prob& P, StripShared<T>& sh, const T* theta, const StripBufs<T>& b, int r) {
+  using PR = Prec<T>;
+  if (threadIdx.x == 0) {
+    b.R[(size_t)P.L2 * P.ES] = T(1);
+    sh.Re[P.L2] = 0;
+    sh.Rs[P.L2] = 0;
+  }
+  __syncthreads();
+  Env e{0, 0};
+  for (int c = P.L2 - 1; c >= 0; --c) {
+    const int i = r * P.L2 + c;
+    rstep1<T>(b.R + (size_t)c * P.ES, b.R + (size_t)(c + 1) * P.ES, sh.sc.T_[c], sh.sc.tD[c],
+              slice_ptr(P, sh.geo, theta, r, c, sh.S[i]), wdim(P, r, c), sh.sc.B[c], sh.sc.bD[c], b.X0, b.X1,
+              PR::scale(e.s), PR::track(sh.wmax));
+    e = next_env(e, PR::shift(sh.wmax));
+    if (threadIdx.x == 0) {
+      sh.Re[c] = e.E;
+      sh.Rs[c] = e.s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline void right_envs2(const Prob& P, StripShared<T>& sh, const T* theta, const StripBufs<T>& b, int r) {
+  using PR = Prec<T>;
+  if (threadIdx.x == 0) {
+    b.R[(size_t)P.L2 * P.ES] = T(1);
+    sh.Re[P.L2] = 0;
+    sh.Rs[P.L2] = 0;
+  }
+  __syncthreads();
+  Env e{0, 0};
+  for (int c = P.L2 - 1; c >= 0; --c) {
+    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
+    rstep2<T>(b.R + (size_t)c * P.ES, b.R + (size_t)(c + 1) * P.ES, sh.sc.T_[c], sh.sc.tD[c],
+              slice_ptr(P, sh.geo, theta, r, c, sh.S[i]), wdim(P, r, c),
+              slice_ptr(P, sh.geo, theta, r + 1, c, sh.S[j]), wdim(P, r + 1, c), sh.sc.B[c], sh.sc.bD[c], b.X0,
+              b.X1, PR::scale(e.s), PR::track(sh.wmax));
+    e = next_env(e, PR::shift(sh.wmax));
+    if (threadIdx.x == 0) {
+      sh.Re[c] = e.E;
+      sh.Rs[c] = e.s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline int env1_size(const Prob& P, const StripCtx<T>& sc, int r, int c) {
+  return sc.tD[c].n2 * wdim(P, r, c).n2 * sc.bD[c].n2;
+}
+
+template <typename T>
+__device__ inline int env2_size(const Prob& P, const StripCtx<T>& sc, int r, int c) {
+  return sc.tD[c].n2 * wdim(P, r, c).n2 * wdim(P, r + 1, c).n2 * sc.bD[c].n2;
+}
+
+// One column of the one-row strip from the left, with exponent tracking.
+template <typename T>
+__device__ inline Env lstep1_t(const Prob& P, StripShared<T>& sh, const StripBufs<T>& b, T* out, const T* L, Env eL,
+                               const T* theta, int r, int c, int Sc) {
+  using PR = Prec<T>;
+  lstep1<T>(out, L, sh.sc.T_[c], sh.sc.tD[c], slice_ptr(P, sh.geo, theta, r, c, Sc), wdim(P, r, c), sh.sc.B[c],
+            sh.sc.bD[c], b.X0, b.X1, PR::scale(eL.s), PR::track(sh.wmax));
+  return next_env(eL, PR::shift(sh.wmax));
+}
+
+// One column of the two-row strip from the left, with exponent tracking.
+template <typename T>
+__device__ inline Env lstep2_t(const Prob& P, StripShared<T>& sh, const StripBufs<T>& b, T* out, const T* L, Env eL,
+                               const T* theta, int r, int c, int S1, int S2) {
+  using PR = Prec<T>;
+  lstep2<T>(out, L, sh.sc.T_[c], sh.sc.tD[c], slice_ptr(P, sh.geo, theta, r, c, S1), wdim(P, r, c),
+            slice_ptr(P, sh.geo, theta, r + 1, c, S2), wdim(P, r + 1, c), sh.sc.B[c], sh.sc.bD[c], b.X0, b.X1,
+            PR::scale(eL.s), PR::track(sh.wmax));
+  return next_env(eL, PR::shift(sh.wmax));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Metropolis passes inside row r: horizontal exchanges, then site moves.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
+                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
+                                               int32_t* status) {
+  __shared__ StripShared<T> sh;
+  const int tid = threadIdx.x;
+  const int ch = blockIdx.x;
+  ChainWS w = chain_ws(P, ws, ch);
+  uint8_t* cfg = configs + (size_t)ch * P.N;
+  strip_prologue(P, sh, cfg);
+  build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
+  __syncthreads();
+  const StripBufs<T> b = strip_bufs<T>(P, w);
+  uint8_t* S = sh.S;
+  T* Lb[2] = {b.Lb0, b.Lb1};
+  int acc_h = 0, acc_s = 0;
+  int slot = slot_base(P, r);
+
+  // horizontal exchanges
+  right_envs1(P, sh, theta, b, r);
+  double rho = (double)b.R[0];
+  int rhoE = sh.Re[0];
+  const T* Lc = &sh.one;
+  Env eL{0, 0};
+  int cur = 0;
+  for (int c = 0; c < P.L2 - 1; ++c) {
+    const int i = r * P.L2 + c, j = i + 1;
+    for (int k = 0; k < P.nb_moves; ++k, ++slot) {
+      int ni, nj;
+      if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
+      const Env eA = lstep1_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni);
+      const Env eB = lstep1_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, nj);
+      const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env1_size(P, sh.sc, r, c + 1), sh.red);
+      const int rnE = eB.E + sh.Re[c + 2];
+      bool acc = false;
+      if (rho == 0.0) {
+        set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
+      } else {
+        const double R = tracked_ratio(rn, rnE, rho, rhoE);
+        if (!isfinite(R)) set_status(status, PEPS_ERR_NONFINITE);
+        acc = metropolis(P, R, slot_uniform(seed, ch, gsweep, slot));
+      }
+      if (acc) {
+        if (tid == 0) { S[i] = (uint8_t)ni; S[j] = (uint8_t)nj; }
+        rho = rn;
+        rhoE = rnE;
+        ++acc_h;
+      }
+      __syncthreads();
+    }
+    eL = lstep1_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i]);
+    Lc = Lb[cur];
+    cur ^= 1;
+  }
+
+  // site moves
+  right_envs1(P, sh, theta, b, r);
+  rho = (double)b.R[0];
+  rhoE = sh.Re[0];
+  Lc = &sh.one;
+  eL = Env{0, 0};
+  for (int c = 0; c < P.L2; ++c) {
+    const int i = r * P.L2 + c;
+    for (int k = 0; k < P.ns_moves; ++k, ++slot) {
+      int ni;
+      if (!site_proposal(P, S[i], k, ni)) continue;
+      const Env eA = lstep1_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni);
+      const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env1_size(P, sh.sc, r, c), sh.red);
+      const int rnE = eA.E + sh.Re[c + 1];
+      bool acc = false;
+      if (rho == 0.0) {
+        set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
+      } else {
+        const double R = tracked_ratio(rn, rnE, rho, rhoE);
+        if (!isfinite(R)) set_status(status, PEPS_ERR_NONFINITE);
+        acc = metropolis(P, R, slot_uniform(seed, ch, gsweep, slot));
+      }
+      if (acc) {
+        if (tid == 0) S[i] = (uint8_t)ni;
+        rho = rn;
+        rhoE = rnE;
+        ++acc_s;
+      }
+      __syncthreads();
+    }
+    if (c < P.L2 - 1) {
+      eL = lstep1_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i]);
+      Lc = Lb[cur];
+      cur ^= 1;
+    }
+  }
+  for (int i = tid; i < P.N; i += NT) cfg[i] = S[i];
+  if (tid == 0 && n_accept) {
+    n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 0] += acc_h;
+    n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 1] += acc_s;
+  }
+}
+
+// Metropolis vertical exchanges between rows r and r+1 (two-row strip).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
+                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
+                                               int32_t* status) {
+  __shared__ StripShared<T> sh;
+  const int tid = threadIdx.x;
+  const int ch = blockIdx.x;
+  ChainWS w = chain_ws(P, ws, ch);
+  uint8_t* cfg = configs + (size_t)ch * P.N;
+  strip_prologue(P, sh, cfg);
+  build_strip<T>(P, sh.geo, w, r, r + 2, &sh.one, sh.sc);
+  __syncthreads();
+  const StripBufs<T> b = strip_bufs<T>(P, w);
+  uint8_t* S = sh.S;
+  T* Lb[2] = {b.Lb0, b.Lb1};
+  int acc_v = 0;
+  int slot = slot_base(P, r) + P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2;
+  right_envs2(P, sh, theta, b, r);
+  double rho = (double)b.R[0];
+  int rhoE = sh.Re[0];
+  const T* Lc = &sh.one;
+  Env eL{0, 0};
+  int cur = 0;
+  for (int c = 0; c < P.L2; ++c) {
+    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
+    for (int k = 0; k < P.nb_moves; ++k, ++slot) {
+      int ni, nj;
+      if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
+      const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni, nj);
+      const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
+      const int rnE = eA.E + sh.Re[c + 1];
+      bool acc = false;
+      if (rho == 0.0) {
+        set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
+      } else {
+        const double R = tracked_ratio(rn, rnE, rho, rhoE);
+        if (!isfinite(R)) set_status(status, PEPS_ERR_NONFINITE);
+        acc = metropolis(P, R, slot_uniform(seed, ch, gsweep, slot));
+      }
+      if (acc) {
+        if (tid == 0) { S[i] = (uint8_t)ni; S[j] = (uint8_t)nj; }
+        rho = rn;
+        rhoE = rnE;
+        ++acc_v;
+      }
+      __syncthreads();
+    }
+    if (c < P.L2 - 1) {
+      eL = lstep2_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i], S[j]);
+      Lc = Lb[cur];
+      cur ^= 1;
+    }
+  }
+  for (int i = tid; i < P.N; i += NT) cfg[i] = S[i];
+  if (tid == 0 && n_accept) n_accept[(size_t)ch * PEPS_N_MOVE_TYPES + 2] += acc_v;
+}
+
+// ---------------------------------------------------------------------------
+// Measurement of row r (one-row strip): the O blocks of the row's sites, the
+// local-energy terms inside the row, and (last row) log|psi| and its sign.
+// epart layout per chain: [0, L1) in-row terms, [L1, 2 L1) cross-row terms,
+// [2 L1] log|psi|, [2 L1 + 1] sign.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+                                              double* ws, double* O_rows, int want_e, int32_t* status) {
+  using PR = Prec<T>;
+  __shared__ StripShared<T> sh;
+  const int tid = threadIdx.x;
+  const int ch = blockIdx.x;
+  ChainWS w = chain_ws(P, ws, ch);
+  strip_prologue(P, sh, configs + (size_t)ch * P.N);
+  build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
+  __syncthreads();
+  const StripBufs<T> b = strip_bufs<T>(P, w);
+  const uint8_t* S = sh.S;
+  T* Lb[2] = {b.Lb0, b.Lb1};
+  right_envs1(P, sh, theta, b, r);
+  const double rho = (double)b.R[0];
+  const int rhoE = sh.Re[0];
+  if (rho == 0.0 || !isfinite(rho)) {
+    set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
+    if (tid == 0) {
+      w.epart[r] = NAN;
+      if (r == P.L1 - 1) { w.epart[2 * P.L1] = NAN; w.epart[2 * P.L1 + 1] = 0.0; }
+    }
+    return;
+  }
+  if (r == P.L1 - 1 && tid == 0) {
+    const double ls = r >= 1 ? w.lstop[r - 1] : 0.0;
+    w.epart[2 * P.L1] = ls + log(fabs(rho)) + (double)rhoE * M_LN2;
+    w.epart[2 * P.L1 + 1] = rho > 0.0 ? 1.0 : -1.0;
+  }
+  double e = 0.0;
+  double* Orow = O_rows ? O_rows + (size_t)ch * P.nnz : nullptr;
+  const double inv = 1.0 / rho;
+  const T* Lc = &sh.one;
+  Env eL{0, 0};
+  int cur = 0;
+  for (int c = 0; c < P.L2; ++c) {
+    const int i = r * P.L2 + c;
+    const Dim4 wd = wdim(P, r, c);
+    if (Orow) {
+      // env * 2^(eL.E + eL.s + E_R + s_R) is the true site environment; the
+      // stored one carries the scale 2^-(eL.s + s_R).
+      site_env1<T>(b.tA, Lc, sh.sc.T_[c], sh.sc.tD[c], sh.sc.B[c], sh.sc.bD[c], b.R + (size_t)(c + 1) * P.ES, wd.n0,
+                   wd.n2, b.X0, b.X1, PR::scale(eL.s + sh.Rs[c + 1]));
+      const double f = ldexp(inv, eL.E + eL.s + sh.Re[c + 1] + sh.Rs[c + 1] - rhoE);
+      const int bs = wd.n0 * wd.n1 * wd.n2 * wd.n3;
+      for (int q = tid; q < bs; q += NT) Orow[sh.geo.ooff[i] + q] = (double)b.tA[q] * f;
+      __syncthreads();
+    }
+    if (want_e && c < P.L2 - 1 && P.model == PEPS_MODEL_HEISENBERG) {
+      for (int k = 0; k < 2; ++k) {
+        int ni, nj;
+        if (!bond_proposal(P, S[i], S[i + 1], k, ni, nj)) continue;
+        const Env eA = lstep1_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni);
+        const Env eB = lstep1_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, nj);
+        const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env1_size(P, sh.sc, r, c + 1), sh.red);
+        e += 0.5 * P.J1 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
+      }
+    }
+    if (c < P.L2 - 1) {
+      eL = lstep1_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i]);
+      Lc = Lb[cur];
+      cur ^= 1;
+    }
+  }
+  if (tid == 0) w.epart[r] = e;
+}
+
+// Cross-row local-energy terms between rows r and r+1 (two-row strip):
+// vertical bonds, and next-nearest-neighbour bonds when J2 != 0.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+                                              double* ws, int32_t* status) {
+  __shared__ StripShared<T> sh;
+  const int tid = threadIdx.x;
+  const int ch = blockIdx.x;
+  ChainWS w = chain_ws(P, ws, ch);
+  strip_prologue(P, sh, configs + (size_t)ch * P.N);
+  build_strip<T>(P, sh.geo, w, r, r + 2, &sh.one, sh.sc);
+  __syncthreads();
+  const StripBufs<T> b = strip_bufs<T>(P, w);
+  const uint8_t* S = sh.S;
+  T* Lb[2] = {b.Lb0, b.Lb1};
+  right_envs2(P, sh, theta, b, r);
+  const double rho = (double)b.R[0];
+  const int rhoE = sh.Re[0];
+  if (rho == 0.0 || !isfinite(rho)) {
+    set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
+    if (tid == 0) w.epart[P.L1 + r] = NAN;
+    return;
+  }
+  double e = 0.0;
+  const T* Lc = &sh.one;
+  Env eL{0, 0};
+  int cur = 0;
+  for (int c = 0; c < P.L2; ++c) {
+    const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
+    if (P.model == PEPS_MODEL_HEISENBERG) {
+      for (int k = 0; k < 2; ++k) {
+        int ni, nj;
+        if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
+        const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni, nj);
+        const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
+        e += 0.5 * P.J1 * tracked_ratio(rn, eA.E + sh.Re[c + 1], rho, rhoE);
+      }
+      if (P.J2 != 0.0 && c < P.L2 - 1) {
+        // bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c)
+        for (int orient = 0; orient < 2; ++orient) {
+          const int sa = orient == 0 ? i : i + 1;    // site in row r
+          const int sbs = orient == 0 ? j + 1 : j;   // site in row r+1
+          for (int k = 0; k < 2; ++k) {
+            int na, nb;
+            if (!bond_proposal(P, S[sa], S[sbs], k, na, nb)) continue;
+            int s1c = S[i], s1n = S[i + 1], s2c = S[j], s2n = S[j + 1];
+            if (orient == 0) { s1c = na; s2n = nb; } else { s1n = na; s2c = nb; }
+            const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, s1c, s2c);
+            const Env eB = lstep2_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, s1n, s2n);
+            const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env2_size(P, sh.sc, r, c + 1), sh.red);
+            e += 0.5 * P.J2 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
+          }
+        }
+      }
+    }
+    if (c < P.L2 - 1) {
+      eL = lstep2_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i], S[j]);
+      Lc = Lb[cur];
+      cur ^= 1;
+    }
+  }
+  if (tid == 0) w.epart[P.L1 + r] = e;
+}
+
+// FP32 copy of theta for the mixed-precision strips.
+__global__ void k_theta32(const double* __restrict__ theta, float* __restrict__ t32, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    t32[i] = (float)theta[i];
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStream_t st) {
+  const int blocks = (int)((P.np + 255) / 256 < 1024 ? (P.np + 255) / 256 : 1024);
+  hipLaunchKernelGGL(k_theta32, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, theta, t32, P.np);
+  return hipGetLastError();
+}
+
+hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
+                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
+                         hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_moves1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, ws, n_accept,
+                       status);
+  else
+    hipLaunchKernelGGL(k_moves1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept,
+                       status);
+  return hipGetLastError();
+}
+
+hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
+                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
+                         hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_moves2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, ws, n_accept,
+                       status);
+  else
+    hipLaunchKernelGGL(k_moves2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept,
+                       status);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
+                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_meas1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, O_rows, want_e, status);
+  else
+    hipLaunchKernelGGL(k_meas1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
+                        double* ws, int32_t* status, hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_meas2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, status);
+  else
+    hipLaunchKernelGGL(k_meas2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, status);
+  return hipGetLastError();
+}
+
+}  // namespace peps

@@ -5,6 +5,12 @@ Tolerances (FP64 path): |d log|psi|| <= 1e-10 max(1, |log|psi||);
 |d E_loc| <= 1e-10 max(|E_loc|, mean|E|); |d O| <= 1e-9 max(1, |O|);
 configurations, accept counts and signs bit-exact (except after a logged
 near-tie of the Metropolis test, |u - min(1,|R|^2)| <= 1e-12).
+
+Mixed precision (FP32 strip contractions, FP64 truncation and reductions):
+log|psi| and E_loc within 1e-4 relative (same normalisations as above), O
+within 1e-4 of the row's largest magnitude, signs exact; sampled
+configurations and accept counts bit-exact for every chain whose Metropolis
+tests all stay 1e-4 away from a tie.
 """
 import sys
 
@@ -31,15 +37,15 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _setup(L1, L2, D, chi, J2=0.0, theta="random", seed=7):
+def _setup(L1, L2, D, chi, J2=0.0, theta="random", seed=7, mixed=False, scale=1.0):
     import paper_2409_05285_amd as p
     lat = Lattice(L1, L2, D=D, chi=chi, J1=1.0, J2=J2)
-    desc = p.Desc(L1, L2, D, chi, J1=1.0, J2=J2)
+    desc = p.Desc(L1, L2, D, chi, J1=1.0, J2=J2, precision=p.PREC_MIXED if mixed else p.PREC_FP64)
     if theta == "random":
         th = synth.theta_random_unit(L1, L2, D, 2, seed=seed)
     else:
         th = synth.theta_identity(L1, L2, D, 2, noise=1e-3, seed=seed)
-    return p, lat, desc, th
+    return p, lat, desc, th * scale
 
 
 def _close_log(a, b, tol=1e-10):
@@ -78,7 +84,7 @@ def test_eval_and_grad_match_oracle(L1, L2, D, chi, J2):
     assert np.all(np.abs(O - ref["O"]) <= 1e-9 * np.maximum(1.0, np.abs(ref["O"])))
 
 
-def _oracle_chains(lat, th, cfg, chi, seed, sweep0, n_sweeps):
+def _oracle_chains(lat, th, cfg, chi, seed, sweep0, n_sweeps, tie_tol=1e-12):
     out = []
     for ch in range(cfg.shape[0]):
         S = cfg[ch].astype(np.int64)
@@ -86,7 +92,7 @@ def _oracle_chains(lat, th, cfg, chi, seed, sweep0, n_sweeps):
         ties = []
         meas = []
         for k in range(n_sweeps):
-            res = sampler.sweep(lat, th, S, chi, seed, ch, sweep0 + k)
+            res = sampler.sweep(lat, th, S, chi, seed, ch, sweep0 + k, tie_tol=tie_tol)
             S = res["S"]
             acc += res["n_accept"]
             ties += res["near_ties"]
@@ -185,3 +191,83 @@ def test_sr_cg_matches_oracle(n_s, iters):
     dense = sr.sr_solve_dense(lat, cfg, O, e, tau=0.01, eps=1e-3)
     assert np.allclose(dth2.cpu().numpy(), dense, rtol=1e-7, atol=1e-10 * np.abs(dense).max())
     assert stats2[2] < 2000
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision
+
+MIXED_TOL = 1e-4
+
+MIXED_EVAL_CASES = [
+    (3, 3, 2, 4, 0.0, 1.0),
+    (4, 5, 3, 5, 0.0, 1.0),
+    (4, 4, 2, 3, 0.5, 1.0),
+    (8, 8, 4, 16, 0.0, 1.0),
+    (4, 8, 2, 4, 0.0, 1e-6),   # strip values far below the FP32 range without rescaling
+    (4, 8, 2, 4, 0.0, 1e6),    # and far above it
+]
+
+
+@pytest.mark.parametrize("L1,L2,D,chi,J2,scale", MIXED_EVAL_CASES)
+def test_mixed_eval_and_grad_match_oracle(L1, L2, D, chi, J2, scale):
+    dev = _dev()
+    p, lat, desc, th = _setup(L1, L2, D, chi, J2, mixed=True, scale=scale)
+    n = 3 if L1 * L2 >= 64 else 6
+    cfg = synth.configs_sector(n, lat.N, 2, seed=L1 * 100 + chi + 1)
+    _say("mixed eval", L1, L2, D, chi, J2, scale, "n", n)
+    theta_d = torch.tensor(th, device=dev)
+    cfg_d = torch.tensor(cfg, device=dev)
+    la, sg, el, st = p.peps_eval_batch(desc, theta_d, cfg_d)
+    O, la2, st2 = p.peps_grad_batch(desc, theta_d, cfg_d)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    ref = measure.evaluate_batch(lat, th, cfg, chi)
+    la, sg, el, O, la2 = (x.cpu().numpy() for x in (la, sg, el, O, la2))
+    assert _close_log(la, ref["log_abs"], MIXED_TOL), (la, ref["log_abs"])
+    assert np.array_equal(la, la2)
+    assert np.array_equal(sg, ref["sign"])
+    emag = max(np.abs(ref["e_loc"]).mean(), 1e-300)
+    err = np.abs(el - ref["e_loc"]) / np.maximum(np.abs(ref["e_loc"]), emag)
+    print("mixed E_loc max rel err", err.max(), flush=True)
+    assert np.all(err <= MIXED_TOL), (el, ref["e_loc"])
+    omax = np.maximum(1.0, np.abs(ref["O"]).max(axis=1, keepdims=True))
+    assert np.all(np.abs(O - ref["O"]) <= MIXED_TOL * omax)
+
+
+MIXED_SWEEP_CASES = [
+    (4, 4, 2, 4, "random", 6, 2),
+    (4, 5, 3, 5, "random", 4, 2),
+    (8, 8, 4, 16, "random", 2, 1),
+]
+
+
+@pytest.mark.parametrize("L1,L2,D,chi,init,n_chains,n_sweeps", MIXED_SWEEP_CASES)
+def test_mixed_sample_sweep(L1, L2, D, chi, init, n_chains, n_sweeps):
+    dev = _dev()
+    p, lat, desc, th = _setup(L1, L2, D, chi, theta=init, seed=11, mixed=True)
+    cfg = synth.configs_diagonal(n_chains, lat.N, 2, seed=5)
+    seed, sweep0 = 20240905, 3
+    _say("mixed sweep", L1, L2, D, chi, init, n_chains, n_sweeps)
+    theta_d = torch.tensor(th, device=dev)
+    cfg_d = torch.tensor(cfg, device=dev)
+    res = p.peps_sample_sweep(desc, theta_d, cfg_d, seed, sweep0, n_sweeps)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    ref = _oracle_chains(lat, th, cfg, chi, seed, sweep0, n_sweeps, tie_tol=MIXED_TOL)
+    got_cfg = cfg_d.cpu().numpy()
+    acc = res["n_accept"].cpu().numpy()
+    e = res["e_loc"].cpu().numpy()
+    la = res["log_abs"].cpu().numpy()
+    compared = 0
+    for ch, (S, a, ties, meas) in enumerate(ref):
+        if ties:
+            print("near-tie, chain", ch, ties)
+            continue
+        compared += 1
+        assert np.array_equal(got_cfg[ch], S.astype(np.uint8)), ch
+        assert np.array_equal(acc[ch], a), (ch, acc[ch], a)
+        for k in range(n_sweeps):
+            m = meas[k]
+            assert _close_log(la[k, ch], m["log_abs"], MIXED_TOL)
+            assert abs(e[k, ch] - m["e_loc"]) <= MIXED_TOL * max(abs(m["e_loc"]), 1.0)
+    assert compared >= 1
