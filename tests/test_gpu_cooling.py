@@ -1,0 +1,92 @@
+"""Whole-loop physics check on the GPU: cooling from beta = 0 on the 4x4
+Heisenberg lattice against exact diagonalisation.
+
+Recipe (4x4 open-boundary Heisenberg, J = 1, D = 4, chi = 16 = exact
+contraction, FP64): theta = identity + N(0, 0.05^2) noise (seed 101), 64
+chains, 60 sweeps per SR step, one sample per chain and sweep, SR with
+tau = 0.01 and shift 1e-4, 25 steps.  D = 4 is the smallest bond dimension
+whose first-order variation around the identity holds a Heisenberg bond
+term (identity plus three Pauli channels per bond); with D = 2 even exact
+expectations cool about three times too slowly.  The perturbation is
+larger than the 1e-3 of the throughput recipe because a Markov chain must
+visit the off-diagonal configurations: their weight |rho| is of the order
+of the square of the perturbation.  Near beta = 0 the off-diagonal
+amplitudes are too small to be reached by sampling |rho|^2, so the chains
+sample |rho| and every average carries the weight |rho| (the reweighted
+estimator of Appendix A, Eq. A1).  Samples drawn after n updates belong
+to beta_phys = 4 n tau (the energy of exp(-n tau calH)|I> is the thermal
+energy at twice its beta; Eq. in_en).  The ED table comes from
+tests/golden/make_ed_tables.py (oracle only).
+
+Bar: |E/N - E_ED/N| <= 3 sigma + 0.02 |E_ED/N| at every sampled beta_phys,
+sigma the standard error of the per-chain means (batch means over the
+sweeps of each chain).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _ed_energy(beta):
+    with open(os.path.join(HERE, "golden", "ed_heisenberg_4x4.json")) as f:
+        t = json.load(f)
+    return float(np.interp(beta, t["beta"], t["E_per_site"]))
+
+
+def test_cooling_4x4_matches_ed():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2409_05285_amd as p
+    dev = torch.device("cuda:0")
+    L1 = L2 = 4
+    D, chi, n_chains, sweeps, steps, tau, eps = 4, 16, 64, 60, 25, 0.01, 1e-4
+    N = L1 * L2
+    desc = p.Desc(L1, L2, D, chi, alpha=1)
+    theta = torch.tensor(synth.theta_identity(L1, L2, D, 2, noise=0.05, seed=101), device=dev)
+    configs = torch.tensor(synth.configs_diagonal(n_chains, N, 2, seed=101), device=dev)
+    nnz = p.peps_orow_count(desc)
+    status = p.new_status(dev)
+    n_s = n_chains * sweeps
+    S_all = torch.empty((sweeps, n_chains, N), dtype=torch.uint8, device=dev)
+    O_all = torch.empty((sweeps, n_chains, nnz), dtype=torch.float64, device=dev)
+    E_all = torch.empty((sweeps, n_chains), dtype=torch.float64, device=dev)
+    LA_all = torch.empty((sweeps, n_chains), dtype=torch.float64, device=dev)
+    seed, gsweep = 4242, 0
+    worst = 0.0
+    for step in range(steps + 1):
+        for k in range(sweeps):
+            out = {"O": O_all[k:k + 1], "e_loc": E_all[k:k + 1], "log_abs": LA_all[k:k + 1]}
+            p.peps_sample_sweep(desc, theta, configs, seed, gsweep, 1, status=status, out=out)
+            S_all[k].copy_(configs)
+            gsweep += 1
+        e = E_all.cpu().numpy() / (2 * N)
+        la = LA_all.cpu().numpy()
+        w = np.exp(la - la.max())
+        E = float((w * e).sum() / w.sum())
+        chain_means = (w * e).sum(axis=0) / w.sum(axis=0)
+        sigma = float(chain_means.std(ddof=1) / np.sqrt(n_chains))
+        w_d = torch.tensor(w.reshape(n_s), device=dev)
+        beta = 4.0 * tau * step
+        e_ed = _ed_energy(beta)
+        dev_rel = abs(E - e_ed) / (3 * sigma + 0.02 * abs(e_ed) + 1e-12)
+        worst = max(worst, dev_rel)
+        print(f"[cool] step {step} beta {beta:.2f} E/N {E:.5f} +- {sigma:.5f} ED {e_ed:.5f}", flush=True)
+        sys.stdout.flush()
+        assert p.check(status) == 0
+        assert abs(E - e_ed) <= 3 * sigma + 0.02 * abs(e_ed), (step, beta, E, sigma, e_ed)
+        if step == steps:
+            break
+        _, _, stats, _ = p.sr_cg_solve(desc, S_all.view(n_s, N), O_all.view(n_s, nnz), E_all.view(n_s), tau, eps,
+                                       200, 1e-10, weights=w_d, want_g=False, theta=theta, status=status)
+    print("[cool] worst deviation / bar", worst, flush=True)

@@ -472,3 +472,53 @@ def test_cg_matches_dense_solve_and_S_is_psd():
     for i in range(n_s):
         g += Ofull[i] * (e[i] - eb) / n_s
     np.testing.assert_allclose(sol["g"], g, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# SR is imaginary-time evolution (P6; Method section, Eq. (5) and the text
+# before it): with exact expectations (enumeration over every S, weights
+# |rho|^2) the SR trajectory approaches exp(-t calH)|rho_0> as tau -> 0 at
+# fixed t = n tau, with an error that shrinks roughly linearly in tau.  The
+# reference evolution is built independently from the dense H (Kronecker
+# products) acting on the vectorised density matrix.
+
+
+def _sr_exact_trajectory(lat, theta, tau, n_steps, eps):
+    confs = network.all_configs(lat)
+    th = theta.copy()
+    for _ in range(n_steps):
+        amps = np.array([network.amplitude(lat, th, S) for S in confs])
+        res = [measure.evaluate(lat, th, S, lat.chi) for S in confs]
+        E = np.array([r["e_loc"] for r in res])
+        O = np.array([r["O"] for r in res])
+        sol = sr.sr_solve(lat, confs, O, E, tau, eps, 5000, 1e-13, weights=amps ** 2)
+        th = th + sol["dtheta"]
+    return th
+
+
+def test_sr_tracks_imaginary_time_evolution():
+    lat = Lattice(2, 2, D=4, chi=64)
+    H = hamiltonian.dense_spin_H(lat)
+    dim = H.shape[0]
+    calH = np.kron(H, np.eye(dim)) + np.kron(np.eye(dim), H.T)
+
+    def energy(rho_vec):
+        return float(rho_vec @ calH @ rho_vec / (rho_vec @ rho_vec)) / (2 * lat.N)
+
+    th0 = synth.theta_identity(2, 2, 4, 2, noise=0.1, seed=101)
+    v0 = network.density_matrix(lat, th0).reshape(-1)
+    t = 0.04
+    w, U = np.linalg.eigh(calH)
+    e_exact = energy(U @ (np.exp(-t * w) * (U.T @ v0)))
+    e_twice = energy(U @ (np.exp(-2 * t * w) * (U.T @ v0)))
+    errs = []
+    for tau in (0.01, 0.005):
+        th = _sr_exact_trajectory(lat, th0, tau, int(round(t / tau)), 1e-10)
+        errs.append(energy(network.density_matrix(lat, th).reshape(-1)) - e_exact)
+    drop = energy(v0) - e_exact
+    # the energy moves by the exact amount (a factor-2 error in the time
+    # scale would land near e_twice instead)
+    assert abs(errs[1]) < 0.15 * abs(drop), (errs, drop)
+    assert abs(e_twice - e_exact) > 5 * abs(errs[1])
+    # first-order convergence in tau
+    assert 1.5 < errs[0] / errs[1] < 3.5, errs
