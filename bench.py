@@ -173,6 +173,26 @@ def cpu_baseline(L1, L2, D, chi, seed_theta, seed, cg_iters, target_core_s=20.0)
 
 
 # ---------------------------------------------------------------------------
+def measured_traffic(kernel, L, D, chi, chains):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel), or None
+    when the workload differs or the kernel's sources changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path) or (L, D, chi, chains) != (8, 4, 16, 1024):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def run_path(p, torch, desc, theta0, configs0, args, seed):
     """Times args.steps steps of one precision from the given state; returns
     timings, the per-class kernel profile and the final state."""
@@ -300,6 +320,11 @@ def main():
     ap.add_argument("--cool-steps", type=int, default=10,
                     help="FP64 SR steps from the identity before the cooled-state energy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both",
+                    help="run one precision only (profiling runs); the JSON line then carries that path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one elementwise kernel over 512 MiB (reads 512 MiB, writes 512 MiB) as the "
+                         "reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -319,6 +344,21 @@ def main():
     seed_theta, seed = 102, 20240905
     theta0 = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
     configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if args.only != "both":
+        r = run_path(p, torch, desc64 if args.only == "fp64" else descmx, theta0, configs0, args, seed)
+        print(json.dumps({"only": args.only, "samples_per_s": round(r["samples_per_s"], 2),
+                          "ms_per_step": round(r["ms_per_step"], 3),
+                          "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
+                          "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}), flush=True)
+        return
 
     r64 = run_path(p, torch, desc64, theta0, configs0, args, seed)
     rmx = run_path(p, torch, descmx, theta0, configs0, args, seed)
@@ -343,7 +383,8 @@ def main():
         flops_per_launch = comp_flops / comp_n * n
         achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / MI355X_FP64_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / MI355X_FP64_TFLOPS, 4),
+                "traffic": measured_traffic("k_compress2", L1, D, chi, n), "traffic_unit": "HBM bytes/launch",
                 "kernel": "k_compress2", "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
     else:
