@@ -78,6 +78,7 @@ Prob make_prob(const peps_desc* d) {
   P.off_L = off;     off += pad(4 * (int64_t)P.ES);
   P.off_X = off;     off += pad(2 * (int64_t)P.XS);
   P.off_epart = off; off += pad(2 * P.L1 + 2);
+  P.off_tau = off;   off += pad((int64_t)P.L2 * P.chi * P.D);
   P.mixed = d->precision == PEPS_PREC_MIXED;
   if (P.mixed) {
     // FP32 copies of the boundaries, same element strides as the FP64 ones

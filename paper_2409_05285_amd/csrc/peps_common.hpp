@@ -28,6 +28,7 @@ struct Prob {
   int64_t chain_stride;  // doubles per chain
   int64_t off_top, off_lstop, off_bot, off_lsbot, off_B, off_tmp, off_R, off_L, off_X, off_epart;
   int64_t off_top32, off_bot32;   // FP32 boundary copies (offsets in doubles)
+  int64_t off_tau;                // Householder scalars of one compression [L2][chi*D]
   int mixed;                      // FP32 strip contractions
 };
 

@@ -2,13 +2,17 @@
 // threads per chain).
 //
 //   1. absorb the row into the boundary: B_c[(a,l)][p][(b,r)];
-//   2. left-to-right thin Householder QR with the matrix in registers (wave w
-//      owns 8 columns, lane l four rows), one workgroup barrier per
-//      reflector; R is kept in LDS and R B_{c+1} is formed straight into the
-//      registers of the next step (rows (x, p) of the next matrix, p fastest);
+//   2. left-to-right thin Householder QR with the matrix in registers (32
+//      groups of 16 lanes, group g owning columns 2g and 2g+1 and lane t
+//      rows 16t..16t+15), one workgroup barrier per reflector; the reflectors
+//      (not Q) are stored, R is kept in LDS and R B_{c+1} is formed straight
+//      into the registers of the next step (rows (x, p) of the next matrix,
+//      p fastest);
 //   3. right-to-left truncation by one-sided Jacobi in LDS: G = M^T when M is
 //      wide or square (no accumulation; U S = M V_k afterwards), G = M with an
-//      accumulated V when M is tall;
+//      accumulated V when M is tall; the left factor U S is carried into the
+//      next site by applying that site's reflectors to it (Q (U S) without
+//      forming Q), each wave on its own columns with no workgroup barrier;
 //   4. normalisation and log-scale.
 // Supported shapes: matrices up to 256 x 64 in the QR sweep, 64 x 64 in the
 // truncation (chi * D <= 64), physical dimension D in {1, 2, 4}.
@@ -22,20 +26,24 @@ namespace peps {
 namespace {
 
 constexpr int NTC = 512;        // threads per workgroup (8 waves)
-constexpr int QR_RPL = 4;       // rows per lane (64 lanes x 4 = 256 rows)
-constexpr int QR_CPW = 8;       // columns per wave (8 waves x 8 = 64 columns)
+constexpr int QL = 16;          // QR rows per lane (16 lanes x 16 = 256 rows)
 constexpr int QR_ROWS_MAX = 256;
-static_assert(QR_RPL % 4 == 0, "rows per lane must be a multiple of every supported D");
+static_assert(QL % 4 == 0, "rows per lane must be a multiple of every supported D");
 constexpr int QR_COLS = 64;     // max columns
 constexpr int SV_MAX = 64;      // max truncation matrix dimension
 constexpr int SV_LD = SV_MAX + 1;
-constexpr int JL = 16;          // lanes per Jacobi pair
+#ifndef PEPS_JL
+#define PEPS_JL 16
+#endif
+constexpr int JL = PEPS_JL;     // lanes per Jacobi pair
 constexpr int JR = SV_MAX / JL; // rows per lane
 constexpr int JAC_MAX_SWEEPS_V2 = 40;
-constexpr double JAC_TOL = 2.0e-15;
+constexpr double JAC_TOL = 2.0e-15;     // rotate while |g_ij| > tol sqrt(g_ii g_jj)
+constexpr double JAC_CONV = 1.0e-8;     // a sweep whose rotations all stay below this is the last:
+                                        // convergence is quadratic, so the next would be below 1e-16
 
 struct ChainPtrs {
-  double *top, *lstop, *bot, *lsbot, *B;
+  double *top, *lstop, *bot, *lsbot, *B, *tmp, *tau;
 };
 
 __device__ inline ChainPtrs chain_ptrs(const Prob& P, double* ws, int ch) {
@@ -46,6 +54,8 @@ __device__ inline ChainPtrs chain_ptrs(const Prob& P, double* ws, int ch) {
   w.bot = base + P.off_bot;
   w.lsbot = base + P.off_lsbot;
   w.B = base + P.off_B;
+  w.tmp = base + P.off_tmp;
+  w.tau = base + P.off_tau;
   return w;
 }
 
@@ -85,12 +95,14 @@ __device__ inline double sqrt1p_sq(double a) {
   return y * rsqrt_nr(y);
 }
 
-// Lane exchange inside one 16-lane DPP row, for a double.
+// Lane exchange inside one 16-lane DPP row, for a double.  Every control
+// used here reads a lane of the same row, so no lane is masked or out of
+// bounds and no old value is needed.
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -106,17 +118,124 @@ __device__ inline double row16_sum(double v) {
 }
 
 
-// Sum over the 64 lanes of a wave with identical bits on every lane:
-// mirror-pair stages inside each 16-lane row, then xor 16 and xor 32.
-__device__ inline double wave_sum(double v) {
-  v = row16_sum(v);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+// Sum of the values of DPP rows 2h and 2h+1 (permlane16 swap), and of the
+// two 32-lane halves (permlane32 swap).  Both lanes of a pair add the same two
+// operands in the same order, so the result has identical bits on both.
+__device__ inline double rows_pair_sum(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+__device__ inline double halves_sum(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
+// Sum over the 64 lanes of a wave with identical bits on every lane, all in
+// VALU cross-lane operations: mirror-pair stages inside each 16-lane row,
+// then row pairs, then halves.
+__device__ inline double wave_sum(double v) { return halves_sum(rows_pair_sum(row16_sum(v))); }
+
+// N independent 16-lane row sums, stage by stage so that their latencies
+// overlap.
+template <int N>
+__device__ inline void row16_sum_n(double* v) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0xB1>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x4E>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x141>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x140>(v[q]);
+}
+
+// N independent wave sums, stage by stage so that their latencies overlap.
+template <int N>
+__device__ inline void wave_sum_n(double* v) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0xB1>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x4E>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x141>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_f64<0x140>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = rows_pair_sum(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = halves_sum(v[q]);
+}
+
+// Q X for the thin Q = H_0 H_1 ... H_{k-1} of one QR step, with
+// H_j = 1 - tau_j v_j v_j^T, the v_j stored column-major (m rows each, unit
+// entry and zeros above it included), and X = [US; 0] of m x nx with US the
+// first k rows (stride ldu).  Wave w takes columns w, w + 8, ... (NCW per
+// wave), lane l rows 4l..4l+3; the waves never synchronise.  The result is
+// written row-major (m x nx) to out.
+template <int NCW>
+__device__ inline void apply_q(const double* __restrict__ vs, const double* __restrict__ taus, int m, int k,
+                               const double* US, int ldu, int nx, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = 4 * lane;
+  double x[4][NCW];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < NCW; ++q) {
+      const int row = r0 + i, col = wave + 8 * q;
+      x[i][q] = (row < k && col < nx) ? US[row * ldu + col] : 0.0;
+    }
+  if (wave < nx) {
+    for (int j = k - 1; j >= 0; --j) {
+      const double tau = taus[j];
+      if (tau == 0.0) continue;   // uniform: every lane reads the same tau
+      double v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = r0 + i < m ? vs[(size_t)j * m + r0 + i] : 0.0;
+      double sd[NCW];
+#pragma unroll
+      for (int q = 0; q < NCW; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t += v[i] * x[i][q];
+        sd[q] = t;
+      }
+      wave_sum_n<NCW>(sd);
+#pragma unroll
+      for (int q = 0; q < NCW; ++q) {
+        const double tw = tau * sd[q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i][q] -= tw * v[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < NCW; ++q) {
+        const int row = r0 + i, col = wave + 8 * q;
+        if (row < m && col < nx) out[row * nx + col] = x[i][q];
+      }
+  }
+}
+
+// Sum over the JL lanes of a Jacobi pair (aligned groups inside a DPP
+// row), identical bits on every lane of the group.
+__device__ inline double pair_sum(double v) {
+  v += dpp_f64<0xB1>(v);                       // quad_perm [1,0,3,2]
+  if (JL >= 4) v += dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
+  if (JL >= 8) v += dpp_f64<0x141>(v);         // row_half_mirror
+  if (JL >= 16) v += dpp_f64<0x140>(v);        // row_mirror
   return v;
 }
 
 // One-sided Jacobi on G (mg x ng <= 64 x 64, column-major, stride SV_LD),
-// optionally accumulating V (ng x ng, column-major, stride SV_LD).
+// optionally accumulating V (ng x ng, column-major, stride SV_LD).  Rows
+// mg..63 of G and ng..63 of V must hold zeros: every lane then works on its
+// four rows without bounds tests (zero rows change no dot product).
 __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
   const int tid = threadIdx.x;
   if (ng < 2) return;
@@ -125,16 +244,17 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
   const int grp = tid / JL, lane = tid % JL;
   if (tid == 0) { flags[0] = 0; flags[1] = 0; }
   __syncthreads();
+  // round-robin (circle) order: in round rnd group 0 pairs (rnd, ne-1) and
+  // group g > 0 pairs ((rnd + g) mod (ne-1), (rnd - g) mod (ne-1)); both
+  // indices advance by one per round.
+  const bool active = grp < npairs;
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS_V2; ++sweep) {
     const int fl = sweep & 1;
+    int pi = grp == 0 ? 0 : grp % (ne - 1);
+    int pj = grp == 0 ? ne - 1 : (ne - 1 - grp) % (ne - 1);
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
-      int ci = -1, cj = -1;
-      if (grp < npairs) {
-        if (grp == 0) { ci = rnd; cj = ne - 1; }
-        else { ci = (rnd + grp) % (ne - 1); cj = (rnd - grp + ne - 1) % (ne - 1); }
-        if (ci >= ng || cj >= ng) ci = -1;
-        if (ci > cj && ci >= 0) { int t = ci; ci = cj; cj = t; }
-      }
+      int ci = pi < pj ? pi : pj, cj = pi < pj ? pj : pi;
+      if (!active || cj >= ng) ci = -1;
       double x[JR], y[JR];
       double al = 0.0, be = 0.0, ga = 0.0;
       if (ci >= 0) {
@@ -143,16 +263,16 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
 #pragma unroll
         for (int t = 0; t < JR; ++t) {
           const int i = lane + JL * t;
-          x[t] = i < mg ? gi[i] : 0.0;
-          y[t] = i < mg ? gj[i] : 0.0;
+          x[t] = gi[i];
+          y[t] = gj[i];
           al += x[t] * x[t];
           be += y[t] * y[t];
           ga += x[t] * y[t];
         }
       }
-      al = row16_sum(al);
-      be = row16_sum(be);
-      ga = row16_sum(ga);
+      al = pair_sum(al);
+      be = pair_sum(be);
+      ga = pair_sum(ga);
       if (ci >= 0 && ga != 0.0 && ga * ga > (JAC_TOL * JAC_TOL) * (al * be)) {
         const double zeta = (be - al) * rcp_nr(2.0 * ga);
         const double az = fabs(zeta);
@@ -165,10 +285,8 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
 #pragma unroll
         for (int tt = 0; tt < JR; ++tt) {
           const int i = lane + JL * tt;
-          if (i < mg) {
-            gi[i] = c * x[tt] - s * y[tt];
-            gj[i] = s * x[tt] + c * y[tt];
-          }
+          gi[i] = c * x[tt] - s * y[tt];
+          gj[i] = s * x[tt] + c * y[tt];
         }
         if (V) {
           double* vi = V + ci * SV_LD;
@@ -176,16 +294,17 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
 #pragma unroll
           for (int tt = 0; tt < JR; ++tt) {
             const int i = lane + JL * tt;
-            if (i < ng) {
-              const double a = vi[i], b = vj[i];
-              vi[i] = c * a - s * b;
-              vj[i] = s * a + c * b;
-            }
+            const double a = vi[i], b = vj[i];
+            vi[i] = c * a - s * b;
+            vj[i] = s * a + c * b;
           }
         }
-        if (lane == 0) flags[fl] = 1;
+        if (lane == 0 && ga * ga > (JAC_CONV * JAC_CONV) * (al * be)) flags[fl] = 1;
       }
       __syncthreads();
+      if (grp != 0) pi = pi + 1 == ne - 1 ? 0 : pi + 1;
+      else pi = pi + 1;
+      pj = (grp != 0 && pj + 1 == ne - 1) ? 0 : (grp != 0 ? pj + 1 : pj);
     }
     const bool done = flags[fl] == 0;
     __syncthreads();
@@ -300,25 +419,26 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
   }
   __syncthreads();
 
-  // 2. QR sweep.  Wave w owns columns 8w..8w+7 and lane l rows 4l..4l+3,
-  // so a column lives in one wave: its norm and the trailing-column dot
-  // products are wave reductions (DPP + swizzle), and a Householder step
-  // needs a single workgroup barrier, after the owner wave has published
-  // v and tau (double-buffered) in LDS.
-  double av[QR_RPL][QR_CPW];
+  // 2. QR sweep.  The workgroup is 32 groups of 16 lanes (one DPP row
+  // each); group g owns columns 2g, 2g+1 and lane t of the group rows
+  // 16t..16t+15.  A column lives inside one DPP row, so its norm and the
+  // trailing dot products are 16-lane DPP reductions, and a Householder step
+  // needs a single workgroup barrier, after the owner group has published v
+  // and tau (double-buffered) in LDS.
+  double av[QL][2];
   double* Rs = bufB;   // zero-padded 64 x 64 copy of R (stride SV_LD)
-  const int lane = tid & 63;
-  const int wv_id = tid >> 6;
-  const int c0 = QR_CPW * wv_id;     // first column of this wave
-  const int r0 = QR_RPL * lane;      // first row of this lane
+  const int grp = tid >> 4;
+  const int gl = tid & 15;
+  const int c0 = 2 * grp;      // first column of this group
+  const int r0 = QL * gl;      // first row of this lane
   {
     const int m = sa[0] * sp[0], n = sb[0];
 #pragma unroll
-    for (int i = 0; i < QR_RPL; ++i)
+    for (int i = 0; i < QL; ++i)
 #pragma unroll
-      for (int cc = 0; cc < QR_CPW; ++cc) {
-        const int row = r0 + i, cl = c0 + cc;
-        av[i][cc] = (row < m && cl < n) ? w.B[row * n + cl] : 0.0;
+      for (int q = 0; q < 2; ++q) {
+        const int row = r0 + i, cl = c0 + q;
+        av[i][q] = (row < m && cl < n) ? w.B[row * n + cl] : 0.0;
       }
   }
   for (int c = 0; c < P.L2 - 1; ++c) {
@@ -327,25 +447,20 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     // ---- factorisation ----
     for (int j = 0; j < k; ++j) {
       const int bf = j & 1;
-      const int cj = j % QR_CPW;               // column of j inside its wave
-      if (wv_id == j / QR_CPW) {               // owner wave of column j
-        double x[QR_RPL];
+      if (grp == (j >> 1)) {                  // owner group of column j
+        const bool hi = (j & 1) != 0;
+        double x[QL];
 #pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) {
-          double t = 0.0;
+        for (int i = 0; i < QL; ++i) x[i] = hi ? av[i][1] : av[i][0];
+        double s2[2] = {0.0, 0.0};
 #pragma unroll
-          for (int cc = 0; cc < QR_CPW; ++cc) t = cc == cj ? av[i][cc] : t;
-          x[i] = t;
-        }
-        double ps = 0.0, aj = 0.0;
-#pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) {
+        for (int i = 0; i < QL; ++i) {
           const int row = r0 + i;
-          ps += row > j ? x[i] * x[i] : 0.0;
-          aj += row == j ? x[i] : 0.0;
+          s2[0] += row > j ? x[i] * x[i] : 0.0;
+          s2[1] += row == j ? x[i] : 0.0;
         }
-        const double sigma2 = wave_sum(ps);
-        const double alpha = wave_sum(aj);
+        row16_sum_n<2>(s2);
+        const double sigma2 = s2[0], alpha = s2[1];
         double tau = 0.0, scale = 0.0, beta = alpha;
         if (sigma2 > 0.0) {
           const double nrm = sqrt(alpha * alpha + sigma2);
@@ -354,134 +469,100 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
           scale = 1.0 / (alpha - beta);
         }
 #pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) {
+        for (int i = 0; i < QL; ++i) {
           const int row = r0 + i;
           const double v = row > j ? x[i] * scale : (row == j ? 1.0 : 0.0);
           qv[bf][row] = v;
           const double nx = row > j ? v : (row == j ? beta : x[i]);
-#pragma unroll
-          for (int cc = 0; cc < QR_CPW; ++cc) av[i][cc] = cc == cj ? nx : av[i][cc];
+          av[i][0] = hi ? av[i][0] : nx;
+          av[i][1] = hi ? nx : av[i][1];
         }
-        if (lane == 0) { qtau[bf] = tau; taus[j] = tau; }
+        if (gl == 0) { qtau[bf] = tau; taus[j] = tau; }
       }
       __syncthreads();
       const double tau = qtau[bf];
-      if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < n) {
-        double v[QR_RPL];
+      if (tau != 0.0 && c0 + 1 > j && c0 < n) {   // the group has a column right of j
+        double v[QL];
 #pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
+        for (int i = 0; i < QL; ++i) v[i] = qv[bf][r0 + i];
+        double sd[2] = {0.0, 0.0};
 #pragma unroll
-        for (int cc = 0; cc < QR_CPW; ++cc) {
-          const int cl = c0 + cc;
-          if (cl > j && cl < n) {        // uniform over the wave
-            double s = 0.0;
+        for (int i = 0; i < QL; ++i) {
+          sd[0] += v[i] * av[i][0];
+          sd[1] += v[i] * av[i][1];
+        }
+        row16_sum_n<2>(sd);
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
-            const double tw = tau * wave_sum(s);
+        for (int q = 0; q < 2; ++q) {
+          const int cl = c0 + q;
+          const double tw = (cl > j && cl < n) ? tau * sd[q] : 0.0;
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
-          }
+          for (int i = 0; i < QL; ++i) av[i][q] -= tw * v[i];
         }
       }
     }
     __syncthreads();
     // zero-padded copy of R (rows >= k and below the diagonal are 0); rows < 64
-    if (lane < QR_COLS / QR_RPL) {
+    if (r0 < QR_COLS) {
 #pragma unroll
-      for (int i = 0; i < QR_RPL; ++i)
+      for (int i = 0; i < QL; ++i)
 #pragma unroll
-        for (int cc = 0; cc < QR_CPW; ++cc) {
-          const int x = r0 + i, cl = c0 + cc;
-          Rs[x * SV_LD + cl] = (x < k && x <= cl && cl < n) ? av[i][cc] : 0.0;
+        for (int q = 0; q < 2; ++q) {
+          const int x = r0 + i, cl = c0 + q;
+          Rs[x * SV_LD + cl] = (x < k && x <= cl && cl < n) ? av[i][q] : 0.0;
         }
     }
-    // ---- explicit thin Q (m x k) by backward accumulation ----
-    for (int j = k - 1; j >= 0; --j) {
-      const int bf = j & 1;
-      const int cj = j % QR_CPW;
-      const double tau = taus[j];
-      const bool own = wv_id == j / QR_CPW;
-      if (own) {
+    // ---- reflectors v_j (column-major, unit entry and zeros above it
+    // included) into B_c, their scalars into tau[c] ----
+    {
+      double* Vs = w.B + (size_t)c * P.BS;
 #pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) {
-          const int row = r0 + i;
-          double t = 0.0;
+      for (int i = 0; i < QL; ++i)
 #pragma unroll
-          for (int cc = 0; cc < QR_CPW; ++cc) t = cc == cj ? av[i][cc] : t;
-          qv[bf][row] = row > j ? t : (row == j ? 1.0 : 0.0);
+        for (int q = 0; q < 2; ++q) {
+          const int row = r0 + i, cl = c0 + q;
+          if (row < m && cl < k) Vs[(size_t)cl * m + row] = row > cl ? av[i][q] : (row == cl ? 1.0 : 0.0);
         }
-      }
-      __syncthreads();
-      if (tau != 0.0 && c0 + QR_CPW > j + 1 && c0 < k) {
-        double v[QR_RPL];
-#pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) v[i] = qv[bf][r0 + i];
-#pragma unroll
-        for (int cc = 0; cc < QR_CPW; ++cc) {
-          const int cl = c0 + cc;
-          if (cl > j && cl < k) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) s += v[i] * av[i][cc];
-            const double tw = tau * wave_sum(s);
-#pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) av[i][cc] -= tw * v[i];
-          }
-        }
-      }
-      if (own) {
-#pragma unroll
-        for (int i = 0; i < QR_RPL; ++i) {
-          const int row = r0 + i;
-#pragma unroll
-          for (int cc = 0; cc < QR_CPW; ++cc)
-            if (cc == cj) av[i][cc] = row < j ? 0.0 : (row == j ? 1.0 - tau : -tau * av[i][cc]);
-        }
-      }
+      for (int j = tid; j < k; j += NTC) w.tau[c * (P.chi * P.D) + j] = taus[j];
     }
-    __syncthreads();
-    // Q -> B_c as [m][k]
-    double* Bc = w.B + (size_t)c * P.BS;
-#pragma unroll
-    for (int i = 0; i < QR_RPL; ++i)
-#pragma unroll
-      for (int cc = 0; cc < QR_CPW; ++cc) {
-        const int row = r0 + i, cl = c0 + cc;
-        if (row < m && cl < k) Bc[row * k + cl] = av[i][cc];
-      }
-    // next matrix: (R B_{c+1}) with rows (x, p), p fastest; B_{c+1}[j][p][b].
-    // Lane l holds rows 4l..4l+3, i.e. x = (4l + i) / DP, p = (4l + i) % DP.
+    // next matrix: (R B_{c+1}) with rows (x, p), p fastest; B_{c+1}[y][p][b].
+    // Lane t holds rows 16t..16t+15, i.e. x = (16t + i) / DP, p = i % DP.
     const int pn = sp[c + 1], nn = sb[c + 1];
     const double* Bn = w.B + (size_t)(c + 1) * P.BS;
 #pragma unroll
-    for (int i = 0; i < QR_RPL; ++i)
-#pragma unroll
-      for (int cc = 0; cc < QR_CPW; ++cc) av[i][cc] = 0.0;
+    for (int i = 0; i < QL; ++i) {
+      av[i][0] = 0.0;
+      av[i][1] = 0.0;
+    }
     // B_{c+1} is staged through LDS (bufA, free during the QR sweep) in
-    // chunks of PJ rows, so each wave reads its wave-uniform operands with
-    // broadcast LDS loads instead of one global load per operand.
+    // chunks of PJ rows.
     {
       constexpr int PJ = 16;
       const int rowlen = pn * nn;            // <= DP * 64
       double* stage = bufA;                  // PJ * rowlen <= 16 * 256 doubles
+      const int x0 = r0 / DP;
       for (int j0 = 0; j0 < n; j0 += PJ) {
         const int jn = n - j0 < PJ ? n - j0 : PJ;
         for (int idx = tid; idx < jn * rowlen; idx += NTC) stage[idx] = Bn[(size_t)j0 * rowlen + idx];
         __syncthreads();
         if (c0 < nn) {
           for (int jj = 0; jj < jn; ++jj) {
-            double rx[QR_RPL];
+            double rx[QL / DP];
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int x = (r0 + i) / DP;
-              rx[i] = x < QR_COLS ? Rs[x * SV_LD + j0 + jj] : 0.0;
+            for (int xi = 0; xi < QL / DP; ++xi) {
+              const int x = x0 + xi;
+              rx[xi] = x < QR_COLS ? Rs[x * SV_LD + j0 + jj] : 0.0;
             }
 #pragma unroll
-            for (int i = 0; i < QR_RPL; ++i) {
-              const int pq = i % DP;             // r0 is a multiple of QR_RPL, and DP divides QR_RPL
+            for (int pq = 0; pq < DP; ++pq) {
               const double* brow = stage + (jj * pn + pq) * nn + c0;
+              const double b0 = brow[0];
+              const double b1 = c0 + 1 < nn ? brow[1] : 0.0;
 #pragma unroll
-              for (int cc = 0; cc < QR_CPW; ++cc) av[i][cc] += rx[i] * (c0 + cc < nn ? brow[cc] : 0.0);
+              for (int xi = 0; xi < QL / DP; ++xi) {
+                av[xi * DP + pq][0] += rx[xi] * b0;
+                av[xi * DP + pq][1] += rx[xi] * b1;
+              }
             }
           }
         }
@@ -499,11 +580,11 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     const int m = sa[c] * sp[c], n = sb[c];
     double* Bc = w.B + (size_t)c * P.BS;
 #pragma unroll
-    for (int i = 0; i < QR_RPL; ++i)
+    for (int i = 0; i < QL; ++i)
 #pragma unroll
-      for (int cc = 0; cc < QR_CPW; ++cc) {
-        const int row = r0 + i, cl = c0 + cc;
-        if (row < m && cl < n) Bc[row * n + cl] = av[i][cc];
+      for (int q = 0; q < 2; ++q) {
+        const int row = r0 + i, cl = c0 + q;
+        if (row < m && cl < n) Bc[row * n + cl] = av[i][q];
       }
     __syncthreads();
   }
@@ -516,7 +597,9 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     const bool tr = a <= nb;
     const int mg = tr ? nb : a, ng = tr ? a : nb;
     const int k2 = P.chi < ng ? P.chi : ng;
-    const double* M = w.B + (size_t)c * P.BS;
+    // the last site's matrix is dense in B after the QR sweep; every other
+    // site's is the product left in tmp by the previous step
+    const double* M = c == P.L2 - 1 ? w.B + (size_t)c * P.BS : w.tmp;
     double* Vt = outT + (size_t)c * P.TS;
     if (k2 == nb) {
       // No truncation and M has no more columns than rows: the identity is
@@ -529,13 +612,13 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       }
       __syncthreads();
     } else {
-    for (int idx = tid; idx < mg * ng; idx += NTC) {
-      const int j = idx / mg, i = idx % mg;
-      G[j * SV_LD + i] = tr ? M[j * nb + i] : M[i * nb + j];
+    for (int idx = tid; idx < SV_MAX * ng; idx += NTC) {
+      const int j = idx / SV_MAX, i = idx % SV_MAX;
+      G[j * SV_LD + i] = i >= mg ? 0.0 : (tr ? M[j * nb + i] : M[i * nb + j]);
     }
     if (!tr)
-      for (int idx = tid; idx < ng * ng; idx += NTC) {
-        const int j = idx / ng, i = idx % ng;
+      for (int idx = tid; idx < SV_MAX * ng; idx += NTC) {
+        const int j = idx / SV_MAX, i = idx % SV_MAX;
         V[j * SV_LD + i] = (i == j) ? 1.0 : 0.0;
       }
     __syncthreads();
@@ -589,17 +672,18 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     }
     __syncthreads();
     }
-    // B_{c-1} (m2 x a) <- B_{c-1} (U S) (a x k2), through LDS (G is free)
-    const int m2 = sa[c - 1] * sp[c - 1];
-    double* Bp = w.B + (size_t)(c - 1) * P.BS;
-    for (int idx = tid; idx < m2 * k2; idx += NTC) {
-      const int i = idx / k2, t = idx % k2;
-      double s = 0.0;
-      for (int j = 0; j < a; ++j) s += Bp[i * a + j] * V[j * SV_LD + t];
-      G[idx] = s;
+    // A_{c-1} <- Q_{c-1} (U S): the reflectors of QR step c-1 applied to
+    // U S (a x k2, in V), written row-major (m2 x k2) to tmp
+    {
+      const int m2 = sa[c - 1] * sp[c - 1];
+      const double* vs = w.B + (size_t)(c - 1) * P.BS;
+      const double* tc = w.tau + (size_t)(c - 1) * (P.chi * P.D);
+      if (k2 <= 8) apply_q<1>(vs, tc, m2, a, V, SV_LD, k2, w.tmp);
+      else if (k2 <= 16) apply_q<2>(vs, tc, m2, a, V, SV_LD, k2, w.tmp);
+      else if (k2 <= 32) apply_q<4>(vs, tc, m2, a, V, SV_LD, k2, w.tmp);
+      else apply_q<8>(vs, tc, m2, a, V, SV_LD, k2, w.tmp);
     }
     __syncthreads();
-    for (int idx = tid; idx < m2 * k2; idx += NTC) Bp[idx] = G[idx];
     if (tid == 0) {
       sb[c - 1] = k2;
       sa[c] = k2;
@@ -610,10 +694,10 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
   // 4. normalise site 0, accumulate the log-scale
   const int tot0 = sa[0] * sp[0] * sb[0];
   double pt = 0.0;
-  for (int idx = tid; idx < tot0; idx += NTC) pt += w.B[idx] * w.B[idx];
+  for (int idx = tid; idx < tot0; idx += NTC) pt += w.tmp[idx] * w.tmp[idx];
   const double nrm = sqrt(block_sum512(pt, red));
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int idx = tid; idx < tot0; idx += NTC) outT[idx] = w.B[idx] * inv;
+  for (int idx = tid; idx < tot0; idx += NTC) outT[idx] = w.tmp[idx] * inv;
   if (tid == 0) {
     lsb[r] = nrm > 0.0 ? ls_prev + log(nrm) : -INFINITY;
     for (int c = 0; c < P.L2; ++c)
