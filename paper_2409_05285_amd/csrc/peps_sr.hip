@@ -4,7 +4,7 @@
 //
 // O is stored compressed, one block per site and sample; the parameter
 // index of entry e of sample i is  base[e] + S_i[site[e]] * bsz[e].
-//   gather  y_i = O_i . x  : one wavefront per sample row, coalesced along e;
+//   gather  y_i = O_i . x  : GR sample rows per workgroup, coalesced along e;
 //   scatter z = O^T t      : one thread per column e and chunk of samples,
 //                            d^2 register accumulators selected by S_i, then a
 //                            fixed-order sum over chunks.
@@ -88,24 +88,45 @@ __global__ void __launch_bounds__(SR_NT) k_sr_ymean(SrDev D, int it) {
   if (threadIdx.x == 0) D.misc[2] = s;
 }
 
-// y_i = O_i . v (one wavefront per sample row).  The row is walked site by
-// site: the block of site s is contiguous in O_i and, for the sample's slice
-// S_i(s), contiguous in v, so both reads are coalesced.
+// y_i = O_i . v for GR sample rows per workgroup.  Threads stride over the
+// entries e of a row (coalesced reads of O); the parameter index of entry e
+// comes from the column maps and the row's configuration (staged in LDS).
+// Per-thread partial sums, then a fixed-order wave and workgroup reduction.
+constexpr int GR = 2;
 __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, int it) {
+  __shared__ uint8_t cfg[GR][MAX_SITES];
+  __shared__ double red[SR_NT / 64][GR];
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (SR_NT / 64) + (threadIdx.x >> 6);
-  if (row >= D.n_s) return;
-  const double* o = D.O + row * D.nnz;
-  const uint8_t* S = D.configs + row * D.N;
-  double s = 0.0;
-  for (int st = 0; st < D.N; ++st) {
-    const int oo = D.soff[st], bs = D.sbs[st];
-    const double* vb = v + D.spoff[st] + (int64_t)S[st] * bs;
-    for (int e = lane; e < bs; e += 64) s += o[oo + e] * vb[e];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * GR;
+  for (int q = tid; q < GR * D.N; q += SR_NT) {
+    const int r = q / D.N, st = q % D.N;
+    cfg[r][st] = row0 + r < D.n_s ? D.configs[(row0 + r) * D.N + st] : 0;
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) D.y[row] = s;
+  __syncthreads();
+  const int nr = D.n_s - row0 < GR ? (int)(D.n_s - row0) : GR;
+  double acc[GR];
+#pragma unroll
+  for (int r = 0; r < GR; ++r) acc[r] = 0.0;
+  for (int64_t e = tid; e < D.nnz; e += SR_NT) {
+    const int st = D.site[e];
+    const int b = D.base[e], bs = D.bsz[e];
+#pragma unroll
+    for (int r = 0; r < GR; ++r)
+      if (r < nr) acc[r] += D.O[(row0 + r) * D.nnz + e] * v[b + cfg[r][st] * bs];
+  }
+#pragma unroll
+  for (int r = 0; r < GR; ++r)
+    for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int r = 0; r < GR; ++r) red[tid >> 6][r] = acc[r];
+  __syncthreads();
+  if (tid < nr) {
+    double t = 0.0;
+    for (int wv = 0; wv < SR_NT / 64; ++wv) t += red[wv][tid];
+    D.y[row0 + tid] = t;
+  }
 }
 
 // zpart[chunk][k] = sum_{i in chunk} t_i O_i[e] at k = base[e] + S_i * bsz[e],
@@ -368,7 +389,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
   scatter(0, -1);
   hipLaunchKernelGGL(k_sr_reduce, dim3(D.n_red), dim3(SR_NT), 0, st, D, 0, tau, eps, -1);
   hipLaunchKernelGGL(k_sr_start, dim3(1), dim3(SR_NT), 0, st, D, rtol, max_iter);
-  const int gb = (int)((n_s + (SR_NT / 64) - 1) / (SR_NT / 64));
+  const int gb = (int)((n_s + GR - 1) / GR);
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL(k_sr_gather, dim3(gb), dim3(SR_NT), 0, st, D, (const double*)D.p, it);
     hipLaunchKernelGGL(k_sr_ymean, dim3(1), dim3(SR_NT), 0, st, D, it);
