@@ -89,31 +89,37 @@ __global__ void __launch_bounds__(SR_NT) k_sr_ymean(SrDev D, int it) {
 }
 
 // y_i = O_i . v for GR sample rows per workgroup.  Threads stride over the
-// entries e of a row (coalesced reads of O); the parameter index of entry e
-// comes from the column maps and the row's configuration (staged in LDS).
-// Per-thread partial sums, then a fixed-order wave and workgroup reduction.
+// entries e of a row (coalesced reads of O).  Entry e of site s maps to the
+// parameter spoff[s] + S_i[s] sbs[s] + (e - soff[s]); the per-row offsets are
+// staged in LDS and each thread follows its site with a running index (its
+// entries increase).  Per-thread partial sums, then a fixed-order wave and
+// workgroup reduction.
 constexpr int GR = 2;
 __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, int it) {
-  __shared__ uint8_t cfg[GR][MAX_SITES];
+  __shared__ int soff[MAX_SITES + 1];
+  __shared__ int vb[GR][MAX_SITES];
   __shared__ double red[SR_NT / 64][GR];
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * GR;
+  const int nr = D.n_s - row0 < GR ? (int)(D.n_s - row0) : GR;
   for (int q = tid; q < GR * D.N; q += SR_NT) {
     const int r = q / D.N, st = q % D.N;
-    cfg[r][st] = row0 + r < D.n_s ? D.configs[(row0 + r) * D.N + st] : 0;
+    const int S = r < nr ? D.configs[(row0 + r) * D.N + st] : 0;
+    vb[r][st] = D.spoff[st] + S * D.sbs[st] - D.soff[st];
   }
+  for (int st = tid; st < D.N; st += SR_NT) soff[st] = D.soff[st];
+  if (tid == 0) soff[D.N] = (int)D.nnz;
   __syncthreads();
-  const int nr = D.n_s - row0 < GR ? (int)(D.n_s - row0) : GR;
   double acc[GR];
 #pragma unroll
   for (int r = 0; r < GR; ++r) acc[r] = 0.0;
-  for (int64_t e = tid; e < D.nnz; e += SR_NT) {
-    const int st = D.site[e];
-    const int b = D.base[e], bs = D.bsz[e];
+  int st = 0;
+  for (int e = tid; e < D.nnz; e += SR_NT) {
+    while (e >= soff[st + 1]) ++st;
 #pragma unroll
     for (int r = 0; r < GR; ++r)
-      if (r < nr) acc[r] += D.O[(row0 + r) * D.nnz + e] * v[b + cfg[r][st] * bs];
+      if (r < nr) acc[r] += D.O[(row0 + r) * D.nnz + e] * v[vb[r][st] + e];
   }
 #pragma unroll
   for (int r = 0; r < GR; ++r)
