@@ -19,7 +19,12 @@
  *   O row of one sample: sites in order i, each a [l][u][r][d] block holding
  *     d log rho / d T_i[S_i] (the other d^2-1 slices of the site are zero and
  *     not stored); nnz = peps_orow_count();
- *   spin digit s: 0 = up, 1 = down.  Hubbard digit s = n_up + 2 n_dn.
+ *   spin digit s: 0 = up, 1 = down.  Hubbard digit s = n_up + 2 n_dn;
+ *     fermion modes are numbered 2 i + sigma (sites row-major, up before
+ *     down), and a hop between modes a and b carries the Jordan-Wigner sign
+ *     (-1)^(occupied modes strictly between a and b), taken in the ket digits
+ *     for the H (x) 1 half of calH and in the bra digits for 1 (x) H^T.  The
+ *     tensors are plain (no fermionic swap signs in the contraction).
  *
  * Memory and streams.  Every pointer argument of the device calls is a
  * device pointer unless stated otherwise; the caller owns all memory,

@@ -92,7 +92,6 @@ Prob make_prob(const peps_desc* d) {
 
 // Checks that the compiled tile limits hold for the device path.
 peps_status device_support(const peps_desc* d, const Prob& P) {
-  if (d->model != PEPS_MODEL_HEISENBERG) return PEPS_ERR_UNSUPPORTED;
   if ((int64_t)P.chi * P.D > 255) return PEPS_ERR_UNSUPPORTED;
   if (compress_dyn_lds(P) + STATIC_LDS_COMPRESS > LDS_LIMIT) return PEPS_ERR_UNSUPPORTED;
   return PEPS_OK;

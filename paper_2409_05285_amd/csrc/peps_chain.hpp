@@ -141,6 +141,28 @@ __device__ inline bool site_proposal(const Prob& P, int S, int k, int& ns) {
   return true;
 }
 
+// Jordan-Wigner sign of moving the sigma particle of one side (0: ket digit,
+// 1: bra digit) between sites i and j: modes are numbered 2 site + sigma
+// (sites row-major, up before down), and the sign is -1 to the number of
+// occupied modes strictly between the two.
+__device__ inline double jw_sign(const Prob& P, const uint8_t* S, int side, int i, int j, int sg) {
+  int lo = 2 * i + sg, hi = 2 * j + sg;
+  if (lo > hi) { const int t = lo; lo = hi; hi = t; }
+  int cnt = 0;
+  for (int m = lo + 1; m < hi; ++m) {
+    const int dg = side == 0 ? ket_of(P, S[m >> 1]) : bra_of(P, S[m >> 1]);
+    cnt += (dg >> (m & 1)) & 1;
+  }
+  return (cnt & 1) ? -1.0 : 1.0;
+}
+
+// Coefficient of the off-diagonal term of calH reached by bond proposal k
+// (Heisenberg: J/2; Hubbard: -t times the Jordan-Wigner sign).
+__device__ inline double bond_coeff(const Prob& P, const uint8_t* S, int i, int j, int k, double J) {
+  if (P.model == PEPS_MODEL_HEISENBERG) return 0.5 * J;
+  return -P.t * jw_sign(P, S, k / 2, i, j, k % 2);
+}
+
 __device__ inline bool metropolis(const Prob& P, double R, double u) {
   double wgt = P.alpha == 2 ? R * R : fabs(R);
   return u < fmin(1.0, wgt);

@@ -250,6 +250,15 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
         }
     }
   }
+  if (P.model == PEPS_MODEL_HUBBARD) {
+    // U n_up n_dn - mu (n_up + n_dn) on every site, ket and bra digits
+    for (int side = 0; side < 2; ++side)
+      for (int i = 0; i < P.N; ++i) {
+        const int dg = side == 0 ? S[i] / P.d : S[i] % P.d;
+        const int nu = dg & 1, nd = (dg >> 1) & 1;
+        diag += P.U * (nu * nd) - P.mu * (nu + nd);
+      }
+  }
   double e = diag;
   for (int q = 0; q < 2 * P.L1 - 1; ++q) e += ep[q];
   e_loc[out_off + ch] = e;

@@ -343,7 +343,8 @@ __global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restric
 
 // ---------------------------------------------------------------------------
 // Measurement of row r (one-row strip): the O blocks of the row's sites, the
-// local-energy terms inside the row, and (last row) log|psi| and its sign.
+// local-energy terms inside the row (exchanges, or hops with their
+// Jordan-Wigner signs), and (last row) log|psi| and its sign.
 // epart layout per chain: [0, L1) in-row terms, [L1, 2 L1) cross-row terms,
 // [2 L1] log|psi|, [2 L1 + 1] sign.
 template <typename T>
@@ -395,14 +396,14 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
       for (int q = tid; q < bs; q += NT) Orow[sh.geo.ooff[i] + q] = (double)b.tA[q] * f;
       __syncthreads();
     }
-    if (want_e && c < P.L2 - 1 && P.model == PEPS_MODEL_HEISENBERG) {
-      for (int k = 0; k < 2; ++k) {
+    if (want_e && c < P.L2 - 1) {
+      for (int k = 0; k < P.nb_moves; ++k) {
         int ni, nj;
         if (!bond_proposal(P, S[i], S[i + 1], k, ni, nj)) continue;
         const Env eA = lstep1_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni);
         const Env eB = lstep1_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, nj);
         const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env1_size(P, sh.sc, r, c + 1), sh.red);
-        e += 0.5 * P.J1 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
+        e += bond_coeff(P, S, i, i + 1, k, P.J1) * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
       }
     }
     if (c < P.L2 - 1) {
@@ -415,7 +416,8 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
 }
 
 // Cross-row local-energy terms between rows r and r+1 (two-row strip):
-// vertical bonds, and next-nearest-neighbour bonds when J2 != 0.
+// vertical bonds (exchanges, or hops with their Jordan-Wigner signs), and
+// next-nearest-neighbour bonds when J2 != 0.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
                                               double* ws, int32_t* status) {
@@ -443,14 +445,14 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
   int cur = 0;
   for (int c = 0; c < P.L2; ++c) {
     const int i = r * P.L2 + c, j = (r + 1) * P.L2 + c;
+    for (int k = 0; k < P.nb_moves; ++k) {
+      int ni, nj;
+      if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
+      const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni, nj);
+      const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
+      e += bond_coeff(P, S, i, j, k, P.J1) * tracked_ratio(rn, eA.E + sh.Re[c + 1], rho, rhoE);
+    }
     if (P.model == PEPS_MODEL_HEISENBERG) {
-      for (int k = 0; k < 2; ++k) {
-        int ni, nj;
-        if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
-        const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni, nj);
-        const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
-        e += 0.5 * P.J1 * tracked_ratio(rn, eA.E + sh.Re[c + 1], rho, rhoE);
-      }
       if (P.J2 != 0.0 && c < P.L2 - 1) {
         // bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c)
         for (int orient = 0; orient < 2; ++orient) {

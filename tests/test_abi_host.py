@@ -62,9 +62,12 @@ def test_workspace_and_errors():
     # a valid call with n = 0 is a no-op that needs no device
     ok = desc.c()
     assert LIB.peps_eval_batch(ctypes.byref(ok), None, 0, None, None, None, None, None, None, 0, None) == 0
-    # the Hubbard model has no device path yet
+    # shapes beyond the compiled tile limits (chi * D > 255) are refused
+    big = p.Desc(4, 4, 8, 64).c()
+    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None) == -2
+    # the Hubbard model (d = 4) is accepted: with n = 0 the call is a no-op
     hub = p.Desc(2, 2, 2, 4, d=4, model=1).c()
-    assert LIB.peps_eval_batch(ctypes.byref(hub), None, 1, None, None, None, None, None, None, 0, None) == -2
+    assert LIB.peps_eval_batch(ctypes.byref(hub), None, 0, None, None, None, None, None, None, 0, None) == 0
     # workspace too small
     assert LIB.peps_eval_batch(ctypes.byref(ok), ctypes.c_void_p(8), 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                ctypes.c_void_p(8), None, None, ctypes.c_void_p(8), 16, None) == -4

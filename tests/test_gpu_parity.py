@@ -141,6 +141,37 @@ def test_sample_sweep_bit_exact(L1, L2, D, chi, init, n_chains, n_sweeps):
             assert np.all(np.abs(O[k, ch] - m["O"]) <= 1e-9 * np.maximum(1.0, np.abs(m["O"])))
 
 
+@pytest.mark.parametrize("L1,L2,D,chi", [(4, 4, 2, 4), (4, 5, 3, 5)])
+def test_reweighted_sweep_bit_exact(L1, L2, D, chi):
+    """alpha = 1 (Appendix A): acceptance on |R|, same bit-exact bar."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    lat = Lattice(L1, L2, D=D, chi=chi)
+    desc = p.Desc(L1, L2, D, chi, alpha=1)
+    th = synth.theta_identity(L1, L2, D, 2, noise=0.05, seed=13)
+    cfg = synth.configs_diagonal(4, lat.N, 2, seed=14)
+    seed, sweep0, n_sweeps = 77, 5, 2
+    _say("reweighted sweep", L1, L2, D, chi)
+    cfg_d = torch.tensor(cfg, device=dev)
+    res = p.peps_sample_sweep(desc, torch.tensor(th, device=dev), cfg_d, seed, sweep0, n_sweeps)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    got = cfg_d.cpu().numpy()
+    acc = res["n_accept"].cpu().numpy()
+    for ch in range(cfg.shape[0]):
+        S = cfg[ch].astype(np.int64)
+        a = np.zeros(3, dtype=np.int64)
+        ties = []
+        for k in range(n_sweeps):
+            r = sampler.sweep(lat, th, S, chi, seed, ch, sweep0 + k, alpha=1)
+            S, ties = r["S"], ties + r["near_ties"]
+            a += r["n_accept"]
+        if ties:
+            continue
+        assert np.array_equal(got[ch], S.astype(np.uint8)), ch
+        assert np.array_equal(acc[ch], a), ch
+
+
 def test_identity_sweep_flips_every_site():
     dev = _dev()
     import paper_2409_05285_amd as p
@@ -160,6 +191,30 @@ def test_identity_sweep_flips_every_site():
     assert np.array_equal(cfg_d.cpu().numpy(), flipped.astype(np.uint8))
     # beta = 0: E_loc(s,s) = 2 H_ss (diagonal only) and log|psi| = 0
     assert np.allclose(res["log_abs"].cpu().numpy(), 0.0, atol=1e-12)
+
+
+def test_weighted_sr_cg_matches_oracle():
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    lat = Lattice(4, 4, D=2, chi=4)
+    desc = p.Desc(4, 4, 2, 4)
+    rng = np.random.default_rng(91)
+    n_s = 120
+    cfg = synth.configs_uniform(n_s, 16, 2, seed=92)
+    O = rng.standard_normal((n_s, lat.nnz))
+    e = rng.standard_normal(n_s)
+    w = rng.uniform(0.05, 2.0, n_s)
+    _say("weighted sr", n_s)
+    dth, g, stats, st = p.sr_cg_solve(desc, torch.tensor(cfg, device=dev), torch.tensor(O, device=dev),
+                                      torch.tensor(e, device=dev), 0.01, 1e-3, 40, 0.0,
+                                      weights=torch.tensor(w, device=dev))
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    ref = sr.sr_solve(lat, cfg, O, e, tau=0.01, eps=1e-3, max_iter=40, rtol=0.0, weights=w)
+    dth, g, stats = dth.cpu().numpy(), g.cpu().numpy(), stats.cpu().numpy()
+    assert np.allclose(g, ref["g"], rtol=1e-12, atol=1e-14 * np.abs(ref["g"]).max())
+    assert np.all(np.abs(dth - ref["dtheta"]) <= 1e-9 * np.abs(ref["dtheta"]).max())
+    assert abs(stats[0] - ref["ebar"]) <= 1e-13 * max(1.0, abs(ref["ebar"]))
 
 
 @pytest.mark.parametrize("n_s,iters", [(40, 25), (300, 60)])
@@ -270,4 +325,69 @@ def test_mixed_sample_sweep(L1, L2, D, chi, init, n_chains, n_sweeps):
             m = meas[k]
             assert _close_log(la[k, ch], m["log_abs"], MIXED_TOL)
             assert abs(e[k, ch] - m["e_loc"]) <= MIXED_TOL * max(abs(m["e_loc"]), 1.0)
+    assert compared >= 1
+
+
+# ---------------------------------------------------------------------------
+# Fermi-Hubbard (d = 4): hops with Jordan-Wigner signs, plain tensors
+
+
+def _hub_setup(L1, L2, D, chi, mixed=False, seed=21):
+    import paper_2409_05285_amd as p
+    from oracle.lattice import MODEL_HUBBARD
+    lat = Lattice(L1, L2, D=D, chi=chi, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    desc = p.Desc(L1, L2, D, chi, d=4, model=p.MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0,
+                  precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = synth.theta_random_unit(L1, L2, D, 4, seed=seed)
+    return p, lat, desc, th
+
+
+@pytest.mark.parametrize("L1,L2,D,chi,mixed", [(3, 3, 2, 4, False), (4, 4, 2, 4, False), (3, 4, 2, 3, False),
+                                               (4, 4, 2, 4, True)])
+def test_hubbard_eval_and_grad_match_oracle(L1, L2, D, chi, mixed):
+    dev = _dev()
+    p, lat, desc, th = _hub_setup(L1, L2, D, chi, mixed)
+    cfg = synth.configs_sector(5, lat.N, 4, seed=L1 * 10 + L2)
+    _say("hubbard eval", L1, L2, D, chi, mixed)
+    theta_d = torch.tensor(th, device=dev)
+    cfg_d = torch.tensor(cfg, device=dev)
+    la, sg, el, st = p.peps_eval_batch(desc, theta_d, cfg_d)
+    O, la2, st2 = p.peps_grad_batch(desc, theta_d, cfg_d)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    ref = measure.evaluate_batch(lat, th, cfg, chi)
+    la, sg, el, O = (x.cpu().numpy() for x in (la, sg, el, O))
+    tol = MIXED_TOL if mixed else 1e-10
+    assert _close_log(la, ref["log_abs"], tol), (la, ref["log_abs"])
+    assert np.array_equal(sg, ref["sign"])
+    emag = max(np.abs(ref["e_loc"]).mean(), 1e-300)
+    assert np.all(np.abs(el - ref["e_loc"]) <= tol * np.maximum(np.abs(ref["e_loc"]), emag)), (el, ref["e_loc"])
+    otol = MIXED_TOL * np.maximum(1.0, np.abs(ref["O"]).max(axis=1, keepdims=True)) if mixed else \
+        1e-9 * np.maximum(1.0, np.abs(ref["O"]))
+    assert np.all(np.abs(O - ref["O"]) <= otol)
+
+
+def test_hubbard_sweep_bit_exact():
+    dev = _dev()
+    p, lat, desc, th = _hub_setup(4, 4, 2, 4)
+    cfg = synth.configs_diagonal(3, lat.N, 4, seed=23)
+    seed, sweep0, n_sweeps = 99, 1, 2
+    _say("hubbard sweep")
+    cfg_d = torch.tensor(cfg, device=dev)
+    res = p.peps_sample_sweep(desc, torch.tensor(th, device=dev), cfg_d, seed, sweep0, n_sweeps)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    ref = _oracle_chains(lat, th, cfg, 4, seed, sweep0, n_sweeps)
+    got = cfg_d.cpu().numpy()
+    acc = res["n_accept"].cpu().numpy()
+    e = res["e_loc"].cpu().numpy()
+    compared = 0
+    for ch, (S, a, ties, meas) in enumerate(ref):
+        if ties:
+            continue
+        compared += 1
+        assert np.array_equal(got[ch], S.astype(np.uint8)), ch
+        assert np.array_equal(acc[ch], a), (ch, acc[ch], a)
+        m = meas[-1]
+        assert abs(e[-1, ch] - m["e_loc"]) <= 1e-10 * max(abs(m["e_loc"]), 1.0)
     assert compared >= 1

@@ -443,8 +443,63 @@ def test_sampled_histogram_matches_rho_squared():
     assert chi2 < 3.0 * dof + 30, (chi2, dof)
 
 
+@pytest.mark.slow
+def test_reweighted_histogram_matches_abs_rho():
+    """Appendix A, Eq. (A1): with alpha = 1 the chain visits S with weight
+    |rho(S)| (chi^2 test against the exact |rho| on 2x2, exact chi)."""
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=73)
+    reach = [S for S in network.all_configs(lat)
+             if sum(lat.ket(x) for x in S) == sum(lat.bra(x) for x in S)]
+    p = np.array([abs(network.amplitude(lat, th, S)) for S in reach])
+    p /= p.sum()
+    index = {tuple(S): k for k, S in enumerate(reach)}
+    counts = np.zeros(len(reach))
+    for ch in range(4):
+        S = synth.configs_diagonal(1, 4, 2, seed=74 + ch)[0].astype(np.int64)
+        for k in range(1500):
+            S = sampler.sweep(lat, th, S, 4, seed=10, chain=ch, gsweep=k, alpha=1)["S"]
+            if k >= 20:
+                counts[index[tuple(S)]] += 1
+    n = counts.sum()
+    exp_ = p * n
+    mask = exp_ > 5
+    chi2 = float((((counts - exp_) ** 2)[mask] / exp_[mask]).sum())
+    dof = int(mask.sum()) - 1
+    assert chi2 < 3.0 * dof + 30, (chi2, dof)
+
+
 # ---------------------------------------------------------------------------
 # SR (P9)
+
+
+def test_weighted_sr_from_definitions():
+    """Weighted averages (Eq. A1 applied to Eqs. 6, 7, 10): g, S and the solve
+    against explicit sums over samples."""
+    lat = Lattice(3, 3, D=2, chi=4)
+    n_p = lat.n_params
+    rng = np.random.default_rng(83)
+    n_s = 60
+    configs = synth.configs_uniform(n_s, 9, 2, seed=84)
+    O = rng.standard_normal((n_s, lat.nnz))
+    e = rng.standard_normal(n_s)
+    w = rng.uniform(0.1, 3.0, n_s)
+    Ofull = sr.dense_O(lat, configs, O)
+    W = w.sum()
+    eb = sum(w[i] * e[i] for i in range(n_s)) / W
+    ob = sum(w[i] * Ofull[i] for i in range(n_s)) / W
+    g = sum(w[i] * Ofull[i] * (e[i] - eb) for i in range(n_s)) / W
+    Sm = sum(w[i] * np.outer(Ofull[i], Ofull[i]) for i in range(n_s)) / W - np.outer(ob, ob)
+    sol = sr.sr_solve(lat, configs, O, e, tau=0.02, eps=1e-2, max_iter=3000, rtol=1e-13, weights=w)
+    assert sol["ebar"] == pytest.approx(eb, rel=1e-13)
+    np.testing.assert_allclose(sol["g"], g, rtol=1e-11, atol=1e-14)
+    np.testing.assert_allclose(sr.sr_matrix(Ofull, w), Sm, rtol=1e-11, atol=1e-13)
+    direct = np.linalg.solve(Sm + 1e-2 * np.eye(n_p), -0.02 * g)
+    np.testing.assert_allclose(sol["dtheta"], direct, rtol=1e-7, atol=1e-11)
+    # uniform weights reduce to the plain estimator
+    sol_u = sr.sr_solve(lat, configs, O, e, tau=0.02, eps=1e-2, max_iter=50, rtol=0.0, weights=np.full(n_s, 2.5))
+    sol_p = sr.sr_solve(lat, configs, O, e, tau=0.02, eps=1e-2, max_iter=50, rtol=0.0)
+    np.testing.assert_allclose(sol_u["dtheta"], sol_p["dtheta"], rtol=1e-12, atol=1e-15)
 
 
 def test_cg_matches_dense_solve_and_S_is_psd():
