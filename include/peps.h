@@ -160,6 +160,16 @@ peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* confi
                         double* dtheta, double* g_out, double* theta, double* stats,
                         int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
 
+/* Vector-Jacobian product of the log-amplitudes (Eq. 8: O_i is the gradient
+   of log|rho(S_i)| with respect to theta): grad = sum_i cot_i O_i, scattered
+   from the compressed O rows into the parameter layout.  This is the
+   backward pass of theta -> log|psi| on a batch of configurations.
+   configs [n][N] uint8; O_rows [n][nnz] (from peps_grad_batch or
+   peps_sample_sweep); cot [n] f64; grad [N_p] f64 out (overwritten).
+   Workspace: peps_workspace_bytes(desc, n, PEPS_WS_SR). */
+peps_status peps_vjp_batch(const peps_desc* desc, int64_t n, const uint8_t* configs, const double* O_rows,
+                           const double* cot, double* grad, void* ws, size_t ws_bytes, peps_stream_t stream);
+
 /* ---- instrumentation (not part of the method) --------------------------- */
 
 /* Kernel classes timed by the profiler. */
@@ -170,7 +180,8 @@ enum {
   PEPS_K_MEAS1 = 3,    /* O rows, in-row E_loc terms, log|psi|              */
   PEPS_K_MEAS2 = 4,    /* cross-row E_loc terms                             */
   PEPS_K_FINAL = 5,    /* per-sample outputs                                */
-  PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve call       */
+  PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve or
+                          peps_vjp_batch call                               */
   PEPS_N_KCLASS = 7
 };
 

@@ -69,6 +69,8 @@ def _load():
                                 c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]
     lib.sr_cg_solve.restype = c_int32
+    lib.peps_vjp_batch.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.peps_vjp_batch.restype = c_int32
     lib.peps_profile_enable.argtypes = [c_int32]
     lib.peps_profile_enable.restype = None
     lib.peps_profile_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
@@ -79,5 +81,5 @@ def _load():
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
-           "peps_profile_enable", "peps_profile_read"]
+           "peps_vjp_batch", "peps_profile_enable", "peps_profile_read"]
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

@@ -230,6 +230,44 @@ def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, we
     return dtheta, g, stats, status
 
 
+def peps_vjp_batch(desc: Desc, configs, O_rows, cot):
+    """grad [N_p] f64 = sum_i cot_i O_i, scattered into the parameter layout."""
+    configs = _configs(desc, configs)
+    n = configs.shape[0]
+    if O_rows.dtype != torch.float64 or O_rows.shape != (n, peps_orow_count(desc)) or not O_rows.is_contiguous():
+        raise ValueError("O_rows must be contiguous float64 [n, nnz]")
+    if cot.dtype != torch.float64 or cot.shape != (n,):
+        raise ValueError("cot must be float64 [n]")
+    _check_dev(configs, O_rows, cot)
+    grad = torch.empty(peps_param_count(desc), dtype=torch.float64, device=O_rows.device)
+    ws = _ws("sr", peps_workspace_bytes(desc, n, _lib.WS_SR), O_rows.device)
+    code = LIB.peps_vjp_batch(ctypes.byref(desc.c()), n, _ptr(configs), _ptr(O_rows), _ptr(cot.contiguous()),
+                              _ptr(grad), _ptr(ws), ws.numel(), _stream())
+    _raise(code, "peps_vjp_batch")
+    return grad
+
+
+class PepsLogAmp(torch.autograd.Function):
+    """log|psi(S_i)| for a batch of configurations as a differentiable
+    function of theta.  Forward: peps_grad_batch (log-amplitudes and the O
+    rows of the adjoint contraction, Eq. 8); backward: peps_vjp_batch with
+    the incoming cotangent.  Usage: PepsLogAmp.apply(theta, configs, desc)."""
+
+    @staticmethod
+    def forward(ctx, theta, configs, desc):
+        O, log_abs, status = peps_grad_batch(desc, theta, configs)
+        ctx.desc = desc
+        ctx.save_for_backward(configs, O, status)
+        return log_abs
+
+    @staticmethod
+    def backward(ctx, g):
+        configs, O, status = ctx.saved_tensors
+        check(status, "PepsLogAmp forward")
+        grad = peps_vjp_batch(ctx.desc, configs, O, g.to(torch.float64).contiguous())
+        return grad, None, None
+
+
 def peps_profile_enable(on: bool):
     """Bracket every library launch with HIP events (instrumentation)."""
     LIB.peps_profile_enable(1 if on else 0)

@@ -329,6 +329,18 @@ peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs,
   return PEPS_OK;
 }
 
+peps_status peps_vjp_batch(const peps_desc* d, int64_t n, const uint8_t* configs, const double* O_rows,
+                           const double* cot, double* grad, void* ws, size_t ws_bytes, peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  if (n < 1) return PEPS_ERR_ARG;
+  if (!configs || !O_rows || !cot || !grad || !ws) return PEPS_ERR_ARG;
+  if (ws_bytes < sr_workspace_bytes(P, n)) return PEPS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(PEPS_K_SR, launch_vjp(P, n, configs, O_rows, cot, grad, ws, st));
+  return PEPS_OK;
+}
+
 void peps_profile_enable(int32_t on) {
   g_prof = on != 0;
   g_used = 0;

@@ -36,5 +36,7 @@ size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
                      const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
                      double* g_out, double* theta, double* stats, int32_t* status, void* ws, hipStream_t st);
+hipError_t launch_vjp(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* cot,
+                      double* grad, void* ws, hipStream_t st);
 
 }  // namespace peps

@@ -137,15 +137,15 @@ __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, i
 
 // zpart[chunk][k] = sum_{i in chunk} t_i O_i[e] at k = base[e] + S_i * bsz[e],
 // with t_i = w_i (src_i - mean): src = e_loc (mode 0, mean misc[0]) or
-// y (mode 1, mean misc[2]).
+// y (mode 1, mean misc[2]); mode 2: t_i = e_i (the cotangent, no weights).
 template <int D2>
 __global__ void __launch_bounds__(SR_NT) k_sr_scatter(SrDev D, int mode, int it) {
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
   const int64_t e = (int64_t)blockIdx.x * SR_NT + threadIdx.x;
   const int chunk = blockIdx.y;
   if (e >= D.nnz) return;
-  const double* src = mode == 0 ? D.e : D.y;
-  const double mean = mode == 0 ? D.misc[0] : D.misc[2];
+  const double* src = mode == 1 ? D.y : D.e;
+  const double mean = mode == 0 ? D.misc[0] : (mode == 1 ? D.misc[2] : 0.0);
   const int st = D.site[e];
   double acc[D2];
 #pragma unroll
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(SR_NT) k_sr_scatter(SrDev D, int mode, int it)
   int64_t i1 = i0 + D.rows_per_chunk;
   if (i1 > D.n_s) i1 = D.n_s;
   for (int64_t i = i0; i < i1; ++i) {
-    const double t = D.w[i] * (src[i] - mean);
+    const double t = mode == 2 ? src[i] : D.w[i] * (src[i] - mean);
     const double v = t * D.O[i * D.nnz + e];
     const int Si = D.configs[i * D.N + st];
 #pragma unroll
@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(SR_NT) k_sr_scatter(SrDev D, int mode, int it)
 // Sum of the chunk partials.  mode 0: g = z, then CG start vectors
 // b = -tau g: x = 0, r = p = b, part = partial(b.b).
 // mode 1: Ap = z + eps p, part = partial(p.Ap).
+// mode 2: g = z only (vector-Jacobian product).
 __global__ void __launch_bounds__(SR_NT) k_sr_reduce(SrDev D, int mode, double tau, double eps, int it) {
   __shared__ double red[SR_NT];
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
@@ -177,7 +178,9 @@ __global__ void __launch_bounds__(SR_NT) k_sr_reduce(SrDev D, int mode, double t
   for (int64_t k = (int64_t)blockIdx.x * SR_NT + threadIdx.x; k < D.np; k += (int64_t)D.n_red * SR_NT) {
     double z = 0.0;
     for (int c = 0; c < D.n_chunks; ++c) z += D.zpart[(int64_t)c * D.np + k];
-    if (mode == 0) {
+    if (mode == 2) {
+      D.g[k] = z;
+    } else if (mode == 0) {
       D.g[k] = z;
       const double b = -tau * z;
       D.x[k] = 0.0;
@@ -406,6 +409,27 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
   }
   hipLaunchKernelGGL(k_sr_stats, dim3(1), dim3(64), 0, st, D, max_iter, stats, status);
   if (theta) hipLaunchKernelGGL(k_sr_apply, dim3(D.n_red), dim3(SR_NT), 0, st, D, theta);
+  return hipGetLastError();
+}
+
+// grad = sum_i cot_i O_i, scattered into the parameter layout.
+hipError_t launch_vjp(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* cot,
+                      double* grad, void* ws, hipStream_t st) {
+  SrDev D;
+  size_t b = 0;
+  sr_layout(P, n_s, D, &b, (char*)ws);
+  D.configs = configs;
+  D.O = O;
+  D.e = cot;
+  D.g = grad;
+  const int cb = (int)((P.nnz + SR_NT - 1) / SR_NT);
+  hipLaunchKernelGGL(k_sr_colmap, dim3(P.N < 1024 ? P.N : 1024), dim3(256), 0, st, P, (int32_t*)D.base,
+                     (int32_t*)D.bsz, (int32_t*)D.site, (int32_t*)D.soff, (int32_t*)D.spoff, (int32_t*)D.sbs);
+  if (P.d2 == 4)
+    hipLaunchKernelGGL(k_sr_scatter<4>, dim3(cb, D.n_chunks), dim3(SR_NT), 0, st, D, 2, -1);
+  else
+    hipLaunchKernelGGL(k_sr_scatter<16>, dim3(cb, D.n_chunks), dim3(SR_NT), 0, st, D, 2, -1);
+  hipLaunchKernelGGL(k_sr_reduce, dim3(D.n_red), dim3(SR_NT), 0, st, D, 2, 0.0, 0.0, -1);
   return hipGetLastError();
 }
 
