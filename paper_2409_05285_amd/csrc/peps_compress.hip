@@ -18,6 +18,8 @@
 // truncation (chi * D <= 64), physical dimension D in {1, 2, 4}.
 #include <math.h>
 
+#include <type_traits>
+
 #include "peps_common.hpp"
 #include "peps_kernels.hpp"
 
@@ -445,19 +447,19 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     const int m = sa[c] * sp[c], n = sb[c];
     const int k = m < n ? m : n;
     // ---- factorisation ----
-    for (int j = 0; j < k; ++j) {
+    // One Householder step for column j, which is column COL (0 or 1) of its
+    // owner group; COL is a compile-time index into the register slice.
+    auto qr_step = [&](int j, auto colc) {
+      constexpr int COL = decltype(colc)::value;
       const int bf = j & 1;
       if (grp == (j >> 1)) {                  // owner group of column j
-        const bool hi = (j & 1) != 0;
-        double x[QL];
-#pragma unroll
-        for (int i = 0; i < QL; ++i) x[i] = hi ? av[i][1] : av[i][0];
         double s2[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
           const int row = r0 + i;
-          s2[0] += row > j ? x[i] * x[i] : 0.0;
-          s2[1] += row == j ? x[i] : 0.0;
+          const double xi = av[i][COL];
+          s2[0] += row > j ? xi * xi : 0.0;
+          s2[1] += row == j ? xi : 0.0;
         }
         row16_sum_n<2>(s2);
         const double sigma2 = s2[0], alpha = s2[1];
@@ -471,35 +473,40 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
           const int row = r0 + i;
-          const double v = row > j ? x[i] * scale : (row == j ? 1.0 : 0.0);
+          const double xi = av[i][COL];
+          const double v = row > j ? xi * scale : (row == j ? 1.0 : 0.0);
           qv[bf][row] = v;
-          const double nx = row > j ? v : (row == j ? beta : x[i]);
-          av[i][0] = hi ? av[i][0] : nx;
-          av[i][1] = hi ? nx : av[i][1];
+          av[i][COL] = row > j ? v : (row == j ? beta : xi);
         }
         if (gl == 0) { qtau[bf] = tau; taus[j] = tau; }
       }
       __syncthreads();
       const double tau = qtau[bf];
       if (tau != 0.0 && c0 + 1 > j && c0 < n) {   // the group has a column right of j
-        double v[QL];
-#pragma unroll
-        for (int i = 0; i < QL; ++i) v[i] = qv[bf][r0 + i];
+        // v is streamed from LDS twice (dots, then update) rather than held in
+        // 16 more register pairs next to the 32 of the matrix slice
         double sd[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
-          sd[0] += v[i] * av[i][0];
-          sd[1] += v[i] * av[i][1];
+          const double vi = qv[bf][r0 + i];
+          sd[0] += vi * av[i][0];
+          sd[1] += vi * av[i][1];
         }
         row16_sum_n<2>(sd);
+        const double tw0 = (c0 > j && c0 < n) ? tau * sd[0] : 0.0;
+        const double tw1 = (c0 + 1 > j && c0 + 1 < n) ? tau * sd[1] : 0.0;
+        asm volatile("" ::: "memory");   // compiler-only fence: reload v below
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int cl = c0 + q;
-          const double tw = (cl > j && cl < n) ? tau * sd[q] : 0.0;
-#pragma unroll
-          for (int i = 0; i < QL; ++i) av[i][q] -= tw * v[i];
+        for (int i = 0; i < QL; ++i) {
+          const double vi = qv[bf][r0 + i];
+          av[i][0] -= tw0 * vi;
+          av[i][1] -= tw1 * vi;
         }
       }
+    };
+    for (int j = 0; j < k; j += 2) {
+      qr_step(j, std::integral_constant<int, 0>());
+      if (j + 1 < k) qr_step(j + 1, std::integral_constant<int, 1>());
     }
     __syncthreads();
     // zero-padded copy of R (rows >= k and below the diagonal are 0); rows < 64
