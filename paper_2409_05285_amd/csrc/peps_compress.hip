@@ -453,13 +453,13 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       constexpr int COL = decltype(colc)::value;
       const int bf = j & 1;
       if (grp == (j >> 1)) {                  // owner group of column j
+        const int dj = j - r0;                // row r0 + i is below the diagonal when i > dj
         double s2[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
-          const int row = r0 + i;
           const double xi = av[i][COL];
-          s2[0] += row > j ? xi * xi : 0.0;
-          s2[1] += row == j ? xi : 0.0;
+          s2[0] += i > dj ? xi * xi : 0.0;
+          s2[1] += i == dj ? xi : 0.0;
         }
         row16_sum_n<2>(s2);
         const double sigma2 = s2[0], alpha = s2[1];
@@ -472,11 +472,10 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
         }
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
-          const int row = r0 + i;
           const double xi = av[i][COL];
-          const double v = row > j ? xi * scale : (row == j ? 1.0 : 0.0);
-          qv[bf][row] = v;
-          av[i][COL] = row > j ? v : (row == j ? beta : xi);
+          const double v = i > dj ? xi * scale : (i == dj ? 1.0 : 0.0);
+          qv[bf][r0 + i] = v;
+          av[i][COL] = i > dj ? v : (i == dj ? beta : xi);
         }
         if (gl == 0) { qtau[bf] = tau; taus[j] = tau; }
       }
