@@ -61,6 +61,41 @@ __device__ inline ChainPtrs chain_ptrs(const Prob& P, double* ws, int ch) {
   return w;
 }
 
+// One absorbed site B_c[(x, p)][(b, r)] = sum_u A[a][u][b] W[l][u][r][p]
+// (top; for the bottom boundary the roles of the vertical legs swap), with
+// x = (a, l).  A is the previous boundary tensor of the column (none for the
+// first row: a = b = 1, A = 1), W the configuration's slice of the site.
+struct Absorb {
+  const double* A;
+  const double* W;
+  int b, qd, pp, Dl, Du, Dr, Dd, dir;
+  __device__ inline double at(int x, int p, int col) const {
+    const int aa = x / Dl, l = x % Dl, bq = col / Dr, rr = col % Dr;
+    double s = 0.0;
+    for (int u = 0; u < qd; ++u) {
+      const double Av = A ? A[(aa * qd + u) * b + bq] : 1.0;
+      const double Wv = dir == 0 ? W[((l * Du + u) * Dr + rr) * Dd + p] : W[((l * Du + p) * Dr + rr) * Dd + u];
+      s += Av * Wv;
+    }
+    return s;
+  }
+};
+
+__device__ inline Absorb absorb_site(const Prob& P, int dir, int r, int c, const double* theta, const uint8_t* cfg,
+                                     const double* bnd, int rp, bool has_prev, const int* poffr, const int* pa,
+                                     const int* pb) {
+  Absorb ab;
+  leg_dims(P, r, c, ab.Dl, ab.Du, ab.Dr, ab.Dd);
+  ab.W = theta + poffr[c] + (size_t)cfg[r * P.L2 + c] * (ab.Dl * ab.Du * ab.Dr * ab.Dd);
+  ab.A = has_prev ? bnd + ((size_t)rp * P.L2 + c) * P.TS : nullptr;
+  ab.b = has_prev ? pb[c] : 1;
+  ab.qd = has_prev ? (dir == 0 ? ab.Du : ab.Dd) : 1;
+  ab.pp = dir == 0 ? ab.Dd : ab.Du;
+  ab.dir = dir;
+  (void)pa;
+  return ab;
+}
+
 // fixed-order sum of NTC values through LDS, identical on every thread
 __device__ inline double block_sum512(double v, double* red) {
   const int tid = threadIdx.x;
@@ -79,12 +114,6 @@ __device__ inline double block_sum512(double v, double* red) {
 // (each step doubles the correct bits; two reach double precision), and
 // sqrt(1 + x^2) as y * rsqrt(y).  Used for the Jacobi rotation parameters,
 // where a few ulp only perturb orthogonality at rounding level.
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
 __device__ inline double rsqrt_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
   double h = 0.5 * x;
@@ -92,9 +121,17 @@ __device__ inline double rsqrt_nr(double x) {
   r = r * fma(-h * r, r, 1.5);
   return r;
 }
-__device__ inline double sqrt1p_sq(double a) {
+// One Newton step (about 1e-14 relative): enough where the value only sets
+// a rotation angle, which the next sweep corrects, and not its orthogonality.
+__device__ inline double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double sqrt1p_sq1(double a) {
   const double y = fma(a, a, 1.0);
-  return y * rsqrt_nr(y);
+  double r = __builtin_amdgcn_rsq(y);
+  r = r * fma(-0.5 * y * r, r, 1.5);
+  return y * r;
 }
 
 // Lane exchange inside one 16-lane DPP row, for a double.  Every control
@@ -255,11 +292,10 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
     int pi = grp == 0 ? 0 : grp % (ne - 1);
     int pj = grp == 0 ? ne - 1 : (ne - 1 - grp) % (ne - 1);
     for (int rnd = 0; rnd < ne - 1; ++rnd) {
-      int ci = pi < pj ? pi : pj, cj = pi < pj ? pj : pi;
-      if (!active || cj >= ng) ci = -1;
-      double x[JR], y[JR];
-      double al = 0.0, be = 0.0, ga = 0.0;
-      if (ci >= 0) {
+      const int ci = pi < pj ? pi : pj, cj = pi < pj ? pj : pi;
+      if (active && cj < ng) {                  // uniform over the group
+        double x[JR], y[JR];
+        double al = 0.0, be = 0.0, ga = 0.0;
         const double* gi = G + ci * SV_LD;
         const double* gj = G + cj * SV_LD;
 #pragma unroll
@@ -271,37 +307,39 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
           be += y[t] * y[t];
           ga += x[t] * y[t];
         }
-      }
-      al = pair_sum(al);
-      be = pair_sum(be);
-      ga = pair_sum(ga);
-      if (ci >= 0 && ga != 0.0 && ga * ga > (JAC_TOL * JAC_TOL) * (al * be)) {
-        const double zeta = (be - al) * rcp_nr(2.0 * ga);
-        const double az = fabs(zeta);
-        const double root = az < 1.0e150 ? sqrt1p_sq(az) : az;
-        const double t = copysign(rcp_nr(az + root), zeta);
-        const double c = rsqrt_nr(fma(t, t, 1.0));
-        const double s = c * t;
-        double* gi = G + ci * SV_LD;
-        double* gj = G + cj * SV_LD;
-#pragma unroll
-        for (int tt = 0; tt < JR; ++tt) {
-          const int i = lane + JL * tt;
-          gi[i] = c * x[tt] - s * y[tt];
-          gj[i] = s * x[tt] + c * y[tt];
-        }
-        if (V) {
-          double* vi = V + ci * SV_LD;
-          double* vj = V + cj * SV_LD;
+        al = pair_sum(al);
+        be = pair_sum(be);
+        ga = pair_sum(ga);
+        if (ga != 0.0 && ga * ga > (JAC_TOL * JAC_TOL) * (al * be)) {
+          // tangent of the angle from the cotangent of twice the angle; only c
+          // and s = c t must be accurate to the last bit (orthogonality)
+          const double zeta = (be - al) * rcp_nr1(2.0 * ga);
+          const double az = fabs(zeta);
+          const double root = az < 1.0e150 ? sqrt1p_sq1(az) : az;
+          const double t = copysign(rcp_nr1(az + root), zeta);
+          const double c = rsqrt_nr(fma(t, t, 1.0));
+          const double s = c * t;
+          double* gwi = G + ci * SV_LD;
+          double* gwj = G + cj * SV_LD;
 #pragma unroll
           for (int tt = 0; tt < JR; ++tt) {
             const int i = lane + JL * tt;
-            const double a = vi[i], b = vj[i];
-            vi[i] = c * a - s * b;
-            vj[i] = s * a + c * b;
+            gwi[i] = c * x[tt] - s * y[tt];
+            gwj[i] = s * x[tt] + c * y[tt];
           }
+          if (V) {
+            double* vi = V + ci * SV_LD;
+            double* vj = V + cj * SV_LD;
+#pragma unroll
+            for (int tt = 0; tt < JR; ++tt) {
+              const int i = lane + JL * tt;
+              const double a = vi[i], b = vj[i];
+              vi[i] = c * a - s * b;
+              vj[i] = s * a + c * b;
+            }
+          }
+          if (lane == 0 && ga * ga > (JAC_CONV * JAC_CONV) * (al * be)) flags[fl] = 1;
         }
-        if (lane == 0 && ga * ga > (JAC_CONV * JAC_CONV) * (al * be)) flags[fl] = 1;
       }
       __syncthreads();
       if (grp != 0) pi = pi + 1 == ne - 1 ? 0 : pi + 1;
@@ -388,37 +426,17 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
   if (bad) return;
   const double ls_prev = has_prev ? lsb[rp] : 0.0;
 
-  // 1. absorption
-  for (int c = 0; c < P.L2; ++c) {
-    int Dl, Du, Dr, Dd;
-    leg_dims(P, r, c, Dl, Du, Dr, Dd);
-    const int i = r * P.L2 + c;
-    const double* W = theta + poffr[c] + (size_t)cfg[i] * (Dl * Du * Dr * Dd);
-    const double* A = has_prev ? bnd + ((size_t)rp * P.L2 + c) * P.TS : nullptr;
-    const int a = has_prev ? pa[c] : 1, b = has_prev ? pb[c] : 1;
-    const int qd = has_prev ? (dir == 0 ? Du : Dd) : 1;
-    const int pp = dir == 0 ? Dd : Du;
-    double* Bc = w.B + (size_t)c * P.BS;
-    const int total = a * Dl * pp * b * Dr;
-    for (int idx = tid; idx < total; idx += NTC) {
-      int rr = idx % Dr, t = idx / Dr;
-      int bq = t % b; t /= b;
-      int pq = t % pp; t /= pp;
-      int l = t % Dl, aa = t / Dl;
-      double s = 0.0;
-      for (int x = 0; x < qd; ++x) {
-        const double Av = A ? A[(aa * qd + x) * b + bq] : 1.0;
-        const double Wv = dir == 0 ? W[((l * Du + x) * Dr + rr) * Dd + pq] : W[((l * Du + pq) * Dr + rr) * Dd + x];
-        s += Av * Wv;
-      }
-      Bc[idx] = s;
+  // 1. absorption: only the dims here; each site's absorbed tensor is formed
+  // where it is consumed (the first QR matrix, and the staged rows of
+  // R B_{c+1}), never stored
+  if (tid == 0)
+    for (int c = 0; c < P.L2; ++c) {
+      int Dl, Du, Dr, Dd;
+      leg_dims(P, r, c, Dl, Du, Dr, Dd);
+      sa[c] = (has_prev ? pa[c] : 1) * Dl;
+      sp[c] = dir == 0 ? Dd : Du;
+      sb[c] = (has_prev ? pb[c] : 1) * Dr;
     }
-    if (tid == 0) {
-      sa[c] = a * Dl;
-      sp[c] = pp;
-      sb[c] = b * Dr;
-    }
-  }
   __syncthreads();
 
   // 2. QR sweep.  The workgroup is 32 groups of 16 lanes (one DPP row
@@ -435,12 +453,13 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
   const int r0 = QL * gl;      // first row of this lane
   {
     const int m = sa[0] * sp[0], n = sb[0];
+    const Absorb ab = absorb_site(P, dir, r, 0, theta, cfg, bnd, rp, has_prev, poffr, pa, pb);
 #pragma unroll
     for (int i = 0; i < QL; ++i)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int row = r0 + i, cl = c0 + q;
-        av[i][q] = (row < m && cl < n) ? w.B[row * n + cl] : 0.0;
+        av[i][q] = (row < m && cl < n) ? ab.at(row / ab.pp, row % ab.pp, cl) : 0.0;
       }
   }
   for (int c = 0; c < P.L2 - 1; ++c) {
@@ -534,7 +553,7 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
     // next matrix: (R B_{c+1}) with rows (x, p), p fastest; B_{c+1}[y][p][b].
     // Lane t holds rows 16t..16t+15, i.e. x = (16t + i) / DP, p = i % DP.
     const int pn = sp[c + 1], nn = sb[c + 1];
-    const double* Bn = w.B + (size_t)(c + 1) * P.BS;
+    const Absorb abn = absorb_site(P, dir, r, c + 1, theta, cfg, bnd, rp, has_prev, poffr, pa, pb);
 #pragma unroll
     for (int i = 0; i < QL; ++i) {
       av[i][0] = 0.0;
@@ -549,7 +568,10 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       const int x0 = r0 / DP;
       for (int j0 = 0; j0 < n; j0 += PJ) {
         const int jn = n - j0 < PJ ? n - j0 : PJ;
-        for (int idx = tid; idx < jn * rowlen; idx += NTC) stage[idx] = Bn[(size_t)j0 * rowlen + idx];
+        for (int idx = tid; idx < jn * rowlen; idx += NTC) {
+          const int jj = idx / rowlen, rem = idx % rowlen;
+          stage[idx] = abn.at(j0 + jj, rem / nn, rem % nn);
+        }
         __syncthreads();
         if (c0 < nn) {
           for (int jj = 0; jj < jn; ++jj) {
