@@ -228,13 +228,22 @@ __device__ inline void apply_q(const double* __restrict__ vs, const double* __re
       const int row = r0 + i, col = wave + 8 * q;
       x[i][q] = (row < k && col < nx) ? US[row * ldu + col] : 0.0;
     }
-  if (wave < nx) {
+  if (wave < nx && k > 0) {
+    // reflector j+1's data is consumed while reflector j's is in flight
+    double vn[4], taun = taus[k - 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) vn[i] = r0 + i < m ? vs[(size_t)(k - 1) * m + r0 + i] : 0.0;
     for (int j = k - 1; j >= 0; --j) {
-      const double tau = taus[j];
-      if (tau == 0.0) continue;   // uniform: every lane reads the same tau
+      const double tau = taun;
       double v[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = r0 + i < m ? vs[(size_t)j * m + r0 + i] : 0.0;
+      for (int i = 0; i < 4; ++i) v[i] = vn[i];
+      if (j > 0) {
+        taun = taus[j - 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vn[i] = r0 + i < m ? vs[(size_t)(j - 1) * m + r0 + i] : 0.0;
+      }
+      if (tau == 0.0) continue;   // uniform: every lane reads the same tau
       double sd[NCW];
 #pragma unroll
       for (int q = 0; q < NCW; ++q) {
@@ -374,6 +383,7 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
   __shared__ int ta[MAX_L], tb[MAX_L], tp[MAX_L];
   __shared__ double sig[SV_MAX];
   __shared__ int rnk[SV_MAX];
+  __shared__ int perm[SV_MAX];
 
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
@@ -651,10 +661,19 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       }
     __syncthreads();
     jacobi64(G, mg, ng, tr ? nullptr : V, flags);
-    for (int j = tid; j < ng; j += NTC) {
-      double s = 0.0;
-      for (int i = 0; i < mg; ++i) s += G[j * SV_LD + i] * G[j * SV_LD + i];
-      sig[j] = sqrt(s);
+    {
+      // column norms: 16 lanes per column (rows zero-padded to 64)
+      const int g16 = tid >> 4, l16 = tid & 15;
+      for (int j = g16; j < ng; j += NTC / 16) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < SV_MAX / 16; ++t) {
+          const double x = G[j * SV_LD + l16 + 16 * t];
+          s += x * x;
+        }
+        s = row16_sum(s);
+        if (l16 == 0) sig[j] = sqrt(s);
+      }
     }
     __syncthreads();
     for (int j = tid; j < ng; j += NTC) {
@@ -662,28 +681,26 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       for (int t = 0; t < ng; ++t)
         if (sig[t] > sig[j] || (sig[t] == sig[j] && t < j)) ++rk;
       rnk[j] = rk;
+      perm[rk] = j;
     }
     __syncthreads();
     if (tr) {
-      // V_k^T rows: normalised columns of G (in place), then U S = M V_k into bufB
-      for (int idx = tid; idx < ng * mg; idx += NTC) {
-        const int j = idx / mg, e = idx % mg;
-        const int rq = rnk[j];
-        if (rq < k2) {
-          const double v = sig[j] > 0.0 ? G[j * SV_LD + e] / sig[j] : 0.0;
-          G[j * SV_LD + e] = v;
-          Vt[rq * nb + e] = v;
-        }
+      // V_k^T rows: normalised kept columns of G (in place), then U S = M V_k
+      for (int idx = tid; idx < k2 * mg; idx += NTC) {
+        const int rq = idx / mg, e = idx % mg;
+        const int j = perm[rq];
+        const double v = sig[j] > 0.0 ? G[j * SV_LD + e] / sig[j] : 0.0;
+        G[j * SV_LD + e] = v;
+        Vt[rq * nb + e] = v;
       }
       __syncthreads();
-      for (int idx = tid; idx < a * ng; idx += NTC) {
-        const int i = idx / ng, j = idx % ng;
-        const int rq = rnk[j];
-        if (rq < k2) {
-          double s = 0.0;
-          for (int e = 0; e < nb; ++e) s += M[i * nb + e] * G[j * SV_LD + e];
-          V[i * SV_LD + rq] = s;
-        }
+      for (int idx = tid; idx < a * k2; idx += NTC) {
+        const int i = idx / k2, rq = idx % k2;
+        const double* gj = G + perm[rq] * SV_LD;
+        const double* mi = M + i * nb;
+        double s = 0.0;
+        for (int e = 0; e < nb; ++e) s += mi[e] * gj[e];
+        V[i * SV_LD + rq] = s;
       }
     } else {
       for (int idx = tid; idx < ng * ng; idx += NTC) {
