@@ -70,12 +70,20 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
     const bool mv = m < M, nv = n < N;
     const int ao = mv ? am(m) : 0, bo = nv ? bn(n) : 0;
     typename MF::acc c = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lk;
-      const bool kv = k < K;
-      const T a = (mv && kv) ? A[ao + ak(k)] : T(0);
-      const T b = (nv && kv) ? B[bk(k) + bo] : T(0);
-      c = MF::run(a, b, c);
+    // KU k-steps per batch: all their operand loads are issued before the
+    // first MFMA of the batch, so the loads of a wave overlap
+    constexpr int KU = 4;
+    for (int k0 = 0; k0 < K; k0 += 4 * KU) {
+      T a[KU], b[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const bool kv = k < K;
+        a[u] = (mv && kv) ? A[ao + ak(k)] : T(0);
+        b[u] = (nv && kv) ? B[bk(k) + bo] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) c = MF::run(a[u], b[u], c);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
