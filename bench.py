@@ -19,6 +19,10 @@ also on the random-tensor state of the timed run.  `value` is the mixed
 path's rate when the cooled-state error is within --tol, else the FP64
 rate.
 
+The same step is also captured once as a HIP graph (device sweep counter,
+caller-owned workspaces) and replayed; `graph_replay` reports that rate
+beside the eager one, which carries the per-kernel HIP-event timings.
+
 Prints one JSON line.  The CPU baseline is the FP64 oracle (tests only,
 never the product path) timed on a bounded sample on this host.
 """
@@ -247,6 +251,52 @@ def run_path(p, torch, desc, theta0, configs0, args, seed):
             "stats": st, "accept": acc, "theta": theta, "configs": configs}
 
 
+def graph_rate(p, torch, desc, theta0, configs0, args, seed):
+    """The same step captured once in a HIP graph (caller-owned workspaces,
+    device sweep counter) and replayed args.steps times after args.warmup
+    eager steps; returns ms per replayed step."""
+    dev = theta0.device
+    n = configs0.shape[0]
+    nnz = p.peps_orow_count(desc)
+    theta = theta0.clone()
+    configs = configs0.clone()
+    ctr = torch.zeros(1, dtype=torch.int64, device=dev)
+    n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+    status = p.new_status(dev)
+    ws = torch.empty(p.workspace_bytes(desc, n, "sweep"), dtype=torch.uint8, device=dev)
+    ws_sr = torch.empty(p.workspace_bytes(desc, n, "sr"), dtype=torch.uint8, device=dev)
+    out = {"log_abs": torch.empty((1, n), dtype=torch.float64, device=dev),
+           "sign": torch.empty((1, n), dtype=torch.int8, device=dev),
+           "e_loc": torch.empty((1, n), dtype=torch.float64, device=dev),
+           "O": torch.empty((1, n, nnz), dtype=torch.float64, device=dev)}
+
+    def step():
+        p.peps_sample_sweep(desc, theta, configs, seed, 0, 1, n_accept=n_accept, status=status, out=out,
+                            sweep_counter=ctr, ws=ws)
+        p.sr_cg_solve(desc, configs, out["O"][0], out["e_loc"][0], args.tau, args.eps, args.cg_iters, 1e-10,
+                      want_g=False, theta=theta, status=status, ws=ws_sr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    p.check(status, "graph replays")
+    ms = ev0.elapsed_time(ev1) / args.steps
+    del graph
+    return {"ms_per_step": round(ms, 3), "samples_per_s": round(n / (ms / 1e3), 2),
+            "sweeps_replayed": int(ctr.item())}
+
+
 def energy_error(p, torch, desc64, descmx, theta, configs):
     """Local energies of the same samples and parameters from both
     precisions: relative error of the mean energy, the same error in units
@@ -369,6 +419,8 @@ def main():
                                seed)
     err_cooled = energy_error(p, torch, desc64, descmx, th_c, cfg_c)
     mixed_ok = err_cooled["mean_E_rel"] <= args.tol
+    graph64 = graph_rate(p, torch, desc64, theta0, configs0, args, seed)
+    graphmx = graph_rate(p, torch, descmx, theta0, configs0, args, seed)
     eval64 = eval_rate(p, torch, desc64, r64["theta"], r64["configs"])
     evalmx = eval_rate(p, torch, descmx, r64["theta"], r64["configs"])
     best = rmx if mixed_ok else r64
@@ -440,6 +492,8 @@ def main():
                                         state=f"identity + noise after {args.cool_steps} FP64 SR steps"),
                          "random": dict(err_random, state="random unit-Frobenius tensors after the timed steps")},
         "eval_samples_per_s": {"fp64": round(eval64, 1), "mixed": round(evalmx, 1)},
+        "graph_replay": {"fp64": graph64, "mixed": graphmx,
+                         "note": "the same step captured once as a HIP graph and replayed"},
         "host_wall_ms_per_step": round(best["wall"] * 1e3 / args.steps, 3),
     }
     if not args.no_cpu_baseline:

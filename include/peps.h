@@ -130,14 +130,18 @@ peps_status peps_grad_batch(const peps_desc* desc, const double* theta, int32_t 
    vertical exchanges c = 0..L2-1 with two-row strip ratios; then the top
    boundary of row r is recomputed.  The uniform of proposal slot q in global
    sweep g of chain ch is Philox4x64-10 with counter (ch, g, q, 0) and key
-   (seed, 0): u = (w0 >> 11) * 2^-53; sweep k of this call has g = sweep0 + k.
+   (seed, 0): u = (w0 >> 11) * 2^-53; sweep k of this call has
+   g = sweep0 + c + k, where c = *sweep_counter (read on the device) when
+   sweep_counter is not NULL, else 0.  sweep_counter: one device uint64 or
+   NULL; when given, the call adds n_sweeps to it after its last kernel, so a
+   call captured once in a HIP graph draws fresh uniforms on every replay.
    configs [n_chains][N] in/out.  Per sweep k and chain ch (index k*n_chains+ch):
    log_abs, sign, e_loc [n_sweeps*n_chains], O_rows [n_sweeps*n_chains][nnz];
    any of these may be NULL (then not written).  n_accept [n_chains][3] int32
    is incremented by the accepted moves of each type (may be NULL). */
 peps_status peps_sample_sweep(const peps_desc* desc, const double* theta, int32_t n_chains,
-                              uint8_t* configs, uint64_t seed, uint64_t sweep0, int32_t n_sweeps,
-                              double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
+                              uint8_t* configs, uint64_t seed, uint64_t sweep0,
+                              uint64_t* sweep_counter, int32_t n_sweeps, double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
                               int32_t* n_accept, int32_t* status, void* ws, size_t ws_bytes,
                               peps_stream_t stream);
 

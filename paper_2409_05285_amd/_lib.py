@@ -61,7 +61,7 @@ def _load():
     lib.peps_grad_batch.argtypes = [P, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]
     lib.peps_grad_batch.restype = c_int32
-    lib.peps_sample_sweep.argtypes = [P, c_void_p, c_int32, c_void_p, c_uint64, c_uint64, c_int32, c_void_p,
+    lib.peps_sample_sweep.argtypes = [P, c_void_p, c_int32, c_void_p, c_uint64, c_uint64, c_void_p, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                       c_void_p]
     lib.peps_sample_sweep.restype = c_int32

@@ -102,6 +102,23 @@ def _ws(kind, nbytes, device):
     return w.get(nbytes, device)
 
 
+def _own_ws(ws, kind, nbytes, device):
+    """The caller's workspace after a size and device check, else the
+    shared cache of that kind."""
+    if ws is None:
+        return _ws(kind, nbytes, device)
+    if ws.dtype != torch.uint8 or not ws.is_contiguous() or ws.device != device or ws.numel() < max(int(nbytes), 256):
+        raise ValueError("workspace must be a contiguous uint8 device tensor of at least %d bytes" % nbytes)
+    return ws
+
+
+def workspace_bytes(desc: Desc, n, kind):
+    """Bytes of workspace a call on n chains ("sweep", "eval", "grad") or
+    n_s samples ("sr") needs."""
+    what = {"sweep": _lib.WS_SWEEP, "eval": _lib.WS_EVAL, "grad": _lib.WS_GRAD, "sr": _lib.WS_SR}[kind]
+    return peps_workspace_bytes(desc, n, what)
+
+
 def _check_dev(*ts):
     for t in ts:
         if t is not None and not t.is_cuda:
@@ -170,11 +187,16 @@ def peps_grad_batch(desc: Desc, theta, configs, status=None):
 
 
 def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measure=True, want_O=True,
-                      n_accept=None, status=None, out=None):
+                      n_accept=None, status=None, out=None, sweep_counter=None, ws=None):
     """Runs n_sweeps sweeps in place on `configs`.  Returns a dict with
     log_abs / sign / e_loc [n_sweeps, n] and O [n_sweeps, n, nnz] (when
     measured), n_accept [n, 3] and status.  `out` may supply preallocated
-    output tensors with those keys."""
+    output tensors with those keys.  `sweep_counter` (int64 [1] on the
+    device, optional) is added to sweep0 on the device and advanced by
+    n_sweeps, which makes the call replayable from a captured graph.  `ws`
+    (uint8 device tensor of at least workspace_bytes(desc, n, "sweep")
+    bytes, optional) replaces the shared workspace cache; a captured call
+    should own its workspace so that no later call can reallocate it."""
     theta = _theta(desc, theta)
     configs = _configs(desc, configs)
     _check_dev(theta, configs)
@@ -190,9 +212,13 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
     if n_accept is None:
         n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
     status = new_status(dev) if status is None else status
-    ws = _ws("chain", peps_workspace_bytes(desc, n, _lib.WS_SWEEP), dev)
+    if sweep_counter is not None:
+        _check_dev(sweep_counter)
+        if sweep_counter.dtype != torch.int64 or sweep_counter.numel() != 1:
+            raise ValueError("sweep_counter must be a one-element int64 device tensor")
+    ws = _own_ws(ws, "chain", peps_workspace_bytes(desc, n, _lib.WS_SWEEP), dev)
     code = LIB.peps_sample_sweep(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(seed), int(sweep0),
-                                 int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
+                                 _ptr(sweep_counter), int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
                                  _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(n_accept), _ptr(status),
                                  _ptr(ws), ws.numel(), _stream())
     _raise(code, "peps_sample_sweep")
@@ -202,10 +228,11 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
 
 
 def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, weights=None, want_g=True,
-                theta=None, status=None):
+                theta=None, status=None, ws=None):
     """(dtheta [N_p], g [N_p] or None, stats [4] = (Ebar, |r|, iters, |b|), status).
     When `theta` (float64 [N_p], device) is given it is updated in place:
-    theta += dtheta."""
+    theta += dtheta.  `ws`: optional caller-owned workspace of at least
+    workspace_bytes(desc, n_s, "sr") bytes."""
     configs = _configs(desc, configs)
     n_s = configs.shape[0]
     if O_rows.dtype != torch.float64 or O_rows.shape != (n_s, peps_orow_count(desc)) or not O_rows.is_contiguous():
@@ -221,7 +248,7 @@ def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, we
     g = torch.empty(n_p, dtype=torch.float64, device=dev) if want_g else None
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
     status = new_status(dev) if status is None else status
-    ws = _ws("sr", peps_workspace_bytes(desc, n_s, _lib.WS_SR), dev)
+    ws = _own_ws(ws, "sr", peps_workspace_bytes(desc, n_s, _lib.WS_SR), dev)
     code = LIB.sr_cg_solve(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights),
                            _ptr(e_loc.contiguous()), float(tau), float(eps), int(max_iter), float(rtol),
                            _ptr(dtheta), _ptr(g), _ptr(theta), _ptr(stats), _ptr(status), _ptr(ws), ws.numel(),

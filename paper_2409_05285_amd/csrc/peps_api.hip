@@ -271,9 +271,9 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
 }
 
 peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n_chains, uint8_t* configs,
-                              uint64_t seed, uint64_t sweep0, int32_t n_sweeps, double* log_abs, int8_t* sign,
-                              double* e_loc, double* O_rows, int32_t* n_accept, int32_t* status, void* ws,
-                              size_t ws_bytes, peps_stream_t stream) {
+                              uint64_t seed, uint64_t sweep0, uint64_t* sweep_counter, int32_t n_sweeps,
+                              double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int32_t* n_accept,
+                              int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream) {
   Prob P;
   peps_status s = common_checks(d, P, n_chains, theta, configs, ws, ws_bytes, PEPS_WS_SWEEP);
   if (s != PEPS_OK || n_chains == 0) return s;
@@ -291,9 +291,9 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       if (s != PEPS_OK) return s;
     }
     for (int r = 0; r < P.L1; ++r) {
-      TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, t32, configs, seed, g, w, n_accept, status, st));
+      TIMED(PEPS_K_MOVES1, launch_moves1(P, n, r, theta, t32, configs, seed, g, sweep_counter, w, n_accept, status, st));
       if (r < P.L1 - 1) {
-        TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, t32, configs, seed, g, w, n_accept, status, st));
+        TIMED(PEPS_K_MOVES2, launch_moves2(P, n, r, theta, t32, configs, seed, g, sweep_counter, w, n_accept, status, st));
         TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
       }
     }
@@ -308,6 +308,7 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       if (s != PEPS_OK) return s;
     }
   }
+  if (sweep_counter && n_sweeps > 0) HIP_TRY(launch_advance_counter(sweep_counter, (uint64_t)n_sweeps, st));
   return PEPS_OK;
 }
 

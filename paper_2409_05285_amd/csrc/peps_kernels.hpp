@@ -19,12 +19,14 @@ hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* t
 // Strip kernels.  theta is the FP64 parameter vector, t32 its FP32 copy
 // (read instead of theta when P.mixed is set).
 hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStream_t st);
+// Adds n to the device sweep counter (one thread, vector store).
+hipError_t launch_advance_counter(uint64_t* ctr, uint64_t n, hipStream_t st);
 hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
-                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
-                         hipStream_t st);
+                         uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
+                         int32_t* status, hipStream_t st);
 hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
-                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
-                         hipStream_t st);
+                         uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
+                         int32_t* status, hipStream_t st);
 hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
                         double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st);
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,

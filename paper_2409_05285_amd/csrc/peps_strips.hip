@@ -187,8 +187,10 @@ __device__ inline Env lstep2_t(const Prob& P, StripShared<T>& sh, const StripBuf
 // Metropolis passes inside row r: horizontal exchanges, then site moves.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
-                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
-                                               int32_t* status) {
+                                               uint64_t seed, uint64_t gsweep0, const uint64_t* gctr, double* ws,
+                                               int32_t* n_accept, int32_t* status) {
+  // global sweep index: the host's base plus the device counter, if any
+  const uint64_t gsweep = gsweep0 + (gctr ? gctr[0] : 0ull);
   __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
@@ -286,8 +288,10 @@ __global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restric
 // Metropolis vertical exchanges between rows r and r+1 (two-row strip).
 template <typename T>
 __global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
-                                               uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept,
-                                               int32_t* status) {
+                                               uint64_t seed, uint64_t gsweep0, const uint64_t* gctr, double* ws,
+                                               int32_t* n_accept, int32_t* status) {
+  // global sweep index: the host's base plus the device counter, if any
+  const uint64_t gsweep = gsweep0 + (gctr ? gctr[0] : 0ull);
   __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
@@ -486,7 +490,18 @@ __global__ void k_theta32(const double* __restrict__ theta, float* __restrict__ 
     t32[i] = (float)theta[i];
 }
 
+// Device sweep counter: advanced once per call, after every kernel of the
+// call has read it (stream order), so graph replays draw fresh numbers.
+__global__ void k_advance_counter(uint64_t* ctr, uint64_t n) {
+  if (threadIdx.x == 0) ctr[0] = ctr[0] + n;
+}
+
 // ---------------------------------------------------------------------------
+hipError_t launch_advance_counter(uint64_t* ctr, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(64), 0, st, ctr, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStream_t st) {
   const int blocks = (int)((P.np + 255) / 256 < 1024 ? (P.np + 255) / 256 : 1024);
   hipLaunchKernelGGL(k_theta32, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, theta, t32, P.np);
@@ -494,25 +509,25 @@ hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStr
 }
 
 hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
-                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
-                         hipStream_t st) {
+                         uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
+                         int32_t* status, hipStream_t st) {
   if (P.mixed)
-    hipLaunchKernelGGL(k_moves1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, ws, n_accept,
+    hipLaunchKernelGGL(k_moves1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, gctr, ws, n_accept,
                        status);
   else
-    hipLaunchKernelGGL(k_moves1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept,
+    hipLaunchKernelGGL(k_moves1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, gctr, ws, n_accept,
                        status);
   return hipGetLastError();
 }
 
 hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
-                         uint64_t seed, uint64_t gsweep, double* ws, int32_t* n_accept, int32_t* status,
-                         hipStream_t st) {
+                         uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
+                         int32_t* status, hipStream_t st) {
   if (P.mixed)
-    hipLaunchKernelGGL(k_moves2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, ws, n_accept,
+    hipLaunchKernelGGL(k_moves2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, seed, gsweep, gctr, ws, n_accept,
                        status);
   else
-    hipLaunchKernelGGL(k_moves2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, ws, n_accept,
+    hipLaunchKernelGGL(k_moves2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, seed, gsweep, gctr, ws, n_accept,
                        status);
   return hipGetLastError();
 }

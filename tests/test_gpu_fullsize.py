@@ -1,0 +1,124 @@
+"""Parity at the throughput workload's full size and launch configuration:
+8x8 open-boundary Heisenberg, d^2 = 4, D = 4, chi = 16, 1024 chains, random
+unit-Frobenius tensors (seed 102), diagonal start (seed 7), Philox seed
+20240905, one sweep with fused measurement, then the SR solve with 200 CG
+iterations -- the step `bench.py` times, launched the same way.
+
+The oracle cannot run all 1024 chains in test time, so a fixed sample of
+chains (first, last, both sides of every 256-chain boundary) is recomputed
+one by one on the CPU from the same seeded inputs and compared at the usual
+bars (FP64: configurations and accept counts bit-exact, log|psi| and E_loc
+1e-10, O 1e-9; mixed: 1e-4 and configurations bit-exact away from near-ties).
+The SR solve is checked through properties that hold at any size: the
+gradient g = (1/N) sum_i O_i (E_i - Ebar) and the residual of the normal
+equations (S + eps 1) x = -tau g, both evaluated in NumPy FP64 from the same
+O rows and local energies.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import measure, sampler
+from oracle.sr import dense_O
+from oracle.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+L1 = L2 = 8
+D, CHI, N_CHAINS = 4, 16, 1024
+SEED, GSWEEP = 20240905, 0
+SAMPLED = [0, 1, 255, 256, 511, 512, 767, 768, 1022, 1023]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _sweep(p, mixed):
+    dev = _dev()
+    desc = p.Desc(L1, L2, D, CHI, precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = synth.theta_random_unit(L1, L2, D, 2, seed=102)
+    cfg = synth.configs_diagonal(N_CHAINS, L1 * L2, 2, seed=7)
+    theta_d = torch.tensor(th, device=dev)
+    cfg_d = torch.tensor(cfg, device=dev)
+    res = p.peps_sample_sweep(desc, theta_d, cfg_d, SEED, GSWEEP, 1)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    return desc, th, cfg, cfg_d, res
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fullsize_sweep_sampled_chains(mixed):
+    import paper_2409_05285_amd as p
+    _say("full-size sweep", "mixed" if mixed else "fp64", N_CHAINS, "chains")
+    desc, th, cfg, cfg_d, res = _sweep(p, mixed)
+    lat = Lattice(L1, L2, D=D, chi=CHI)
+    tol_log, tol_e, tol_tie = (1e-4, 1e-4, 1e-4) if mixed else (1e-10, 1e-10, 1e-12)
+    got = cfg_d.cpu().numpy()
+    acc = res["n_accept"].cpu().numpy()
+    la = res["log_abs"].cpu().numpy()[0]
+    e = res["e_loc"].cpu().numpy()[0]
+    O = res["O"].cpu().numpy()[0]
+    compared = 0
+    for ch in SAMPLED:
+        r = sampler.sweep(lat, th, cfg[ch].astype(np.int64), CHI, SEED, ch, GSWEEP, tie_tol=tol_tie)
+        if r["near_ties"]:
+            print("near-tie, chain", ch, r["near_ties"], flush=True)
+            continue
+        compared += 1
+        assert np.array_equal(got[ch], r["S"].astype(np.uint8)), ch
+        assert np.array_equal(acc[ch], r["n_accept"]), (ch, acc[ch], r["n_accept"])
+        m = measure.evaluate(lat, th, r["S"], CHI)
+        assert abs(la[ch] - m["log_abs"]) <= tol_log * max(1.0, abs(m["log_abs"])), (ch, la[ch], m["log_abs"])
+        assert abs(e[ch] - m["e_loc"]) <= tol_e * max(abs(m["e_loc"]), 1.0), (ch, e[ch], m["e_loc"])
+        if mixed:
+            assert np.all(np.abs(O[ch] - m["O"]) <= 1e-4 * np.abs(m["O"]).max()), ch
+        else:
+            assert np.all(np.abs(O[ch] - m["O"]) <= 1e-9 * np.maximum(1.0, np.abs(m["O"]))), ch
+    assert compared >= len(SAMPLED) - 2
+    # every chain: finite outputs and configurations in the sector of the start
+    assert np.all(np.isfinite(la)) and np.all(np.isfinite(e)) and np.all(np.isfinite(O))
+    s, sp = got // 2, got % 2
+    assert np.array_equal(s.sum(axis=1), sp.sum(axis=1))
+
+
+def test_fullsize_sr_solve_properties():
+    import paper_2409_05285_amd as p
+    _say("full-size SR", N_CHAINS, "samples")
+    desc, th, cfg, cfg_d, res = _sweep(p, False)
+    tau, eps = 0.02, 1e-4
+    O_d, e_d = res["O"][0], res["e_loc"][0]
+    dth, g, stats, st = p.sr_cg_solve(desc, cfg_d, O_d, e_d, tau, eps, 200, 1e-10)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    lat = Lattice(L1, L2, D=D, chi=CHI)
+    Of = dense_O(lat, cfg_d.cpu().numpy(), O_d.cpu().numpy())
+    e = e_d.cpu().numpy()
+    x, g, stats = dth.cpu().numpy(), g.cpu().numpy(), stats.cpu().numpy()
+    n = Of.shape[0]
+    ebar = e.mean()
+    g_ref = Of.T @ ((e - ebar) / n)
+    assert abs(stats[0] - ebar) <= 1e-12 * max(1.0, abs(ebar))
+    assert np.all(np.abs(g - g_ref) <= 1e-11 * np.abs(g_ref).max())
+    b = -tau * g_ref
+    y = Of @ x
+    Ax = Of.T @ ((y - y.mean()) / n) + eps * x
+    true_res = np.linalg.norm(Ax - b)
+    bn = np.linalg.norm(b)
+    assert abs(stats[3] - bn) <= 1e-10 * bn
+    # the recurrence residual the solver reports is the true one up to round-off
+    assert abs(true_res - stats[1]) <= 1e-3 * stats[1] + 1e-9 * bn, (true_res, stats[1], bn)
+    assert true_res < 0.5 * bn
+    # the step is a descent direction of the variational energy: g . x < 0
+    assert float(g_ref @ x) < 0.0
