@@ -2,13 +2,15 @@
 
 Workload (default): 8x8 open-boundary spin-1/2 Heisenberg model, vectorised
 PEPS with d^2 = 4, bond dimension D = 4, boundary dimension chi = 16,
-1024 Markov chains, seeded random site tensors of unit Frobenius norm.
-One step = one Metropolis sweep of every chain + measurement of each chain's
-final configuration (log|psi|, E_loc, O row) + stochastic-reconfiguration
-solve by conjugate gradient on those samples + the parameter update.
-Metric: samples per second (one sample = one chain's sweep + measurement).
+1024 Markov chains x 200 sweeps per SR step, seeded random site tensors of
+unit Frobenius norm.  One step = 200 Metropolis sweeps of every chain, each
+followed by a measurement of the chain's configuration (log|psi|, E_loc, O
+row), then the stochastic-reconfiguration solve by conjugate gradient on all
+204,800 samples and the parameter update.  Metric: samples per second of
+whole steps (one sample = one chain's sweep + measurement; the SR solve is
+inside the timed region).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cg-iters 200]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweeps 200] [--cg-iters 200]
 
 Both precisions run the same K steps from the same state: FP64 throughout,
 and mixed (FP32 MFMA strip contractions with FP64 QR/SVD, reductions and
@@ -19,9 +21,9 @@ also on the random-tensor state of the timed run.  `value` is the mixed
 path's rate when the cooled-state error is within --tol, else the FP64
 rate.
 
-The same step is also captured once as a HIP graph (device sweep counter,
-caller-owned workspaces) and replayed; `graph_replay` reports that rate
-beside the eager one, which carries the per-kernel HIP-event timings.
+A one-sweep step is also run eagerly and captured once as a HIP graph
+(device sweep counter, caller-owned workspaces) and replayed;
+`graph_replay` reports both rates.
 
 Prints one JSON line.  The CPU baseline is the FP64 oracle (tests only,
 never the product path) timed on a bounded sample on this host.
@@ -199,17 +201,23 @@ def measured_traffic(kernel, L, D, chi, chains):
 
 def run_path(p, torch, desc, theta0, configs0, args, seed):
     """Times args.steps steps of one precision from the given state; returns
-    timings, the per-class kernel profile and the final state."""
+    timings, the per-class kernel profile and the final state.  A step is
+    args.sweeps sweeps of every chain in one library call (the bottom
+    boundaries of each measurement serve the next sweep), with a
+    measurement after every sweep, then one SR solve on all n*sweeps
+    samples and the parameter update."""
     dev = theta0.device
     n = configs0.shape[0]
+    S = args.sweeps
     theta = theta0.clone()
     configs = configs0.clone()
     nnz = p.peps_orow_count(desc)
     out = {
-        "log_abs": torch.empty((1, n), dtype=torch.float64, device=dev),
-        "sign": torch.empty((1, n), dtype=torch.int8, device=dev),
-        "e_loc": torch.empty((1, n), dtype=torch.float64, device=dev),
-        "O": torch.empty((1, n, nnz), dtype=torch.float64, device=dev),
+        "log_abs": torch.empty((S, n), dtype=torch.float64, device=dev),
+        "sign": torch.empty((S, n), dtype=torch.int8, device=dev),
+        "e_loc": torch.empty((S, n), dtype=torch.float64, device=dev),
+        "O": torch.empty((S, n, nnz), dtype=torch.float64, device=dev),
+        "configs": torch.empty((S, n, desc.N), dtype=torch.uint8, device=dev),
     }
     n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
     status = p.new_status(dev)
@@ -217,11 +225,11 @@ def run_path(p, torch, desc, theta0, configs0, args, seed):
     last = {}
 
     def step():
-        res = p.peps_sample_sweep(desc, theta, configs, seed, gsweep[0], 1, n_accept=n_accept, status=status,
-                                  out=out)
-        gsweep[0] += 1
-        _, _, stats, _ = p.sr_cg_solve(desc, configs, res["O"][0], res["e_loc"][0], args.tau, args.eps,
-                                       args.cg_iters, 1e-10, want_g=False, theta=theta, status=status)
+        p.peps_sample_sweep(desc, theta, configs, seed, gsweep[0], S, n_accept=n_accept, status=status, out=out)
+        gsweep[0] += S
+        _, _, stats, _ = p.sr_cg_solve(desc, out["configs"].view(S * n, desc.N), out["O"].view(S * n, nnz),
+                                       out["e_loc"].view(S * n), args.tau, args.eps, args.cg_iters, 1e-10,
+                                       want_g=False, theta=theta, status=status)
         last["stats"] = stats
 
     for _ in range(args.warmup):
@@ -246,15 +254,17 @@ def run_path(p, torch, desc, theta0, configs0, args, seed):
     p.check(status, "timed steps")
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     st = last["stats"].cpu().numpy()
-    acc = n_accept.cpu().numpy().sum(axis=0) / (n * args.steps)
-    return {"ms_per_step": ms_per_step, "samples_per_s": n / (ms_per_step / 1e3), "wall": wall, "prof": prof,
+    acc = n_accept.cpu().numpy().sum(axis=0) / (n * S * args.steps)
+    del out
+    return {"ms_per_step": ms_per_step, "samples_per_s": n * S / (ms_per_step / 1e3), "wall": wall, "prof": prof,
             "stats": st, "accept": acc, "theta": theta, "configs": configs}
 
 
 def graph_rate(p, torch, desc, theta0, configs0, args, seed):
-    """The same step captured once in a HIP graph (caller-owned workspaces,
-    device sweep counter) and replayed args.steps times after args.warmup
-    eager steps; returns ms per replayed step."""
+    """A one-sweep step (sweep, measurement, SR on those n samples, update)
+    run eagerly and, captured once in a HIP graph (caller-owned workspaces,
+    device sweep counter), replayed: ms per step of both, args.steps each
+    after args.warmup eager steps."""
     dev = theta0.device
     n = configs0.shape[0]
     nnz = p.peps_orow_count(desc)
@@ -276,25 +286,31 @@ def graph_rate(p, torch, desc, theta0, configs0, args, seed):
         p.sr_cg_solve(desc, configs, out["O"][0], out["e_loc"][0], args.tau, args.eps, args.cg_iters, 1e-10,
                       want_g=False, theta=theta, status=status, ws=ws_sr)
 
+    def timed(fn, k):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(k):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / k
+
+    k = max(args.steps, 3)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    eager_ms = timed(step, k)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        graph.replay()
-    ev1.record()
-    torch.cuda.synchronize()
+    graph_ms = timed(graph.replay, k)
     p.check(status, "graph replays")
-    ms = ev0.elapsed_time(ev1) / args.steps
     del graph
-    return {"ms_per_step": round(ms, 3), "samples_per_s": round(n / (ms / 1e3), 2),
-            "sweeps_replayed": int(ctr.item())}
+    return {"eager_ms_per_step": round(eager_ms, 3), "graph_ms_per_step": round(graph_ms, 3),
+            "graph_samples_per_s": round(n / (graph_ms / 1e3), 2), "steps_each": k,
+            "sweeps_run": int(ctr.item())}
 
 
 def energy_error(p, torch, desc64, descmx, theta, configs):
@@ -357,8 +373,9 @@ def eval_rate(p, torch, desc, theta, configs, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=200, help="sweeps (samples per chain) per SR step")
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--D", type=int, default=4)
     ap.add_argument("--chi", type=int, default=16)
@@ -410,8 +427,13 @@ def main():
                           "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}), flush=True)
         return
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     r64 = run_path(p, torch, desc64, theta0, configs0, args, seed)
+    progress(f"fp64 path: {r64['ms_per_step']:.1f} ms per step")
     rmx = run_path(p, torch, descmx, theta0, configs0, args, seed)
+    progress(f"mixed path: {rmx['ms_per_step']:.1f} ms per step")
     # energy error on the FP64 path's final samples and parameters, and on a
     # cooled (physical) state
     err_random = energy_error(p, torch, desc64, descmx, r64["theta"], r64["configs"])
@@ -419,8 +441,10 @@ def main():
                                seed)
     err_cooled = energy_error(p, torch, desc64, descmx, th_c, cfg_c)
     mixed_ok = err_cooled["mean_E_rel"] <= args.tol
+    progress("energy error checks done")
     graph64 = graph_rate(p, torch, desc64, theta0, configs0, args, seed)
     graphmx = graph_rate(p, torch, descmx, theta0, configs0, args, seed)
+    progress("graph replays done")
     eval64 = eval_rate(p, torch, desc64, r64["theta"], r64["configs"])
     evalmx = eval_rate(p, torch, descmx, r64["theta"], r64["configs"])
     best = rmx if mixed_ok else r64
@@ -449,7 +473,7 @@ def main():
     nnz = p.peps_orow_count(desc64)
     sr_ms = prof["sr"][0] / args.steps
     cg_it = int(best["stats"][2])
-    sr_bytes = (2 * cg_it + 1) * n * nnz * 8
+    sr_bytes = (2 * cg_it + 1) * n * args.sweeps * nnz * 8
     sr_roof = {"bound": "hbm", "achieved": round(sr_bytes / (sr_ms / 1e3) / 1e9, 1), "peak": MI355X_HBM_GBS,
                "unit": "GB/s", "frac": round(sr_bytes / (sr_ms / 1e3) / 1e9 / MI355X_HBM_GBS, 4),
                "kernel": "sr_cg_solve", "ms_per_solve": round(sr_ms, 3), "cg_iters": cg_it}
@@ -475,10 +499,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed_ok else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{L1}x{L2} Heisenberg OBC, d^2=4, D={D}, chi={chi}, {n} chains, random "
-                               f"unit-Frobenius tensors; step = 1 sweep + measurement + SR CG "
-                               f"({args.cg_iters} it max) + update",
-                   "lattice": [L1, L2], "D": D, "chi": chi, "chains": n, "sweeps_per_step": 1,
+        "config": {"workload": f"{L1}x{L2} Heisenberg OBC, d^2=4, D={D}, chi={chi}, {n} chains x "
+                               f"{args.sweeps} sweeps per SR step, random unit-Frobenius tensors; step = "
+                               f"{args.sweeps} sweeps each followed by a measurement + SR CG on all "
+                               f"{n * args.sweeps} samples ({args.cg_iters} it max) + update",
+                   "lattice": [L1, L2], "D": D, "chi": chi, "chains": n, "sweeps_per_step": args.sweeps,
                    "cg_iters": args.cg_iters,
                    "precision": "mixed (FP32 MFMA strips, FP64 QR/SVD/SR)" if mixed_ok else "fp64"},
         "roofline": roof,
@@ -493,10 +518,12 @@ def main():
                          "random": dict(err_random, state="random unit-Frobenius tensors after the timed steps")},
         "eval_samples_per_s": {"fp64": round(eval64, 1), "mixed": round(evalmx, 1)},
         "graph_replay": {"fp64": graph64, "mixed": graphmx,
-                         "note": "the same step captured once as a HIP graph and replayed"},
+                         "note": "one-sweep step (1024 samples, SR on them) eager vs captured once as a HIP "
+                                 "graph and replayed"},
         "host_wall_ms_per_step": round(best["wall"] * 1e3 / args.steps, 3),
     }
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(L1, L2, D, chi, seed_theta, seed, args.cg_iters)
     print(json.dumps(line), flush=True)
 

@@ -137,11 +137,15 @@ peps_status peps_grad_batch(const peps_desc* desc, const double* theta, int32_t 
    call captured once in a HIP graph draws fresh uniforms on every replay.
    configs [n_chains][N] in/out.  Per sweep k and chain ch (index k*n_chains+ch):
    log_abs, sign, e_loc [n_sweeps*n_chains], O_rows [n_sweeps*n_chains][nnz];
-   any of these may be NULL (then not written).  n_accept [n_chains][3] int32
-   is incremented by the accepted moves of each type (may be NULL). */
+   any of these may be NULL (then not written).  sample_configs
+   [n_sweeps*n_chains][N] uint8 (may be NULL) receives the configuration each
+   measurement was taken on, the row order of O_rows, so that the samples of
+   several sweeps can go to sr_cg_solve together.  n_accept [n_chains][3]
+   int32 is incremented by the accepted moves of each type (may be NULL). */
 peps_status peps_sample_sweep(const peps_desc* desc, const double* theta, int32_t n_chains,
                               uint8_t* configs, uint64_t seed, uint64_t sweep0,
-                              uint64_t* sweep_counter, int32_t n_sweeps, double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
+                              uint64_t* sweep_counter, int32_t n_sweeps, double* log_abs,
+                              int8_t* sign, double* e_loc, double* O_rows, uint8_t* sample_configs,
                               int32_t* n_accept, int32_t* status, void* ws, size_t ws_bytes,
                               peps_stream_t stream);
 

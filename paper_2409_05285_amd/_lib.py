@@ -62,8 +62,8 @@ def _load():
                                     c_size_t, c_void_p]
     lib.peps_grad_batch.restype = c_int32
     lib.peps_sample_sweep.argtypes = [P, c_void_p, c_int32, c_void_p, c_uint64, c_uint64, c_void_p, c_int32, c_void_p,
-                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
-                                      c_void_p]
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]
     lib.peps_sample_sweep.restype = c_int32
     lib.sr_cg_solve.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32,
                                 c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,

@@ -187,30 +187,44 @@ def peps_grad_batch(desc: Desc, theta, configs, status=None):
 
 
 def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measure=True, want_O=True,
-                      n_accept=None, status=None, out=None, sweep_counter=None, ws=None):
+                      n_accept=None, status=None, out=None, sweep_counter=None, ws=None, want_configs=False):
     """Runs n_sweeps sweeps in place on `configs`.  Returns a dict with
     log_abs / sign / e_loc [n_sweeps, n] and O [n_sweeps, n, nnz] (when
-    measured), n_accept [n, 3] and status.  `out` may supply preallocated
-    output tensors with those keys.  `sweep_counter` (int64 [1] on the
-    device, optional) is added to sweep0 on the device and advanced by
-    n_sweeps, which makes the call replayable from a captured graph.  `ws`
-    (uint8 device tensor of at least workspace_bytes(desc, n, "sweep")
-    bytes, optional) replaces the shared workspace cache; a captured call
-    should own its workspace so that no later call can reallocate it."""
+    measured), configs [n_sweeps, n, N] (the configuration of every
+    measurement, when want_configs), n_accept [n, 3] and status.  `out` may
+    supply preallocated output tensors with those keys (checked for shape,
+    dtype and contiguity).  `sweep_counter` (int64 [1] on the device,
+    optional) is added to sweep0 on the device and advanced by n_sweeps,
+    which makes the call replayable from a captured graph.  `ws` (uint8
+    device tensor of at least workspace_bytes(desc, n, "sweep") bytes,
+    optional) replaces the shared workspace cache; a captured call should
+    own its workspace so that no later call can reallocate it."""
     theta = _theta(desc, theta)
     configs = _configs(desc, configs)
     _check_dev(theta, configs)
     n = configs.shape[0]
     dev = theta.device
     res = {} if out is None else dict(out)
+    shapes = {"log_abs": ((n_sweeps, n), torch.float64), "sign": ((n_sweeps, n), torch.int8),
+              "e_loc": ((n_sweeps, n), torch.float64),
+              "O": ((n_sweeps, n, peps_orow_count(desc)), torch.float64),
+              "configs": ((n_sweeps, n, desc.N), torch.uint8)}
     if measure:
-        res.setdefault("log_abs", torch.empty((n_sweeps, n), dtype=torch.float64, device=dev))
-        res.setdefault("sign", torch.empty((n_sweeps, n), dtype=torch.int8, device=dev))
-        res.setdefault("e_loc", torch.empty((n_sweeps, n), dtype=torch.float64, device=dev))
+        for k in ("log_abs", "sign", "e_loc"):
+            res.setdefault(k, torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev))
         if want_O:
-            res.setdefault("O", torch.empty((n_sweeps, n, peps_orow_count(desc)), dtype=torch.float64, device=dev))
+            res.setdefault("O", torch.empty(shapes["O"][0], dtype=torch.float64, device=dev))
+        if want_configs:
+            res.setdefault("configs", torch.empty(shapes["configs"][0], dtype=torch.uint8, device=dev))
+    for k, t in res.items():
+        if k in shapes and t is not None:
+            if tuple(t.shape) != shapes[k][0] or t.dtype != shapes[k][1] or not t.is_contiguous() or t.device != dev:
+                raise ValueError("out[%r] must be a contiguous %s device tensor of shape %s"
+                                 % (k, shapes[k][1], shapes[k][0]))
     if n_accept is None:
         n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+    elif n_accept.dtype != torch.int32 or tuple(n_accept.shape) != (n, 3) or not n_accept.is_contiguous():
+        raise ValueError("n_accept must be a contiguous int32 [n, 3] device tensor")
     status = new_status(dev) if status is None else status
     if sweep_counter is not None:
         _check_dev(sweep_counter)
@@ -219,8 +233,8 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
     ws = _own_ws(ws, "chain", peps_workspace_bytes(desc, n, _lib.WS_SWEEP), dev)
     code = LIB.peps_sample_sweep(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(seed), int(sweep0),
                                  _ptr(sweep_counter), int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
-                                 _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(n_accept), _ptr(status),
-                                 _ptr(ws), ws.numel(), _stream())
+                                 _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(res.get("configs")),
+                                 _ptr(n_accept), _ptr(status), _ptr(ws), ws.numel(), _stream())
     _raise(code, "peps_sample_sweep")
     res["n_accept"] = n_accept
     res["status"] = status

@@ -272,13 +272,14 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
 
 peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n_chains, uint8_t* configs,
                               uint64_t seed, uint64_t sweep0, uint64_t* sweep_counter, int32_t n_sweeps,
-                              double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int32_t* n_accept,
-                              int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream) {
+                              double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
+                              uint8_t* sample_configs, int32_t* n_accept, int32_t* status, void* ws,
+                              size_t ws_bytes, peps_stream_t stream) {
   Prob P;
   peps_status s = common_checks(d, P, n_chains, theta, configs, ws, ws_bytes, PEPS_WS_SWEEP);
   if (s != PEPS_OK || n_chains == 0) return s;
   if (n_sweeps < 0) return PEPS_ERR_ARG;
-  const bool measure_any = log_abs || sign || e_loc || O_rows;
+  const bool measure_any = log_abs || sign || e_loc || O_rows || sample_configs;
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
   const int n = n_chains;
@@ -306,6 +307,8 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       s = measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, O_rows ? O_rows + off * P.nnz : nullptr, off,
                   status, st);
       if (s != PEPS_OK) return s;
+      if (sample_configs)
+        HIP_TRY(launch_copy_bytes(sample_configs + off * P.N, configs, (int64_t)n * P.N, st));
     }
   }
   if (sweep_counter && n_sweeps > 0) HIP_TRY(launch_advance_counter(sweep_counter, (uint64_t)n_sweeps, st));

@@ -19,6 +19,9 @@ hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* t
 // Strip kernels.  theta is the FP64 parameter vector, t32 its FP32 copy
 // (read instead of theta when P.mixed is set).
 hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStream_t st);
+// dst[0..n) = src[0..n) on the stream (a copy kernel: no copy or memset
+// nodes when captured in a graph).
+hipError_t launch_copy_bytes(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);
 // Adds n to the device sweep counter (one thread, vector store).
 hipError_t launch_advance_counter(uint64_t* ctr, uint64_t n, hipStream_t st);
 hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,

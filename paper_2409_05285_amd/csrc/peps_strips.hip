@@ -496,7 +496,23 @@ __global__ void k_advance_counter(uint64_t* ctr, uint64_t n) {
   if (threadIdx.x == 0) ctr[0] = ctr[0] + n;
 }
 
+__global__ void k_copy_bytes(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n16 = ((uintptr_t)dst % 16 == 0 && (uintptr_t)src % 16 == 0) ? n / 16 : 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+  for (int64_t i = n16 * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
+hipError_t launch_copy_bytes(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n / 16 + 255) / 256;
+  hipLaunchKernelGGL(k_copy_bytes, dim3(blocks < 1 ? 1 : (blocks > 1024 ? 1024 : (int)blocks)), dim3(256), 0, st,
+                     dst, src, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_advance_counter(uint64_t* ctr, uint64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(64), 0, st, ctr, n);
   return hipGetLastError();

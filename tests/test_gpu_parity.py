@@ -391,3 +391,33 @@ def test_hubbard_sweep_bit_exact():
         m = meas[-1]
         assert abs(e[-1, ch] - m["e_loc"]) <= 1e-10 * max(abs(m["e_loc"]), 1.0)
     assert compared >= 1
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_multi_sweep_call_matches_single_sweeps(mixed):
+    """One call of n sweeps (bottom boundaries of each measurement reused by
+    the next sweep) against n calls of one sweep (recomputed each call):
+    bit-identical configurations, per-sweep sample configurations,
+    measurements and accept counts."""
+    dev = _dev()
+    p, lat, desc, th = _setup(4, 5, 3, 5, theta="random", seed=41, mixed=mixed)
+    cfg = synth.configs_diagonal(6, lat.N, 2, seed=42)
+    seed, sweep0, ns = 9090, 11, 3
+    _say("multi-sweep call", "mixed" if mixed else "fp64")
+    theta_d = torch.tensor(th, device=dev)
+    cfg_a = torch.tensor(cfg, device=dev)
+    ra = p.peps_sample_sweep(desc, theta_d, cfg_a, seed, sweep0, ns, want_configs=True)
+    cfg_b = torch.tensor(cfg, device=dev)
+    acc_b = torch.zeros((cfg.shape[0], 3), dtype=torch.int32, device=dev)
+    rb = []
+    for k in range(ns):
+        r = p.peps_sample_sweep(desc, theta_d, cfg_b, seed, sweep0 + k, 1, n_accept=acc_b, want_configs=True)
+        rb.append({key: r[key].clone() for key in ("log_abs", "e_loc", "O", "configs")})
+    torch.cuda.synchronize()
+    assert p.check(ra["status"]) == 0
+    assert torch.equal(cfg_a, cfg_b)
+    assert torch.equal(ra["n_accept"], acc_b)
+    for k in range(ns):
+        for key in ("log_abs", "e_loc", "O", "configs"):
+            assert torch.equal(ra[key][k], rb[k][key][0]), (k, key)
+    assert torch.equal(ra["configs"][ns - 1], cfg_a)
