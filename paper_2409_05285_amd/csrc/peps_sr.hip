@@ -17,6 +17,7 @@
 namespace peps {
 
 constexpr int SR_NT = 256;
+constexpr int YB = 128;   // blocks of the weighted mean of y
 
 struct SrDev {
   int64_t n_s, nnz, np;
@@ -39,6 +40,7 @@ struct SrDev {
   double* x;
   double* g;
   double* part;          // [2][n_red]
+  double* ypart;         // [YB] block partials of sum_i w_i y_i
   double* scal;          // [max_iter + 2][4]: rr, stop, pAp, alpha
   double* misc;          // [8]: ebar, bnorm, ybar, ...
 };
@@ -78,14 +80,18 @@ __global__ void __launch_bounds__(SR_NT) k_sr_weights(SrDev D, const double* wei
   }
 }
 
-// Fixed-order weighted mean of y (single block): misc[2] = sum_i w_i y_i.
+// Weighted mean of y in two fixed-order stages: block b sums its slice of
+// w_i y_i into ypart[b]; the scatter kernel adds the YB partials.
 __global__ void __launch_bounds__(SR_NT) k_sr_ymean(SrDev D, int it) {
   __shared__ double red[SR_NT];
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
+  const int64_t per = (D.n_s + YB - 1) / YB;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < D.n_s ? i0 + per : D.n_s;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < D.n_s; i += SR_NT) s += D.w[i] * D.y[i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += SR_NT) s += D.w[i] * D.y[i];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) D.misc[2] = s;
+  if (threadIdx.x == 0) D.ypart[blockIdx.x] = s;
 }
 
 // y_i = O_i . v for GR sample rows per workgroup.  Threads stride over the
@@ -115,7 +121,33 @@ __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, i
 #pragma unroll
   for (int r = 0; r < GR; ++r) acc[r] = 0.0;
   int st = 0;
-  for (int e = tid; e < D.nnz; e += SR_NT) {
+  int e = tid;
+  // four entries per thread and pass, loads issued before the products
+  // (same summation order as one entry per pass)
+  constexpr int EU = 4;
+  for (; e + (EU - 1) * SR_NT < D.nnz; e += EU * SR_NT) {
+    int sts[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      while (e + u * SR_NT >= soff[st + 1]) ++st;
+      sts[u] = st;
+    }
+    double o[EU][GR], x[EU][GR];
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const int eu = e + u * SR_NT;
+        o[u][r] = r < nr ? D.O[(row0 + r) * D.nnz + eu] : 0.0;
+        x[u][r] = r < nr ? v[vb[r][sts[u]] + eu] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+#pragma unroll
+      for (int r = 0; r < GR; ++r)
+        if (r < nr) acc[r] += o[u][r] * x[u][r];
+  }
+  for (; e < D.nnz; e += SR_NT) {
     while (e >= soff[st + 1]) ++st;
 #pragma unroll
     for (int r = 0; r < GR; ++r)
@@ -137,15 +169,18 @@ __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, i
 
 // zpart[chunk][k] = sum_{i in chunk} t_i O_i[e] at k = base[e] + S_i * bsz[e],
 // with t_i = w_i (src_i - mean): src = e_loc (mode 0, mean misc[0]) or
-// y (mode 1, mean misc[2]); mode 2: t_i = e_i (the cotangent, no weights).
+// y (mode 1, mean from the YB partials of k_sr_ymean); mode 2: t_i = e_i (the
+// cotangent, no weights).
 template <int D2>
 __global__ void __launch_bounds__(SR_NT) k_sr_scatter(SrDev D, int mode, int it) {
+  __shared__ double red[SR_NT];
   if (it >= 0 && D.scal[it * 4 + 1] != 0.0) return;
+  double mean = mode == 0 ? D.misc[0] : 0.0;
+  if (mode == 1) mean = block_sum(threadIdx.x < YB ? D.ypart[threadIdx.x] : 0.0, red);
   const int64_t e = (int64_t)blockIdx.x * SR_NT + threadIdx.x;
   const int chunk = blockIdx.y;
   if (e >= D.nnz) return;
   const double* src = mode == 1 ? D.y : D.e;
-  const double mean = mode == 0 ? D.misc[0] : (mode == 1 ? D.misc[2] : 0.0);
   const int st = D.site[e];
   double acc[D2];
 #pragma unroll
@@ -153,7 +188,27 @@ __global__ void __launch_bounds__(SR_NT) k_sr_scatter(SrDev D, int mode, int it)
   const int64_t i0 = (int64_t)chunk * D.rows_per_chunk;
   int64_t i1 = i0 + D.rows_per_chunk;
   if (i1 > D.n_s) i1 = D.n_s;
-  for (int64_t i = i0; i < i1; ++i) {
+  int64_t i = i0;
+  // eight rows per pass, loads issued before the accumulation (same order
+  // of summation as one row per pass)
+  constexpr int UR = 8;
+  for (; i + UR <= i1; i += UR) {
+    double o[UR], t[UR];
+    int sv[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      o[u] = D.O[(i + u) * D.nnz + e];
+      sv[u] = D.configs[(i + u) * D.N + st];
+      t[u] = mode == 2 ? src[i + u] : D.w[i + u] * (src[i + u] - mean);
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const double v = t[u] * o[u];
+#pragma unroll
+      for (int q = 0; q < D2; ++q) acc[q] += (sv[u] == q) ? v : 0.0;
+    }
+  }
+  for (; i < i1; ++i) {
     const double t = mode == 2 ? src[i] : D.w[i] * (src[i] - mean);
     const double v = t * D.O[i * D.nnz + e];
     const int Si = D.configs[i * D.N + st];
@@ -346,6 +401,7 @@ static void sr_layout(const Prob& P, int64_t n_s, SrDev& D, size_t* bytes, char*
   size_t o_part = take(sizeof(double) * 2 * D.n_red);
   size_t o_scal = take(sizeof(double) * 4 * (size_t)(SR_MAX_ITER + 2));
   size_t o_misc = take(sizeof(double) * 8);
+  size_t o_ypart = take(sizeof(double) * YB);
   *bytes = off;
   if (ws) {
     D.base = (const int32_t*)(ws + o_base);
@@ -364,6 +420,7 @@ static void sr_layout(const Prob& P, int64_t n_s, SrDev& D, size_t* bytes, char*
     D.part = (double*)(ws + o_part);
     D.scal = (double*)(ws + o_scal);
     D.misc = (double*)(ws + o_misc);
+    D.ypart = (double*)(ws + o_ypart);
   }
 }
 
@@ -401,7 +458,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
   const int gb = (int)((n_s + GR - 1) / GR);
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL(k_sr_gather, dim3(gb), dim3(SR_NT), 0, st, D, (const double*)D.p, it);
-    hipLaunchKernelGGL(k_sr_ymean, dim3(1), dim3(SR_NT), 0, st, D, it);
+    hipLaunchKernelGGL(k_sr_ymean, dim3(YB), dim3(SR_NT), 0, st, D, it);
     scatter(1, it);
     hipLaunchKernelGGL(k_sr_reduce, dim3(D.n_red), dim3(SR_NT), 0, st, D, 1, tau, eps, it);
     hipLaunchKernelGGL(k_sr_update, dim3(D.n_red), dim3(SR_NT), 0, st, D, it, status);
