@@ -12,8 +12,6 @@ using namespace peps;
 
 namespace {
 
-constexpr size_t LDS_LIMIT = 160 * 1024;   // gfx950 LDS per workgroup
-constexpr size_t STATIC_LDS_COMPRESS = 16 * 1024;
 
 bool desc_ok(const peps_desc* d) {
   if (!d) return false;
@@ -76,7 +74,12 @@ Prob make_prob(const peps_desc* d) {
   P.off_tmp = off;   off += pad(P.BS);
   P.off_R = off;     off += pad((int64_t)(P.L2 + 1) * P.ES);
   P.off_L = off;     off += pad(4 * (int64_t)P.ES);
-  P.off_X = off;     off += pad(2 * (int64_t)P.XS);
+  {
+    // strip intermediates; also the general compression kernel's work
+    // matrices when they exceed its LDS
+    const int64_t xs = 2 * (int64_t)P.XS, cs = (int64_t)(compress_dyn_lds(P) / sizeof(double));
+    P.off_X = off;   off += pad(xs > cs ? xs : cs);
+  }
   P.off_epart = off; off += pad(2 * P.L1 + 2);
   P.off_tau = off;   off += pad((int64_t)P.L2 * P.chi * P.D);
   P.mixed = d->precision == PEPS_PREC_MIXED;
@@ -92,8 +95,9 @@ Prob make_prob(const peps_desc* d) {
 
 // Checks that the compiled tile limits hold for the device path.
 peps_status device_support(const peps_desc* d, const Prob& P) {
-  if ((int64_t)P.chi * P.D > 255) return PEPS_ERR_UNSUPPORTED;
-  if (compress_dyn_lds(P) + STATIC_LDS_COMPRESS > LDS_LIMIT) return PEPS_ERR_UNSUPPORTED;
+  (void)d;
+  if ((int64_t)P.chi * P.D > CD_MAX) return PEPS_ERR_UNSUPPORTED;   // compression column arrays
+  if (P.chi > 255) return PEPS_ERR_UNSUPPORTED;                    // compressed bond table (8 bits)
   return PEPS_OK;
 }
 

@@ -9,7 +9,13 @@
 namespace peps {
 
 constexpr int SR_MAX_ITER = 4096;
+// Largest chi * D of the general compression kernel (its per-column LDS
+// arrays), and the dynamic LDS it may use before its work matrices move to
+// the workspace.
+constexpr int CD_MAX = 512;
+constexpr size_t COMPRESS_DYN_LDS_MAX = 128 * 1024;
 
+// Bytes of the dense work matrices of the general compression kernel.
 size_t compress_dyn_lds(const Prob& P);
 bool compress2_supported(const Prob& P);
 hipError_t launch_compress2(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,

@@ -62,9 +62,14 @@ def test_workspace_and_errors():
     # a valid call with n = 0 is a no-op that needs no device
     ok = desc.c()
     assert LIB.peps_eval_batch(ctypes.byref(ok), None, 0, None, None, None, None, None, None, 0, None) == 0
-    # shapes beyond the compiled tile limits (chi * D > 255) are refused
-    big = p.Desc(4, 4, 8, 64).c()
+    # shapes beyond the compiled limits (chi * D > 512, or chi > 255) are refused
+    big = p.Desc(4, 4, 8, 72).c()
     assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None) == -2
+    big = p.Desc(4, 4, 1, 256).c()
+    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None) == -2
+    # chi * D = 512 is within them: with n = 0 the call is a no-op
+    edge = p.Desc(4, 4, 8, 64).c()
+    assert LIB.peps_eval_batch(ctypes.byref(edge), None, 0, None, None, None, None, None, None, 0, None) == 0
     # the Hubbard model (d = 4) is accepted: with n = 0 the call is a no-op
     hub = p.Desc(2, 2, 2, 4, d=4, model=1).c()
     assert LIB.peps_eval_batch(ctypes.byref(hub), None, 0, None, None, None, None, None, None, 0, None) == 0

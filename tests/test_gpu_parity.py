@@ -58,6 +58,8 @@ EVAL_CASES = [
     (4, 5, 3, 5, 0.0),     # truncating, ragged bond dimensions
     (4, 4, 2, 3, 0.5),     # J1-J2, truncating
     (8, 8, 4, 16, 0.0),    # the 8x8 throughput lattice
+    (5, 5, 4, 24, 0.0),    # chi D = 96: general compression kernel, work matrices in the workspace
+    (5, 5, 6, 12, 0.5),    # D = 6, J1-J2: general kernel, workspace-resident
 ]
 
 
@@ -107,6 +109,7 @@ SWEEP_CASES = [
     (3, 4, 3, 6, "random", 4, 2),
     (4, 5, 3, 5, "random", 3, 2),
     (8, 8, 4, 16, "random", 2, 1),
+    (5, 5, 4, 24, "random", 2, 1),
 ]
 
 
