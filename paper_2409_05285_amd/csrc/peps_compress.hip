@@ -123,6 +123,10 @@ __device__ inline double rsqrt_nr(double x) {
 }
 // One Newton step (about 1e-14 relative): enough where the value only sets
 // a rotation angle, which the next sweep corrects, and not its orthogonality.
+__device__ inline double rsqrt_nr1(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
 __device__ inline double rcp_nr1(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   return fma(r, fma(-x, r, 1.0), r);
@@ -320,14 +324,32 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
         be = pair_sum(be);
         ga = pair_sum(ga);
         if (ga != 0.0 && ga * ga > (JAC_TOL * JAC_TOL) * (al * be)) {
-          // tangent of the angle from the cotangent of twice the angle; only c
-          // and s = c t must be accurate to the last bit (orthogonality)
-          const double zeta = (be - al) * rcp_nr1(2.0 * ga);
-          const double az = fabs(zeta);
-          const double root = az < 1.0e150 ? sqrt1p_sq1(az) : az;
-          const double t = copysign(rcp_nr1(az + root), zeta);
-          const double c = rsqrt_nr(fma(t, t, 1.0));
-          const double s = c * t;
+          // Rotation (Rutishauser's angle, |theta| <= pi/4) from the double
+          // angle: with d = be - al, e = 2 ga, r = |(d, e)|, cos 2theta =
+          // |d| / r and sin 2theta = sign(d) e / r, so (c, s) is parallel to
+          // ((1 + cos 2theta) / 2, sin 2theta / 2).  That vector is
+          // normalised by a full-precision 1/sqrt, so c^2 + s^2 = 1 to
+          // rounding whatever the error of 1/r, which only perturbs the
+          // angle (the next sweep corrects it).  Out of range of d^2 + e^2:
+          // the same angle through the cotangent.
+          const double d = be - al, e = 2.0 * ga;
+          const double r2 = fma(d, d, e * e);
+          double c, s;
+          if (r2 < 1.0e300 && r2 > 1.0e-300) {
+            const double u = rsqrt_nr1(r2);
+            const double h = fma(0.5 * fabs(d), u, 0.5);
+            const double q = (d >= 0.0 ? 0.5 : -0.5) * e * u;
+            const double w = rsqrt_nr(fma(h, h, q * q));
+            c = h * w;
+            s = q * w;
+          } else {
+            const double zeta = (be - al) * rcp_nr1(2.0 * ga);
+            const double az = fabs(zeta);
+            const double root = az < 1.0e150 ? sqrt1p_sq1(az) : az;
+            const double t = copysign(rcp_nr1(az + root), zeta);
+            c = rsqrt_nr(fma(t, t, 1.0));
+            s = c * t;
+          }
           double* gwi = G + ci * SV_LD;
           double* gwj = G + cj * SV_LD;
 #pragma unroll
