@@ -505,13 +505,15 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       const int bf = j & 1;
       if (grp == (j >> 1)) {                  // owner group of column j
         const int dj = j - r0;                // row r0 + i is below the diagonal when i > dj
-        double s2[2] = {0.0, 0.0};
+        // four interleaved partial sums: dependency chains of QL / 4
+        double s2p[4] = {0.0, 0.0, 0.0, 0.0}, alp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
           const double xi = av[i][COL];
-          s2[0] += i > dj ? xi * xi : 0.0;
-          s2[1] += i == dj ? xi : 0.0;
+          s2p[i & 3] += i > dj ? xi * xi : 0.0;
+          alp[i & 3] += i == dj ? xi : 0.0;
         }
+        double s2[2] = {(s2p[0] + s2p[1]) + (s2p[2] + s2p[3]), (alp[0] + alp[1]) + (alp[2] + alp[3])};
         row16_sum_n<2>(s2);
         const double sigma2 = s2[0], alpha = s2[1];
         double tau = 0.0, scale = 0.0, beta = alpha;
@@ -535,13 +537,15 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
       if (tau != 0.0 && c0 + 1 > j && c0 < n) {   // the group has a column right of j
         // v is streamed from LDS twice (dots, then update) rather than held in
         // 16 more register pairs next to the 32 of the matrix slice
-        double sd[2] = {0.0, 0.0};
+        // two interleaved partial sums per column: chains of QL / 2
+        double sp0[2] = {0.0, 0.0}, sp1[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < QL; ++i) {
           const double vi = qv[bf][r0 + i];
-          sd[0] += vi * av[i][0];
-          sd[1] += vi * av[i][1];
+          sp0[i & 1] += vi * av[i][0];
+          sp1[i & 1] += vi * av[i][1];
         }
+        double sd[2] = {sp0[0] + sp0[1], sp1[0] + sp1[1]};
         row16_sum_n<2>(sd);
         const double tw0 = (c0 > j && c0 < n) ? tau * sd[0] : 0.0;
         const double tw1 = (c0 + 1 > j && c0 + 1 < n) ? tau * sd[1] : 0.0;
