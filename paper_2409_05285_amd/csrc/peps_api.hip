@@ -82,6 +82,8 @@ Prob make_prob(const peps_desc* d) {
   }
   P.off_epart = off; off += pad(2 * P.L1 + 2);
   P.off_tau = off;   off += pad((int64_t)P.L2 * P.chi * P.D);
+  P.off_T = off;
+  if (!compress2_supported(P) && !compress_in_lds(P)) off += pad((int64_t)compress_big_T_doubles(P));
   P.mixed = d->precision == PEPS_PREC_MIXED;
   if (P.mixed) {
     // FP32 copies of the boundaries, same element strides as the FP64 ones
@@ -140,7 +142,8 @@ struct ProfScope {
 hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                         double* ws, int32_t* status, hipStream_t st) {
   if (compress2_supported(P)) return launch_compress2(P, n, dir, r, theta, configs, ws, status, st);
-  return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
+  if (compress_in_lds(P)) return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
+  return launch_compress_big(P, n, dir, r, theta, configs, ws, status, st);
 }
 
 // FP32 copy of theta (mixed precision), placed after the chain workspaces.

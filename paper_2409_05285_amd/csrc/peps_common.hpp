@@ -29,6 +29,7 @@ struct Prob {
   int64_t off_top, off_lstop, off_bot, off_lsbot, off_B, off_tmp, off_R, off_L, off_X, off_epart;
   int64_t off_top32, off_bot32;   // FP32 boundary copies (offsets in doubles)
   int64_t off_tau;                // Householder scalars of one compression [L2][chi*D]
+  int64_t off_T;                  // panel T factors of the workspace-resident compression
   int mixed;                      // FP32 strip contractions
 };
 

@@ -1,0 +1,438 @@
+// Boundary-row compression for bond dimensions whose QR matrices do not fit
+// on chip (chi * D beyond the register kernel, matrices beyond LDS): the
+// same two-sweep C_chi as the other compression kernels (boundary-MPS
+// contraction with boundary dimension D_c = chi; QR left to right, SVD
+// truncation right to left), one 256-thread workgroup per chain, with the
+// dense matrices in the chain's workspace:
+//   * QR of (a p) x b by blocked Householder (Golub & Van Loan, Alg. 5.2.2,
+//     compact WY of Schreiber & Van Loan): panels of up to 16 columns
+//     factorised in LDS, T factors kept, trailing columns updated one per
+//     wave as A - V T^T (V^T A), reading each column twice and writing it once
+//     per panel;
+//   * R B_{c+1} as FP64 MFMA tiles;
+//   * the truncation by one-sided Jacobi (Hestenes) in the workspace;
+//   * Q_{c-1} (U S) applied panel by panel from the stored reflectors and T.
+#include <math.h>
+
+#include "peps_chain.hpp"
+#include "peps_common.hpp"
+#include "peps_contract.hpp"
+#include "peps_kernels.hpp"
+#include "peps_linalg.hpp"
+
+namespace peps {
+
+namespace {
+
+constexpr int NBMAX = 16;                       // widest panel
+constexpr int PANEL_DOUBLES = 12 * 1024;        // LDS panel: 96 KB
+constexpr int NWAVE_B = NT / 64;
+
+// Panel width for a QR with m rows (the panel must fit the LDS array).
+__host__ __device__ inline int panel_width(int m) {
+  int nb = PANEL_DOUBLES / (m > 0 ? m : 1);
+  if (nb > NBMAX) nb = NBMAX;
+  if (nb < 1) nb = 1;
+  return nb;
+}
+
+__device__ inline double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order sum over the workgroup (waves, then the NWAVE_B partials).
+__device__ inline double block_sum_b(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum64(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NWAVE_B; ++q) s += red[q];
+  __syncthreads();
+  return s;
+}
+
+// Absorbed site c of row r: element (x = (aa, l), p, col = (bq, rr)) of
+// B_c = sum_u A[aa][u][bq] W[l][u][rr][p] (top; the vertical legs swap for the
+// bottom boundary).  Written at dst[x * xs + p * ps + col * cs].
+__device__ void absorb_site_to(const Prob& P, const Geo& geo, int dir, int r, int c, const double* theta,
+                               const uint8_t* cfg, const double* bnd, bool has_prev, int rp, double* dst,
+                               int64_t xs, int64_t ps, int64_t cs, int& sa_out, int& sp_out, int& sb_out) {
+  int Dl, Du, Dr, Dd;
+  leg_dims(P, r, c, Dl, Du, Dr, Dd);
+  const int i = r * P.L2 + c;
+  const double* W = theta + geo.poff[i] + (size_t)cfg[i] * (Dl * Du * Dr * Dd);
+  const double* A = has_prev ? bnd + ((size_t)rp * P.L2 + c) * P.TS : nullptr;
+  const int a = has_prev ? geo.ba[dir][rp][c] : 1;
+  const int b = has_prev ? geo.bb[dir][rp][c] : 1;
+  const int q = has_prev ? (dir == 0 ? Du : Dd) : 1;
+  const int pp = dir == 0 ? Dd : Du;
+  const int total = a * Dl * pp * b * Dr;
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    int rr = idx % Dr, t = idx / Dr;
+    const int bq = t % b;
+    t /= b;
+    const int p = t % pp;
+    t /= pp;
+    const int l = t % Dl, aa = t / Dl;
+    double s = 0.0;
+    for (int u = 0; u < q; ++u) {
+      const double Av = A ? A[(aa * q + u) * b + bq] : 1.0;
+      const double Wv = dir == 0 ? W[((l * Du + u) * Dr + rr) * Dd + p] : W[((l * Du + p) * Dr + rr) * Dd + u];
+      s += Av * Wv;
+    }
+    const int x = aa * Dl + l, col = bq * Dr + rr;
+    dst[x * xs + p * ps + col * cs] = s;
+  }
+  sa_out = a * Dl;
+  sp_out = pp;
+  sb_out = b * Dr;
+}
+
+// Blocked Householder QR of X (m x n, column-major, leading dimension m) in
+// place: R on and above the diagonal of the first k = min(m, n) rows, the
+// reflectors v_j (unit entry implied) below it, tau_j in taus[j], and the
+// upper-triangular T of each panel (Q_panel = I - V T V^T) at
+// Tst[j0 * NBMAX ...] (nb x nb, row-major).
+__device__ void qr_blocked(double* X, int m, int n, double* taus, double* Tst, double* panel, double* Tm,
+                           double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = m < n ? m : n;
+  const int NB = panel_width(m);
+  for (int j0 = 0; j0 < k; j0 += NB) {
+    const int nb = k - j0 < NB ? k - j0 : NB;
+    const int rows = m - j0;
+    for (int idx = tid; idx < nb * rows; idx += NT) {
+      const int t = idx / rows, i = idx % rows;
+      panel[idx] = X[(size_t)(j0 + t) * m + j0 + i];
+    }
+    __syncthreads();
+    // unblocked factorisation of the panel
+    for (int t = 0; t < nb; ++t) {
+      double* pc = panel + t * rows;
+      double part = 0.0;
+      for (int i = t + 1 + tid; i < rows; i += NT) part += pc[i] * pc[i];
+      const double sigma2 = block_sum_b(part, red);
+      const double alpha = pc[t];
+      double tau = 0.0, scale = 0.0, beta = alpha;
+      if (sigma2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (tau != 0.0)
+        for (int i = t + 1 + tid; i < rows; i += NT) pc[i] *= scale;
+      __syncthreads();
+      if (tid == 0) {
+        pc[t] = beta;
+        taus[j0 + t] = tau;
+        Tm[t * NBMAX + t] = tau;
+      }
+      if (tau != 0.0) {
+        for (int u = t + 1 + wave; u < nb; u += NWAVE_B) {
+          double* pu = panel + u * rows;
+          double s = lane == 0 ? pu[t] : 0.0;
+          for (int i = t + 1 + lane; i < rows; i += 64) s += pc[i] * pu[i];
+          const double wt = tau * wave_sum64(s);
+          if (lane == 0) pu[t] -= wt;
+          for (int i = t + 1 + lane; i < rows; i += 64) pu[i] -= pc[i] * wt;
+        }
+      }
+      __syncthreads();
+    }
+    // T (forward, column-wise): T[0:t, t] = -tau_t T[0:t, 0:t] (V[:, 0:t]^T v_t)
+    for (int st = wave; st < nb * nb; st += NWAVE_B) {
+      const int s = st / nb, t = st % nb;
+      if (s >= t) continue;
+      // v_s . v_t over rows >= t (v_t[t] = 1, zero above)
+      double d = lane == 0 ? panel[s * rows + t] : 0.0;
+      for (int i = t + 1 + lane; i < rows; i += 64) d += panel[s * rows + i] * panel[t * rows + i];
+      d = wave_sum64(d);
+      if (lane == 0) Tm[s * NBMAX + t] = d;   // dot, replaced by T below
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double z[NBMAX];
+      for (int t = 1; t < nb; ++t) {
+        const double tau = Tm[t * NBMAX + t];
+        for (int s = 0; s < t; ++s) z[s] = -tau * Tm[s * NBMAX + t];
+        for (int s = 0; s < t; ++s) {
+          double v = 0.0;
+          for (int q = s; q < t; ++q) v += (q == s ? Tm[s * NBMAX + s] : Tm[s * NBMAX + q]) * z[q];
+          Tm[s * NBMAX + t] = v;
+        }
+      }
+      for (int s = 0; s < nb; ++s)
+        for (int t = 0; t < nb; ++t) Tst[(size_t)j0 * NBMAX + s * nb + t] = t >= s ? Tm[s * NBMAX + t] : 0.0;
+    }
+    // panel back to the matrix
+    for (int idx = tid; idx < nb * rows; idx += NT) {
+      const int t = idx / rows, i = idx % rows;
+      X[(size_t)(j0 + t) * m + j0 + i] = panel[idx];
+    }
+    __syncthreads();
+    // trailing columns: A <- A - V T^T (V^T A), one wave per column
+    for (int col = j0 + nb + wave; col < n; col += NWAVE_B) {
+      double* xc = X + (size_t)col * m + j0;
+      double wv[NBMAX];
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t) wv[t] = 0.0;
+      for (int i = lane; i < rows; i += 64) {
+        const double x = xc[i];
+#pragma unroll
+        for (int t = 0; t < NBMAX; ++t)
+          if (t < nb) wv[t] += (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * x;
+      }
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] = wave_sum64(wv[t]);
+      double w2[NBMAX];
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t) {
+        double v = 0.0;
+        for (int s = 0; s <= t && s < nb; ++s) v += Tm[s * NBMAX + t] * wv[s];
+        w2[t] = t < nb ? v : 0.0;
+      }
+      for (int i = lane; i < rows; i += 64) {
+        double x = xc[i];
+#pragma unroll
+        for (int t = 0; t < NBMAX; ++t)
+          if (t < nb) x -= (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * w2[t];
+        xc[i] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Y <- Q Y for the Q of a blocked QR (X: reflectors, m rows, k of them;
+// Tst: panel T factors), Y m x ny row-major with leading dimension ny.
+__device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst, double* Y, int ny, double* Wl) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int NB = panel_width(m);
+  if (k <= 0) return;
+  const int last = ((k - 1) / NB) * NB;
+  for (int j0 = last; j0 >= 0; j0 -= NB) {
+    const int nb = k - j0 < NB ? k - j0 : NB;
+    const int rows = m - j0;
+    const double* V = X + (size_t)j0 * m + j0;   // column t at V + t * m
+    const double* T = Tst + (size_t)j0 * NBMAX;  // nb x nb
+    double* W = Wl;                              // nb x ny
+    double* W2 = Wl + NBMAX * ny;                // nb x ny
+    for (int tq = wave; tq < nb * ny; tq += NWAVE_B) {
+      const int t = tq / ny, q = tq % ny;
+      double s = 0.0;
+      for (int i = t + lane; i < rows; i += 64) {
+        const double v = i == t ? 1.0 : V[(size_t)t * m + i];
+        s += v * Y[(size_t)(j0 + i) * ny + q];
+      }
+      s = wave_sum64(s);
+      if (lane == 0) W[t * ny + q] = s;
+    }
+    __syncthreads();
+    for (int tq = tid; tq < nb * ny; tq += NT) {
+      const int t = tq / ny, q = tq % ny;
+      double v = 0.0;
+      for (int s = t; s < nb; ++s) v += T[t * nb + s] * W[s * ny + q];
+      W2[t * ny + q] = v;
+    }
+    __syncthreads();
+    for (int iq = tid; iq < rows * ny; iq += NT) {
+      const int i = iq / ny, q = iq % ny;
+      double y = Y[(size_t)(j0 + i) * ny + q];
+      for (int t = 0; t < nb && t <= i; ++t) {
+        const double v = i == t ? 1.0 : V[(size_t)t * m + i];
+        y -= v * W2[t * ny + q];
+      }
+      Y[(size_t)(j0 + i) * ny + q] = y;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, const double* __restrict__ theta,
+                                                     const uint8_t* __restrict__ configs, double* ws,
+                                                     int32_t* status) {
+  __shared__ Geo geo;
+  __shared__ double red[NT];
+  __shared__ double panel[PANEL_DOUBLES];
+  __shared__ double Tm[NBMAX * NBMAX];
+  __shared__ double sig[CD_MAX];
+  __shared__ int rnk[CD_MAX];
+  __shared__ int flags[2];
+  __shared__ int sa[MAX_L], sp[MAX_L], sb[MAX_L];
+  const int tid = threadIdx.x;
+  const int ch = blockIdx.x;
+  if (tid == 0) build_geo(P, geo);
+  __syncthreads();
+  ChainWS w = chain_ws(P, ws, ch);
+  double* base = ws + (size_t)ch * P.chain_stride;
+  double* taus_all = base + P.off_tau;
+  double* T_all = base + P.off_T;
+  const int cd = P.chi * P.D;
+  const uint8_t* cfg = configs + (size_t)ch * P.N;
+  double* bnd = dir == 0 ? w.top : w.bot;
+  double* lsb = dir == 0 ? w.lstop : w.lsbot;
+  double* outT = bnd + (size_t)r * P.L2 * P.TS;
+  const bool has_prev = dir == 0 ? (r > 0) : (r < P.L1 - 1);
+  const int rp = dir == 0 ? r - 1 : r + 1;
+  const double ls_prev = has_prev ? lsb[rp] : 0.0;
+
+  // 1. site 0 absorbed straight into its QR matrix (rows (x, p), column-major)
+  {
+    int a0, p0, b0;
+    int Dl, Du, Dr, Dd;
+    leg_dims(P, r, 0, Dl, Du, Dr, Dd);
+    const int pp = dir == 0 ? Dd : Du;
+    const int a = (has_prev ? geo.ba[dir][rp][0] : 1) * Dl;
+    const int m0 = a * pp;
+    absorb_site_to(P, geo, dir, r, 0, theta, cfg, bnd, has_prev, rp, w.B, pp, 1, m0, a0, p0, b0);
+    if (tid == 0) { sa[0] = a0; sp[0] = p0; sb[0] = b0; }
+  }
+  __syncthreads();
+
+  // 2. left-to-right QR; X_{c+1} = R_c B_{c+1} by MFMA tiles
+  for (int c = 0; c < P.L2 - 1; ++c) {
+    const int m = sa[c] * sp[c], n = sb[c];
+    const int k = m < n ? m : n;
+    double* X = w.B + (size_t)c * P.BS;
+    qr_blocked(X, m, n, taus_all + (size_t)c * cd, T_all + (size_t)c * cd * NBMAX, panel, Tm, red);
+    // R (k x n, row-major, zero below the diagonal)
+    double* Rr = w.R;
+    for (int idx = tid; idx < k * n; idx += NT) {
+      const int i = idx / n, j = idx % n;
+      Rr[idx] = j >= i ? X[(size_t)j * m + i] : 0.0;
+    }
+    // B_{c+1} absorbed, row-major [y][p][col]
+    int a1, p1, b1;
+    {
+      int Dl, Du, Dr, Dd;
+      leg_dims(P, r, c + 1, Dl, Du, Dr, Dd);
+      const int pp = dir == 0 ? Dd : Du;
+      const int bb = (has_prev ? geo.bb[dir][rp][c + 1] : 1) * Dr;
+      absorb_site_to(P, geo, dir, r, c + 1, theta, cfg, bnd, has_prev, rp, w.tmp, (int64_t)pp * bb, bb, 1, a1, p1,
+                     b1);
+    }
+    __syncthreads();
+    if (a1 != n) set_status(status, PEPS_ERR_UNSUPPORTED);   // bond of the absorbed row: cannot differ
+    // X_{c+1}[col * m' + x * p + q] = sum_y R[x][y] B[y][q][col], m' = k p
+    const int mn = k * p1;
+    double* Xn = w.B + (size_t)(c + 1) * P.BS;
+    wg_gemm<double>(Xn, mstride(p1), Map2{b1, 1, mn}, Rr, mstride(n), mid(), w.tmp, mstride(p1 * b1), mid(), k,
+                    p1 * b1, n);
+    if (tid == 0) {
+      sb[c] = k;
+      sa[c + 1] = k;
+      sp[c + 1] = p1;
+      sb[c + 1] = b1;
+    }
+    __syncthreads();
+  }
+  // the last site as the first truncation matrix: row-major a x (p b)
+  {
+    const int c = P.L2 - 1;
+    const int a = sa[c], pp = sp[c], b = sb[c], m = a * pp;
+    const double* X = w.B + (size_t)c * P.BS;
+    for (int idx = tid; idx < a * pp * b; idx += NT) {
+      const int i = idx / (pp * b), e = idx % (pp * b), p = e / b, col = e % b;
+      w.tmp[idx] = X[(size_t)col * m + i * pp + p];
+    }
+    __syncthreads();
+  }
+
+  // 3. right-to-left truncation to chi
+  for (int c = P.L2 - 1; c >= 1; --c) {
+    const int a = sa[c], nb = sp[c] * sb[c];
+    const bool tr = a < nb;
+    const int mg = tr ? nb : a, ng = tr ? a : nb;
+    const int cs = mg | 1;
+    double* G = w.X;
+    double* V = w.X + (size_t)cs * ng;
+    const double* M = w.tmp;
+    for (int idx = tid; idx < mg * ng; idx += NT) {
+      const int j = idx / mg, i = idx % mg;
+      G[(size_t)j * cs + i] = tr ? M[(size_t)j * nb + i] : M[(size_t)i * nb + j];
+    }
+    for (int idx = tid; idx < ng * ng; idx += NT) {
+      const int j = idx / ng, i = idx % ng;
+      V[idx] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    wg_jacobi(G, mg, ng, cs, V, ng, flags);
+    for (int j = tid; j < ng; j += NT) {
+      double s = 0.0;
+      for (int i = 0; i < mg; ++i) s += G[(size_t)j * cs + i] * G[(size_t)j * cs + i];
+      sig[j] = sqrt(s);
+    }
+    __syncthreads();
+    for (int j = tid; j < ng; j += NT) {
+      int rk = 0;
+      for (int q = 0; q < ng; ++q)
+        if (sig[q] > sig[j] || (sig[q] == sig[j] && q < j)) ++rk;
+      rnk[j] = rk;
+    }
+    __syncthreads();
+    const int k2 = P.chi < ng ? P.chi : ng;
+    double* Vt = outT + (size_t)c * P.TS;
+    double* US = w.R;   // a x k2, row-major
+    for (int idx = tid; idx < a * ng; idx += NT) {
+      const int i = idx / ng, j = idx % ng;
+      const int q = rnk[j];
+      if (q < k2) US[i * k2 + q] = tr ? V[(size_t)j * ng + i] * sig[j] : G[(size_t)j * cs + i];
+    }
+    for (int idx = tid; idx < nb * ng; idx += NT) {
+      const int e = idx / ng, j = idx % ng;
+      const int q = rnk[j];
+      if (q < k2) Vt[q * nb + e] = tr ? (sig[j] > 0.0 ? G[(size_t)j * cs + e] / sig[j] : 0.0) : V[(size_t)j * ng + e];
+    }
+    __syncthreads();
+    // A_{c-1} <- Q_{c-1} [U S; 0]: m2 x k2 row-major into tmp
+    const int m2 = sa[c - 1] * sp[c - 1];
+    const int kq = sb[c - 1];
+    for (int idx = tid; idx < m2 * k2; idx += NT) {
+      const int i = idx / k2, q = idx % k2;
+      w.tmp[idx] = i < a ? US[i * k2 + q] : 0.0;
+    }
+    __syncthreads();
+    apply_q_blocked(w.B + (size_t)(c - 1) * P.BS, m2, kq, T_all + (size_t)(c - 1) * cd * NBMAX, w.tmp, k2, panel);
+    if (tid == 0) {
+      sb[c - 1] = k2;
+      sa[c] = k2;
+    }
+    __syncthreads();
+  }
+
+  // 4. normalise site 0 and accumulate the log-scale
+  const int tot0 = sa[0] * sp[0] * sb[0];
+  double part = 0.0;
+  for (int idx = tid; idx < tot0; idx += NT) part += w.tmp[idx] * w.tmp[idx];
+  const double nrm = sqrt(block_sum_b(part, red));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int idx = tid; idx < tot0; idx += NT) outT[idx] = w.tmp[idx] * inv;
+  if (tid == 0) {
+    lsb[r] = nrm > 0.0 ? ls_prev + log(nrm) : -INFINITY;
+    for (int c = 0; c < P.L2; ++c)
+      if (sa[c] != geo.ba[dir][r][c] || sb[c] != geo.bb[dir][r][c]) set_status(status, PEPS_ERR_UNSUPPORTED);
+  }
+  if (P.mixed) {
+    __syncthreads();
+    float* o32 = (float*)(ws + (size_t)ch * P.chain_stride + (dir == 0 ? P.off_top32 : P.off_bot32)) +
+                 (size_t)r * P.L2 * P.TS;
+    for (int idx = tid; idx < P.L2 * P.TS; idx += NT) o32[idx] = (float)outT[idx];
+  }
+}
+
+size_t compress_big_T_doubles(const Prob& P) { return (size_t)P.L2 * P.chi * P.D * NBMAX; }
+
+hipError_t launch_compress_big(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
+                               double* ws, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_compress_big, dim3(n), dim3(NT), 0, st, P, dir, r, theta, configs, ws, status);
+  return hipGetLastError();
+}
+
+}  // namespace peps

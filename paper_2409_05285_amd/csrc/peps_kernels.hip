@@ -12,19 +12,15 @@ namespace peps {
 // ---------------------------------------------------------------------------
 // Compression of one boundary row: top[r] = C(top[r-1] o M_r) (dir 0) or
 // bot[r] = C(M_r o bot[r+1]) (dir 1), for every chain.
-// The dense work matrices (QR matrix, Jacobi pair G and V, products) live
-// in dynamic LDS when they fit (in_lds), else in the chain's strip
-// intermediate region of the workspace, which no compression step
-// otherwise uses (the same code then runs out of L2 / HBM).
 __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const double* __restrict__ theta,
                                                  const uint8_t* __restrict__ configs, double* ws,
-                                                 int32_t* status, int in_lds) {
-  extern __shared__ double dyn_lds[];
+                                                 int32_t* status) {
+  extern __shared__ double dyn[];
   __shared__ Geo geo;
   __shared__ double red[NT];
-  __shared__ double tau[CD_MAX];
-  __shared__ double sig[CD_MAX];
-  __shared__ int rnk[CD_MAX];
+  __shared__ double tau[256];
+  __shared__ double sig[256];
+  __shared__ int rnk[256];
   __shared__ int flags[2];
   __shared__ int sa[MAX_L], sp[MAX_L], sb[MAX_L];
   __shared__ double one;
@@ -36,7 +32,6 @@ __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const d
   }
   __syncthreads();
   ChainWS w = chain_ws(P, ws, ch);
-  double* dyn = in_lds ? dyn_lds : w.X;
   const uint8_t* cfg = configs + (size_t)ch * P.N;
   double* bnd = dir == 0 ? w.top : w.bot;
   double* lsb = dir == 0 ? w.lstop : w.lsbot;
@@ -286,15 +281,14 @@ bool compress_in_lds(const Prob& P) { return compress_lds_bytes(P) <= COMPRESS_D
 
 hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                            double* ws, int32_t* status, hipStream_t st) {
-  const bool in_lds = compress_in_lds(P);
-  const size_t lds = in_lds ? compress_lds_bytes(P) : 0;
+  const size_t lds = compress_lds_bytes(P);
   static size_t configured = 0;
   if (lds > configured) {
     hipError_t e = hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     configured = lds;
   }
-  hipLaunchKernelGGL(k_compress, dim3(n), dim3(NT), lds, st, P, dir, r, theta, configs, ws, status, in_lds ? 1 : 0);
+  hipLaunchKernelGGL(k_compress, dim3(n), dim3(NT), lds, st, P, dir, r, theta, configs, ws, status);
   return hipGetLastError();
 }
 

@@ -9,14 +9,21 @@
 namespace peps {
 
 constexpr int SR_MAX_ITER = 4096;
-// Largest chi * D of the general compression kernel (its per-column LDS
-// arrays), and the dynamic LDS it may use before its work matrices move to
-// the workspace.
+// Largest chi * D of the workspace-resident compression kernel (its
+// per-column LDS arrays), and the dynamic LDS the LDS-resident general
+// kernel may use.
 constexpr int CD_MAX = 512;
 constexpr size_t COMPRESS_DYN_LDS_MAX = 128 * 1024;
 
-// Bytes of the dense work matrices of the general compression kernel.
+// Bytes of the dense work matrices of the LDS-resident general kernel, and
+// whether they fit its LDS.
 size_t compress_dyn_lds(const Prob& P);
+bool compress_in_lds(const Prob& P);
+// Doubles of panel T factors one chain needs in the workspace-resident
+// kernel (k_compress_big), and its launcher.
+size_t compress_big_T_doubles(const Prob& P);
+hipError_t launch_compress_big(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
+                               double* ws, int32_t* status, hipStream_t st);
 bool compress2_supported(const Prob& P);
 hipError_t launch_compress2(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                             double* ws, int32_t* status, hipStream_t st);
