@@ -17,6 +17,7 @@
 #include "peps_chain.hpp"
 #include "peps_common.hpp"
 #include "peps_contract.hpp"
+#include "peps_dpp.hpp"
 #include "peps_kernels.hpp"
 #include "peps_linalg.hpp"
 
@@ -25,8 +26,9 @@ namespace peps {
 namespace {
 
 constexpr int NBMAX = 16;                       // widest panel
-constexpr int PANEL_DOUBLES = 12 * 1024;        // LDS panel: 96 KB
+constexpr int PANEL_DOUBLES = 14 * 1024;        // LDS work array: 112 KB (QR panel, Jacobi blocks, W of Q Y)
 constexpr int NWAVE_B = NT / 64;
+constexpr double JAC_CONV_BIG = 1.0e-8;
 
 // Panel width for a QR with m rows (the panel must fit the LDS array).
 __host__ __device__ inline int panel_width(int m) {
@@ -36,10 +38,7 @@ __host__ __device__ inline int panel_width(int m) {
   return nb;
 }
 
-__device__ inline double wave_sum64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ inline double wave_sum64(double v) { return wave_sum(v); }
 
 // Fixed-order sum over the workgroup (waves, then the NWAVE_B partials).
 __device__ inline double block_sum_b(double v, double* red) {
@@ -96,7 +95,7 @@ __device__ void absorb_site_to(const Prob& P, const Geo& geo, int dir, int r, in
 // reflectors v_j (unit entry implied) below it, tau_j in taus[j], and the
 // upper-triangular T of each panel (Q_panel = I - V T V^T) at
 // Tst[j0 * NBMAX ...] (nb x nb, row-major).
-__device__ void qr_blocked(double* X, int m, int n, double* taus, double* Tst, double* panel, double* Tm,
+__device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus, double* Tst, double* panel, double* Tm,
                            double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int k = m < n ? m : n;
@@ -174,34 +173,87 @@ __device__ void qr_blocked(double* X, int m, int n, double* taus, double* Tst, d
       X[(size_t)(j0 + t) * m + j0 + i] = panel[idx];
     }
     __syncthreads();
-    // trailing columns: A <- A - V T^T (V^T A), one wave per column
+    // trailing columns: A <- A - V T^T (V^T A), one wave per column; a
+    // column of up to 64 RMAX rows is loaded into registers in one batch
+    constexpr int RMAX = 32;
+    const bool staged = rows <= 64 * RMAX;
     for (int col = j0 + nb + wave; col < n; col += NWAVE_B) {
       double* xc = X + (size_t)col * m + j0;
       double wv[NBMAX];
 #pragma unroll
       for (int t = 0; t < NBMAX; ++t) wv[t] = 0.0;
-      for (int i = lane; i < rows; i += 64) {
-        const double x = xc[i];
+      double xr[RMAX];
+      if (staged) {
 #pragma unroll
-        for (int t = 0; t < NBMAX; ++t)
-          if (t < nb) wv[t] += (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * x;
+        for (int u = 0; u < RMAX; ++u) {
+          const int i = lane + 64 * u;
+          xr[u] = i < rows ? xc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RMAX; ++u) {
+          const int i = lane + 64 * u;
+          if (64 * u < rows) {
+#pragma unroll
+            for (int t = 0; t < NBMAX; ++t)
+              if (t < nb) wv[t] += ((i > t && i < rows) ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * xr[u];
+          }
+        }
+      } else {
+        for (int i = lane; i < rows; i += 64) {
+          const double x = xc[i];
+#pragma unroll
+          for (int t = 0; t < NBMAX; ++t)
+            if (t < nb) wv[t] += (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * x;
+        }
       }
+      // the nb wave sums stage by stage, so that their latencies overlap
 #pragma unroll
       for (int t = 0; t < NBMAX; ++t)
-        if (t < nb) wv[t] = wave_sum64(wv[t]);
+        if (t < nb) wv[t] += dpp_f64<0xB1>(wv[t]);
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] += dpp_f64<0x4E>(wv[t]);
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] += dpp_f64<0x141>(wv[t]);
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] += dpp_f64<0x140>(wv[t]);
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] = rows_pair_sum(wv[t]);
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) wv[t] = halves_sum(wv[t]);
       double w2[NBMAX];
 #pragma unroll
       for (int t = 0; t < NBMAX; ++t) {
         double v = 0.0;
-        for (int s = 0; s <= t && s < nb; ++s) v += Tm[s * NBMAX + t] * wv[s];
+#pragma unroll
+        for (int s = 0; s < NBMAX; ++s)
+          if (s <= t && s < nb) v += Tm[s * NBMAX + t] * wv[s];
         w2[t] = t < nb ? v : 0.0;
       }
-      for (int i = lane; i < rows; i += 64) {
-        double x = xc[i];
+      if (staged) {
 #pragma unroll
-        for (int t = 0; t < NBMAX; ++t)
-          if (t < nb) x -= (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * w2[t];
-        xc[i] = x;
+        for (int u = 0; u < RMAX; ++u) {
+          const int i = lane + 64 * u;
+          if (64 * u < rows) {
+            double x = xr[u];
+#pragma unroll
+            for (int t = 0; t < NBMAX; ++t)
+              if (t < nb) x -= ((i > t && i < rows) ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * w2[t];
+            if (i < rows) xc[i] = x;
+          }
+        }
+      } else {
+        for (int i = lane; i < rows; i += 64) {
+          double x = xc[i];
+#pragma unroll
+          for (int t = 0; t < NBMAX; ++t)
+            if (t < nb) x -= (i > t ? panel[t * rows + i] : (i == t ? 1.0 : 0.0)) * w2[t];
+          xc[i] = x;
+        }
       }
     }
     __syncthreads();
@@ -250,6 +302,215 @@ __device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst
       Y[(size_t)(j0 + i) * ny + q] = y;
     }
     __syncthreads();
+  }
+}
+
+// One-sided Jacobi (Hestenes) on G (mg x ng, column-major, column stride
+// cs) in the workspace, without accumulating the rotations: every pair of a
+// round-robin round is worked on at once by lp lanes (lp = largest power of
+// two with lp * pairs <= NT), so a round costs one workgroup barrier.
+// Stops after a sweep in which no pair was rotated.
+__device__ void jacobi_ws(double* G, int mg, int ng, int cs, int* flags) {
+  const int tid = threadIdx.x;
+  if (ng < 2) return;
+  const int ne = ng + (ng & 1), npairs = ne / 2;
+  const int q = NT / npairs;
+  const int lp = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
+  const int gpr = NT / lp;
+  const int grp = tid / lp, li = tid % lp;
+  if (tid == 0) { flags[0] = 0; flags[1] = 0; }
+  __syncthreads();
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    const int fl = sweep & 1;
+    for (int rnd = 0; rnd < ne - 1; ++rnd) {
+      for (int pr = grp; pr < npairs; pr += gpr) {
+        int ci, cj;
+        if (pr == 0) { ci = rnd; cj = ne - 1; }
+        else { ci = (rnd + pr) % (ne - 1); cj = (rnd - pr + ne - 1) % (ne - 1); }
+        if (ci > cj) { const int t = ci; ci = cj; cj = t; }
+        if (cj >= ng) continue;                 // uniform over the lp lanes of the pair
+        double* gi = G + (size_t)ci * cs;
+        double* gj = G + (size_t)cj * cs;
+        double al[4] = {0.0, 0.0, 0.0, 0.0}, be[4] = {0.0, 0.0, 0.0, 0.0}, ga[4] = {0.0, 0.0, 0.0, 0.0};
+        int t = 0;
+#pragma unroll 4
+        for (int i = li; i < mg; i += lp, ++t) {
+          const double x = gi[i], y = gj[i];
+          al[t & 3] += x * x;
+          be[t & 3] += y * y;
+          ga[t & 3] += x * y;
+        }
+        double sa = (al[0] + al[1]) + (al[2] + al[3]);
+        double sb = (be[0] + be[1]) + (be[2] + be[3]);
+        double sg = (ga[0] + ga[1]) + (ga[2] + ga[3]);
+        sa = group_sum(sa, lp);
+        sb = group_sum(sb, lp);
+        sg = group_sum(sg, lp);
+        if (sg != 0.0 && fabs(sg) > JAC_TOL * sqrt(sa) * sqrt(sb)) {
+          const double zeta = (sb - sa) / (2.0 * sg);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt);
+          const double s = c * tt;
+#pragma unroll 4
+          for (int i = li; i < mg; i += lp) {
+            const double x = gi[i], y = gj[i];
+            gi[i] = c * x - s * y;
+            gj[i] = s * x + c * y;
+          }
+          if (li == 0) flags[fl] = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const bool done = flags[fl] == 0;
+    __syncthreads();
+    if (tid == 0) flags[fl] = 0;
+    __syncthreads();
+    if (done) break;
+  }
+}
+
+// One inner round-robin sweep over the nl columns held in LDS (column
+// stride ld; local column j < n1 at slot j, later ones at slot bw + j - n1):
+// one barrier per round.  Returns nonzero (on every thread) when some pair
+// was rotated.
+__device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int n1, int bw, int* flag) {
+  const int tid = threadIdx.x;
+  const int ne = nl + (nl & 1), npairs = ne / 2;
+  const int q = NT / npairs;
+  const int lp = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
+  const int gpr = NT / lp;
+  const int grp = tid / lp, li = tid % lp;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int rnd = 0; rnd < ne - 1; ++rnd) {
+    for (int pr = grp; pr < npairs; pr += gpr) {
+      int ci, cj;
+      if (pr == 0) { ci = rnd; cj = ne - 1; }
+      else { ci = (rnd + pr) % (ne - 1); cj = (rnd - pr + ne - 1) % (ne - 1); }
+      if (ci > cj) { const int t = ci; ci = cj; cj = t; }
+      if (cj >= nl) continue;
+      double* gi = Gl + (ci < n1 ? ci : bw + ci - n1) * ld;
+      double* gj = Gl + (cj < n1 ? cj : bw + cj - n1) * ld;
+      // the pair's rows are loaded into registers in one batch (EMAX per
+      // lane; longer columns are streamed)
+      constexpr int EMAX = 32;
+      const bool staged = mg <= lp * EMAX;
+      double xr[EMAX], yr[EMAX];
+      double al[2] = {0.0, 0.0}, be[2] = {0.0, 0.0}, ga[2] = {0.0, 0.0};
+      if (staged) {
+#pragma unroll
+        for (int u = 0; u < EMAX; ++u) {
+          const int i = li + lp * u;
+          xr[u] = i < mg ? gi[i] : 0.0;
+          yr[u] = i < mg ? gj[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < EMAX; ++u) {
+          al[u & 1] += xr[u] * xr[u];
+          be[u & 1] += yr[u] * yr[u];
+          ga[u & 1] += xr[u] * yr[u];
+        }
+      } else {
+        int t = 0;
+        for (int i = li; i < mg; i += lp, ++t) {
+          const double x = gi[i], y = gj[i];
+          al[t & 1] += x * x;
+          be[t & 1] += y * y;
+          ga[t & 1] += x * y;
+        }
+      }
+      double sa = al[0] + al[1], sb = be[0] + be[1], sg = ga[0] + ga[1];
+      sa = group_sum(sa, lp);
+      sb = group_sum(sb, lp);
+      sg = group_sum(sg, lp);
+      if (sg != 0.0 && fabs(sg) > JAC_TOL * sqrt(sa) * sqrt(sb)) {
+        const double zeta = (sb - sa) / (2.0 * sg);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt);
+        const double s = c * tt;
+        if (staged) {
+#pragma unroll
+          for (int u = 0; u < EMAX; ++u) {
+            const int i = li + lp * u;
+            if (i < mg) {
+              gi[i] = c * xr[u] - s * yr[u];
+              gj[i] = s * xr[u] + c * yr[u];
+            }
+          }
+        } else {
+          for (int i = li; i < mg; i += lp) {
+            const double x = gi[i], y = gj[i];
+            gi[i] = c * x - s * y;
+            gj[i] = s * x + c * y;
+          }
+        }
+        // a sweep whose rotations all stay below 1e-8 is the last one: the
+        // next would be at rounding level (quadratic convergence)
+        if (li == 0 && fabs(sg) > JAC_CONV_BIG * sqrt(sa) * sqrt(sb)) *flag = 1;
+      }
+    }
+    __syncthreads();
+  }
+  const int f = *flag;
+  __syncthreads();
+  return f;
+}
+
+// Block one-sided Jacobi on G (mg x ng, column-major, stride cs) in the
+// workspace: the columns form blocks of bw; every pair of blocks (round-
+// robin over blocks) is loaded into LDS (2 bw columns), swept once there,
+// and written back.  An outer sweep without any rotation ends it.  With a
+// single block the block is swept in LDS until no pair rotates.
+__device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs, double* Gl, int* flags) {
+  const int tid = threadIdx.x;
+  if (ng < 2) return;
+  const int ld = mg | 1;
+  int bw = PANEL_DOUBLES / (2 * ld);
+  if (bw > 32) bw = 32;
+  if (bw < 1) bw = 1;
+  const int nblk = (ng + bw - 1) / bw;
+  auto load = [&](int b, int slot) {
+    const int c0 = b * bw, nc = ng - c0 < bw ? ng - c0 : bw;
+    for (int idx = tid; idx < nc * mg; idx += NT) {
+      const int j = idx / mg, i = idx % mg;
+      Gl[(slot * bw + j) * ld + i] = G[(size_t)(c0 + j) * cs + i];
+    }
+    return nc;
+  };
+  auto store = [&](int b, int slot, int nc) {
+    const int c0 = b * bw;
+    for (int idx = tid; idx < nc * mg; idx += NT) {
+      const int j = idx / mg, i = idx % mg;
+      G[(size_t)(c0 + j) * cs + i] = Gl[(slot * bw + j) * ld + i];
+    }
+  };
+  if (nblk == 1) {
+    load(0, 0);
+    __syncthreads();
+    for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep)
+      if (!lds_sweep(Gl, mg, ng, ld, ng, bw, flags)) break;
+    store(0, 0, ng);
+    __syncthreads();
+    return;
+  }
+  const int nbe = nblk + (nblk & 1);
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    int any = 0;
+    for (int rnd = 0; rnd < nbe - 1; ++rnd)
+      for (int pr = 0; pr < nbe / 2; ++pr) {
+        int b1, b2;
+        if (pr == 0) { b1 = rnd; b2 = nbe - 1; }
+        else { b1 = (rnd + pr) % (nbe - 1); b2 = (rnd - pr + nbe - 1) % (nbe - 1); }
+        if (b1 >= nblk || b2 >= nblk) continue;
+        const int n1 = load(b1, 0), n2 = load(b2, 1);
+        __syncthreads();
+        any |= lds_sweep(Gl, mg, n1 + n2, ld, n1, bw, flags + 1);
+        store(b1, 0, n1);
+        store(b2, 1, n2);
+        __syncthreads();
+      }
+    if (!any) break;
   }
 }
 
@@ -348,7 +609,10 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
   // 3. right-to-left truncation to chi
   for (int c = P.L2 - 1; c >= 1; --c) {
     const int a = sa[c], nb = sp[c] * sb[c];
-    const bool tr = a < nb;
+    // G = M^T when M has no more rows than columns: its columns become V S
+    // and U S = M V_k follows without accumulating rotations; else G = M
+    // with the rotations accumulated into V (ng = nb is then small)
+    const bool tr = a <= nb;
     const int mg = tr ? nb : a, ng = tr ? a : nb;
     const int cs = mg | 1;
     double* G = w.X;
@@ -358,12 +622,14 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
       const int j = idx / mg, i = idx % mg;
       G[(size_t)j * cs + i] = tr ? M[(size_t)j * nb + i] : M[(size_t)i * nb + j];
     }
-    for (int idx = tid; idx < ng * ng; idx += NT) {
-      const int j = idx / ng, i = idx % ng;
-      V[idx] = (i == j) ? 1.0 : 0.0;
-    }
+    if (!tr)
+      for (int idx = tid; idx < ng * ng; idx += NT) {
+        const int j = idx / ng, i = idx % ng;
+        V[idx] = (i == j) ? 1.0 : 0.0;
+      }
     __syncthreads();
-    wg_jacobi(G, mg, ng, cs, V, ng, flags);
+    if (tr) jacobi_blocked(G, mg, ng, cs, panel, flags);
+    else wg_jacobi(G, mg, ng, cs, V, ng, flags);
     for (int j = tid; j < ng; j += NT) {
       double s = 0.0;
       for (int i = 0; i < mg; ++i) s += G[(size_t)j * cs + i] * G[(size_t)j * cs + i];
@@ -380,15 +646,30 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     const int k2 = P.chi < ng ? P.chi : ng;
     double* Vt = outT + (size_t)c * P.TS;
     double* US = w.R;   // a x k2, row-major
-    for (int idx = tid; idx < a * ng; idx += NT) {
-      const int i = idx / ng, j = idx % ng;
-      const int q = rnk[j];
-      if (q < k2) US[i * k2 + q] = tr ? V[(size_t)j * ng + i] * sig[j] : G[(size_t)j * cs + i];
-    }
-    for (int idx = tid; idx < nb * ng; idx += NT) {
-      const int e = idx / ng, j = idx % ng;
-      const int q = rnk[j];
-      if (q < k2) Vt[q * nb + e] = tr ? (sig[j] > 0.0 ? G[(size_t)j * cs + e] / sig[j] : 0.0) : V[(size_t)j * ng + e];
+    if (tr) {
+      for (int idx = tid; idx < nb * ng; idx += NT) {
+        const int e = idx / ng, j = idx % ng;
+        const int q = rnk[j];
+        if (q < k2) Vt[q * nb + e] = sig[j] > 0.0 ? G[(size_t)j * cs + e] / sig[j] : 0.0;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < a * k2; idx += NT) {
+        const int i = idx / k2, q = idx % k2;
+        double s = 0.0;
+        for (int e = 0; e < nb; ++e) s += M[(size_t)i * nb + e] * Vt[q * nb + e];
+        US[idx] = s;
+      }
+    } else {
+      for (int idx = tid; idx < a * ng; idx += NT) {
+        const int i = idx / ng, j = idx % ng;
+        const int q = rnk[j];
+        if (q < k2) US[i * k2 + q] = G[(size_t)j * cs + i];
+      }
+      for (int idx = tid; idx < nb * ng; idx += NT) {
+        const int e = idx / ng, j = idx % ng;
+        const int q = rnk[j];
+        if (q < k2) Vt[q * nb + e] = V[(size_t)j * ng + e];
+      }
     }
     __syncthreads();
     // A_{c-1} <- Q_{c-1} [U S; 0]: m2 x k2 row-major into tmp
