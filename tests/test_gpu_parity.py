@@ -346,7 +346,9 @@ def _hub_setup(L1, L2, D, chi, mixed=False, seed=21):
 
 
 @pytest.mark.parametrize("L1,L2,D,chi,mixed", [(3, 3, 2, 4, False), (4, 4, 2, 4, False), (3, 4, 2, 3, False),
-                                               (4, 4, 2, 4, True)])
+                                               (4, 4, 2, 4, True),
+                                               # chi D = 80: the workspace-resident compression kernel
+                                               (4, 4, 4, 20, False), (5, 5, 4, 20, False), (5, 5, 4, 20, True)])
 def test_hubbard_eval_and_grad_match_oracle(L1, L2, D, chi, mixed):
     dev = _dev()
     p, lat, desc, th = _hub_setup(L1, L2, D, chi, mixed)
