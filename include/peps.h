@@ -66,6 +66,7 @@ enum { PEPS_MODEL_HEISENBERG = 0, PEPS_MODEL_HUBBARD = 1 };
 enum { PEPS_PREC_FP64 = 0, PEPS_PREC_MIXED = 1 };
 enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3 };
 enum { PEPS_N_MOVE_TYPES = 3 }; /* horizontal exchange, site move, vertical exchange */
+enum { PEPS_N_OBS = 4 };        /* local values per sample of peps_observables_batch */
 
 typedef struct {
   int32_t L1, L2;    /* rows, columns (open boundaries), each >= 2                */
@@ -177,6 +178,22 @@ peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* confi
    Workspace: peps_workspace_bytes(desc, n, PEPS_WS_SR). */
 peps_status peps_vjp_batch(const peps_desc* desc, int64_t n, const uint8_t* configs, const double* O_rows,
                            const double* cot, double* grad, void* ws, size_t ws_bytes, peps_stream_t stream);
+
+/* Local values of diagonal thermal observables (Benchmark section: uniform
+   susceptibility chi = beta <M_z^2> / N with <M_z>^2 taken as 0; double
+   occupancy of the Hubbard model).  For an operator A diagonal in the
+   computational basis the local value of sample S = (s, s') is
+   (A(s) + A(s')) / 2, whose |rho|^2-weighted mean is the symmetrised
+   expectation Tr(rho rho^T A + rho^T rho A) / (2 Tr(rho rho^T)).
+   out [n][PEPS_N_OBS] f64, per sample: M_z, M_z^2, particle number (Hubbard;
+   0 for spins), double occupancy sum_i n_i,up n_i,dn (Hubbard; 0 for spins),
+   with S^z = 1/2 - s for spins and (n_up - n_dn) / 2 for Hubbard.  The values
+   are exact multiples of 1/8.  configs [n][N] uint8.  Enqueues one kernel;
+   no workspace.  Off-diagonal correlations such as sum S_i.S_j over a bond
+   set are local energies of a Hamiltonian with those couplings (J1, J2 of
+   peps_desc; peps_eval_batch), halved. */
+peps_status peps_observables_batch(const peps_desc* desc, int64_t n, const uint8_t* configs, double* out,
+                                   peps_stream_t stream);
 
 /* ---- instrumentation (not part of the method) --------------------------- */
 

@@ -52,6 +52,30 @@ def spin_spectrum(lat):
     return np.concatenate(ev)
 
 
+def spin_spectrum_sectors(lat):
+    """[(n_down, eigenvalues)] of the J1-J2 Hamiltonian; M_z = (N - 2 n_down) / 2
+    is constant on each sector."""
+    return [(nd, np.linalg.eigvalsh(spin_sector_matrix(lat, nd))) for nd in range(lat.N + 1)]
+
+
+def thermal_mz2(sectors, N, beta):
+    """Canonical <M_z^2> at inverse temperature beta (array-valued): M_z is
+    conserved, so each eigenstate of sector n_down contributes
+    ((N - 2 n_down) / 2)^2."""
+    e0 = min(float(ev.min()) for _, ev in sectors)
+    beta = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+    out = np.empty_like(beta)
+    for k, b in enumerate(beta):
+        num = 0.0
+        den = 0.0
+        for nd, ev in sectors:
+            w = np.exp(-b * (ev - e0)).sum()
+            num += w * ((N - 2 * nd) / 2.0) ** 2
+            den += w
+        out[k] = num / den
+    return out
+
+
 def thermal_energy(evals, beta):
     """Canonical internal energy at inverse temperature beta (array-valued)."""
     evals = np.asarray(evals, dtype=np.float64)

@@ -23,6 +23,7 @@ STATUS = {
 MODEL_HEISENBERG, MODEL_HUBBARD = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR = 0, 1, 2, 3
+N_OBS = 4   # peps_observables_batch: M_z, M_z^2, particle number, double occupancy
 
 
 class PepsDesc(ctypes.Structure):
@@ -71,6 +72,8 @@ def _load():
     lib.sr_cg_solve.restype = c_int32
     lib.peps_vjp_batch.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.peps_vjp_batch.restype = c_int32
+    lib.peps_observables_batch.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.peps_observables_batch.restype = c_int32
     lib.peps_profile_enable.argtypes = [c_int32]
     lib.peps_profile_enable.restype = None
     lib.peps_profile_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
@@ -81,5 +84,5 @@ def _load():
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
-           "peps_vjp_batch", "peps_profile_enable", "peps_profile_read"]
+           "peps_vjp_batch", "peps_observables_batch", "peps_profile_enable", "peps_profile_read"]
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

@@ -288,6 +288,38 @@ def peps_vjp_batch(desc: Desc, configs, O_rows, cot):
     return grad
 
 
+OBS_NAMES = ("mz", "mz2", "n", "docc")
+
+
+def peps_observables_batch(desc: Desc, configs):
+    """Local values [n, 4] f64 of M_z, M_z^2, particle number and double
+    occupancy, (A(s) + A(s')) / 2 per sample (columns in OBS_NAMES order)."""
+    configs = _configs(desc, configs)
+    _check_dev(configs)
+    n = configs.shape[0]
+    out = torch.empty((n, _lib.N_OBS), dtype=torch.float64, device=configs.device)
+    _raise(LIB.peps_observables_batch(ctypes.byref(desc.c()), n, _ptr(configs), _ptr(out), _stream()),
+           "peps_observables_batch")
+    return out
+
+
+def thermal_observables(desc: Desc, configs, beta_phys, weights=None):
+    """Sample estimates at inverse temperature beta_phys: per-site <M_z^2>/N,
+    susceptibility beta <M_z^2> / N (<M_z>^2 := 0), <n>/N and double
+    occupancy <D>/N, weighted by `weights` (Eq. A1) when given.  Host
+    floats; synchronises."""
+    v = peps_observables_batch(desc, configs)
+    if weights is None:
+        m = v.mean(dim=0)
+    else:
+        w = weights.to(torch.float64)
+        m = (w[:, None] * v).sum(dim=0) / w.sum()
+    m = m.cpu().tolist()
+    N = desc.N
+    return {"mz2_per_site": m[1] / N, "chi": beta_phys * m[1] / N, "n_per_site": m[2] / N,
+            "docc_per_site": m[3] / N, "mz_per_site": m[0] / N}
+
+
 class PepsLogAmp(torch.autograd.Function):
     """log|psi(S_i)| for a batch of configurations as a differentiable
     function of theta.  Forward: peps_grad_batch (log-amplitudes and the O

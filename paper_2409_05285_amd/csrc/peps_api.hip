@@ -352,6 +352,17 @@ peps_status peps_vjp_batch(const peps_desc* d, int64_t n, const uint8_t* configs
   return PEPS_OK;
 }
 
+peps_status peps_observables_batch(const peps_desc* d, int64_t n, const uint8_t* configs, double* out,
+                                   peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  if (n < 0) return PEPS_ERR_ARG;
+  if (n == 0) return PEPS_OK;
+  if (!configs || !out) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  HIP_TRY(launch_observables(P, n, configs, out, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
 void peps_profile_enable(int32_t on) {
   g_prof = on != 0;
   g_used = 0;

@@ -210,6 +210,42 @@ __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const d
   }
 }
 
+// Local values (A(s) + A(s')) / 2 of M_z, M_z^2, particle number and double
+// occupancy for each sample; every term is a multiple of 1/8, so the sums
+// are exact.
+__global__ void k_observables(Prob P, int64_t n, const uint8_t* __restrict__ configs, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint8_t* S = configs + k * P.N;
+  double acc[PEPS_N_OBS] = {0.0, 0.0, 0.0, 0.0};
+  for (int side = 0; side < 2; ++side) {
+    double mz = 0.0, np_ = 0.0, dc = 0.0;
+    for (int i = 0; i < P.N; ++i) {
+      const int s = side == 0 ? S[i] / P.d : S[i] % P.d;
+      if (P.model == PEPS_MODEL_HEISENBERG) {
+        mz += 0.5 - s;
+      } else {
+        const int nu = s & 1, nd = (s >> 1) & 1;
+        mz += 0.5 * (nu - nd);
+        np_ += nu + nd;
+        dc += nu * nd;
+      }
+    }
+    acc[0] += 0.5 * mz;
+    acc[1] += 0.5 * mz * mz;
+    acc[2] += 0.5 * np_;
+    acc[3] += 0.5 * dc;
+  }
+#pragma unroll
+  for (int q = 0; q < PEPS_N_OBS; ++q) out[k * PEPS_N_OBS + q] = acc[q];
+}
+
+hipError_t launch_observables(const Prob& P, int64_t n, const uint8_t* configs, double* out, hipStream_t st) {
+  const int bs = 128;
+  hipLaunchKernelGGL(k_observables, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, P, n, configs, out);
+  return hipGetLastError();
+}
+
 // Diagonal energy, sum of the parts, and the per-sample outputs.
 __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int32_t* status) {

@@ -35,6 +35,8 @@ hipError_t launch_theta32(const Prob& P, const double* theta, float* t32, hipStr
 // dst[0..n) = src[0..n) on the stream (a copy kernel: no copy or memset
 // nodes when captured in a graph).
 hipError_t launch_copy_bytes(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);
+// Local values of the diagonal observables, one thread per sample.
+hipError_t launch_observables(const Prob& P, int64_t n, const uint8_t* configs, double* out, hipStream_t st);
 // Adds n to the device sweep counter (one thread, vector store).
 hipError_t launch_advance_counter(uint64_t* ctr, uint64_t n, hipStream_t st);
 hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,

@@ -20,7 +20,10 @@ tests/golden/make_ed_tables.py (oracle only).
 
 Bar: |E/N - E_ED/N| <= 3 sigma + 0.02 |E_ED/N| at every sampled beta_phys,
 sigma the standard error of the per-chain means (batch means over the
-sweeps of each chain).
+sweeps of each chain).  The same samples give <M_z^2>/N (the local value of
+a diagonal operator is (A(s) + A(s'))/2), whose susceptibility
+chi = beta <M_z^2> / N the Benchmark section reports; it is checked against
+the ED table within 3 sigma + 0.05 |ED|.
 """
 import json
 import os
@@ -38,10 +41,14 @@ torch = pytest.importorskip("torch")
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def _ed_energy(beta):
+def _ed(beta, key="E_per_site"):
     with open(os.path.join(HERE, "golden", "ed_heisenberg_4x4.json")) as f:
         t = json.load(f)
-    return float(np.interp(beta, t["beta"], t["E_per_site"]))
+    return float(np.interp(beta, t["beta"], t[key]))
+
+
+def _ed_energy(beta):
+    return _ed(beta)
 
 
 def test_cooling_4x4_matches_ed():
@@ -81,10 +88,18 @@ def test_cooling_4x4_matches_ed():
         e_ed = _ed_energy(beta)
         dev_rel = abs(E - e_ed) / (3 * sigma + 0.02 * abs(e_ed) + 1e-12)
         worst = max(worst, dev_rel)
-        print(f"[cool] step {step} beta {beta:.2f} E/N {E:.5f} +- {sigma:.5f} ED {e_ed:.5f}", flush=True)
+        obs = p.peps_observables_batch(desc, S_all.view(n_s, N)).cpu().numpy()
+        mz2 = obs[:, 1].reshape(sweeps, n_chains) / N
+        M2 = float((w * mz2).sum() / w.sum())
+        m2_chain = (w * mz2).sum(axis=0) / w.sum(axis=0)
+        sig_m = float(m2_chain.std(ddof=1) / np.sqrt(n_chains))
+        m2_ed = _ed(beta, "Mz2_per_site")
+        print(f"[cool] step {step} beta {beta:.2f} E/N {E:.5f} +- {sigma:.5f} ED {e_ed:.5f}  "
+              f"<Mz^2>/N {M2:.5f} +- {sig_m:.5f} ED {m2_ed:.5f}  chi {beta * M2:.5f}", flush=True)
         sys.stdout.flush()
         assert p.check(status) == 0
         assert abs(E - e_ed) <= 3 * sigma + 0.02 * abs(e_ed), (step, beta, E, sigma, e_ed)
+        assert abs(M2 - m2_ed) <= 3 * sig_m + 0.05 * abs(m2_ed), (step, beta, M2, sig_m, m2_ed)
         if step == steps:
             break
         _, _, stats, _ = p.sr_cg_solve(desc, S_all.view(n_s, N), O_all.view(n_s, nnz), E_all.view(n_s), tau, eps,

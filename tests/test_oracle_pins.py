@@ -577,3 +577,92 @@ def test_sr_tracks_imaginary_time_evolution():
     assert abs(e_twice - e_exact) > 5 * abs(errs[1])
     # first-order convergence in tau
     assert 1.5 < errs[0] / errs[1] < 3.5, errs
+
+
+# ---------------------------------------------------------------------------
+# Thermal observables (diagonal operators): local value (A(s) + A(s')) / 2
+
+
+def _dense_diag(lat, fn):
+    """Diagonal operator sum built from digit strings, basis order of
+    network.density_matrix (site 1 most significant)."""
+    d, N = lat.d, lat.N
+    vals = np.zeros(d ** N)
+    for x in range(d ** N):
+        digits = [(x // d ** (N - 1 - i)) % d for i in range(N)]
+        vals[x] = fn(digits)
+    return np.diag(vals)
+
+
+def test_observable_local_values_by_enumeration():
+    """For diagonal A, sum_S |rho|^2 (A(s) + A(s'))/2 / sum |rho|^2 equals
+    Tr(rho rho^T A + rho^T rho A) / (2 Tr(rho rho^T)), with A built as a dense
+    matrix independently of the oracle's local values (spin M_z, M_z^2)."""
+    from oracle import observables
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=61)
+    rho = network.density_matrix(lat, th)
+    w, vals = [], []
+    for S in network.all_configs(lat):
+        a = network.amplitude(lat, th, S)
+        w.append(a * a)
+        vals.append(observables.local_values(lat, S))
+    w = np.array(w)
+    est = observables.estimate(np.array(vals), w)
+    mz = _dense_diag(lat, lambda dg: sum(0.5 - s for s in dg))
+    for k, A in ((0, mz), (1, mz @ mz)):
+        rhs = np.trace(rho @ rho.T @ A + rho.T @ rho @ A) / (2 * np.trace(rho @ rho.T))
+        assert est[k] == pytest.approx(rhs, rel=1e-12, abs=1e-14)
+
+
+def test_observable_local_values_hubbard_by_enumeration():
+    """Same identity for the Hubbard particle number and double occupancy
+    (D = 1 tensors: the amplitude is a product of site factors)."""
+    from oracle import observables
+    lat = Lattice(2, 2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    th = synth.theta_random_unit(2, 2, 1, 4, seed=62)
+    rho = network.density_matrix(lat, th)
+    w, vals = [], []
+    for S in network.all_configs(lat):
+        a = network.amplitude(lat, th, S)
+        w.append(a * a)
+        vals.append(observables.local_values(lat, S))
+    est = observables.estimate(np.array(vals), np.array(w))
+    nop = _dense_diag(lat, lambda dg: sum(bin(s).count("1") for s in dg))
+    dop = _dense_diag(lat, lambda dg: sum(1 for s in dg if s == 3))
+    mzop = _dense_diag(lat, lambda dg: sum(0.5 * ((s & 1) - (s >> 1)) for s in dg))
+    for k, A in ((0, mzop), (1, mzop @ mzop), (2, nop), (3, dop)):
+        rhs = np.trace(rho @ rho.T @ A + rho.T @ rho @ A) / (2 * np.trace(rho @ rho.T))
+        assert est[k] == pytest.approx(rhs, rel=1e-12, abs=1e-14)
+
+
+def test_observables_identity_state_closed_forms():
+    """beta = 0 (|I>): every diagonal configuration has the same weight, so
+    <M_z^2> = N / 4 for spins (a sum of N independent +-1/2), and for Hubbard
+    <n> / N = 1 and the double occupancy per site is 1/4."""
+    from oracle import observables
+    lat = Lattice(2, 3, D=1, chi=1)
+    vals = [observables.local_values(lat, [2 * s + s for s in sv]) for sv in itertools.product(range(2), repeat=6)]
+    assert np.mean(vals, axis=0)[1] == pytest.approx(6 / 4, abs=1e-14)
+    assert np.mean(vals, axis=0)[0] == pytest.approx(0.0, abs=1e-14)
+    hl = Lattice(2, 2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    hv = [observables.local_values(hl, [4 * s + s for s in sv]) for sv in itertools.product(range(4), repeat=4)]
+    m = np.mean(hv, axis=0)
+    assert m[2] / 4 == pytest.approx(1.0, abs=1e-14)
+    assert m[3] / 4 == pytest.approx(0.25, abs=1e-14)
+
+
+def test_ed_thermal_mz2_matches_dense_trace():
+    """The sector-wise <M_z^2>(beta) of the ED module against the dense
+    trace Tr(exp(-beta H) M_z^2) / Tr exp(-beta H) on a 2x3 J1-J2 lattice,
+    and N / 4 at beta = 0."""
+    import scipy.linalg
+    lat = Lattice(2, 3, D=1, chi=1, J1=1.0, J2=0.5)
+    H = hamiltonian.dense_H(lat)
+    mz = _dense_diag(lat, lambda dg: sum(0.5 - s for s in dg))
+    sectors = ed.spin_spectrum_sectors(lat)
+    for b in (0.0, 0.3, 1.7):
+        rho = scipy.linalg.expm(-b * H)
+        ref = np.trace(rho @ mz @ mz) / np.trace(rho)
+        assert ed.thermal_mz2(sectors, lat.N, b)[0] == pytest.approx(ref, rel=1e-10)
+    assert ed.thermal_mz2(sectors, lat.N, 0.0)[0] == pytest.approx(lat.N / 4, abs=1e-13)
