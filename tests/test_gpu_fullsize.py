@@ -21,7 +21,6 @@ import pytest
 
 import synth
 from oracle import measure, sampler
-from oracle.sr import dense_O
 from oracle.lattice import Lattice
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +42,24 @@ def _dev():
 def _say(*a):
     print("[case]", *a, flush=True)
     sys.stdout.flush()
+
+
+def _dense_rows(cfg, O):
+    """Compressed O rows expanded to the parameter layout: the block of site
+    i sits at the parameter offset of i plus S_i times the block size (the
+    layout of include/peps.h), written here from the lattice shape alone."""
+    bs = []
+    for r in range(L1):
+        for c in range(L2):
+            legs = (1 if c == 0 else D, 1 if r == 0 else D, 1 if c == L2 - 1 else D, 1 if r == L1 - 1 else D)
+            bs.append(int(np.prod(legs)))
+    poff = np.concatenate([[0], np.cumsum([4 * b for b in bs])])
+    ooff = np.concatenate([[0], np.cumsum(bs)])
+    full = np.zeros((O.shape[0], int(poff[-1])))
+    for i, b in enumerate(bs):
+        cols = poff[i] + cfg[:, i].astype(np.int64)[:, None] * b + np.arange(b)[None, :]
+        np.put_along_axis(full, cols, O[:, ooff[i]:ooff[i] + b], axis=1)
+    return full
 
 
 def _sweep(p, mixed):
@@ -102,8 +119,7 @@ def test_fullsize_sr_solve_properties():
     dth, g, stats, st = p.sr_cg_solve(desc, cfg_d, O_d, e_d, tau, eps, 200, 1e-10)
     torch.cuda.synchronize()
     assert p.check(st) == 0
-    lat = Lattice(L1, L2, D=D, chi=CHI)
-    Of = dense_O(lat, cfg_d.cpu().numpy(), O_d.cpu().numpy())
+    Of = _dense_rows(cfg_d.cpu().numpy(), O_d.cpu().numpy())
     e = e_d.cpu().numpy()
     x, g, stats = dth.cpu().numpy(), g.cpu().numpy(), stats.cpu().numpy()
     n = Of.shape[0]
