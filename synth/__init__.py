@@ -47,6 +47,31 @@ def theta_random_unit(L1, L2, D, d, seed=0):
     return np.concatenate(blocks)
 
 
+def _popcount(x):
+    return bin(int(x)).count("1")
+
+
+def theta_random_parity_even(L1, L2, D, d, seed=0):
+    """Z2-graded random tensors (the fermionic ansatz's block structure):
+    a virtual index k of a leg of dimension D has parity 0 for k < D // 2
+    and 1 otherwise (a leg of dimension 1 is even); the physical index
+    S = s d + s' has the parity of the occupation numbers of s and s' (bit
+    counts of the Hubbard digits; for d = 2 the bit of each digit).  Entries
+    whose total parity is odd are zero; the rest are i.i.d. N(0,1), each
+    site scaled to unit Frobenius norm."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    blocks = []
+    for shp in site_shapes(L1, L2, D, d):
+        T = rng.standard_normal(shp)
+        ps = np.array([(_popcount(S // d) + _popcount(S % d)) & 1 for S in range(d * d)])
+        legs = [np.array([0 if (n == 1 or k < n // 2) else 1 for k in range(n)]) for n in shp[1:]]
+        par = (ps[:, None, None, None, None] + legs[0][None, :, None, None, None] + legs[1][None, None, :, None, None]
+               + legs[2][None, None, None, :, None] + legs[3][None, None, None, None, :]) & 1
+        T = np.where(par == 0, T, 0.0)
+        blocks.append((T / np.linalg.norm(T)).reshape(-1))
+    return np.concatenate(blocks)
+
+
 def configs_diagonal(n, N, d, seed=0):
     """n configurations with s_i = s'_i, s_i uniform (an exact sample of |I>)."""
     rng = np.random.Generator(np.random.Philox(seed))

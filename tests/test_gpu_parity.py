@@ -12,6 +12,7 @@ within 1e-4 of the row's largest magnitude, signs exact; sampled
 configurations and accept counts bit-exact for every chain whose Metropolis
 tests all stay 1e-4 away from a tie.
 """
+import math
 import sys
 
 import numpy as np
@@ -426,3 +427,55 @@ def test_multi_sweep_call_matches_single_sweeps(mixed):
         for key in ("log_abs", "e_loc", "O", "configs"):
             assert torch.equal(ra[key][k], rb[k][key][0]), (k, key)
     assert torch.equal(ra["configs"][ns - 1], cfg_a)
+
+
+def test_parity_even_hubbard_ansatz():
+    """Z2-graded (parity-even) Hubbard tensors: even configurations match the
+    oracle at the usual bars, a sweep from the diagonal start is bit-exact
+    and stays in the even sector, and configurations of odd total parity
+    have zero amplitude (reported through the status word, log|psi| = -inf)."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    from oracle.lattice import MODEL_HUBBARD
+    L1, L2, D, chi = 3, 4, 2, 4
+    lat = Lattice(L1, L2, D=D, chi=chi, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    desc = p.Desc(L1, L2, D, chi, d=4, model=p.MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    th = synth.theta_random_parity_even(L1, L2, D, 4, seed=91)
+    theta_d = torch.tensor(th, device=dev)
+    _say("parity-even hubbard")
+    # even sector: sector-consistent configurations have even total parity
+    cfg = synth.configs_sector(4, lat.N, 4, seed=92)
+    assert all(sum(bin(int(x)).count("1") for x in S) % 2 == 0 for S in cfg)
+    la, sg, el, st = p.peps_eval_batch(desc, theta_d, torch.tensor(cfg, device=dev))
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    ref = measure.evaluate_batch(lat, th, cfg, chi, want_O=False)
+    la, sg, el = (x.cpu().numpy() for x in (la, sg, el))
+    assert _close_log(la, ref["log_abs"])
+    assert np.array_equal(sg, ref["sign"])
+    emag = max(np.abs(ref["e_loc"]).mean(), 1e-300)
+    assert np.all(np.abs(el - ref["e_loc"]) <= 1e-10 * np.maximum(np.abs(ref["e_loc"]), emag))
+    # one sweep from the diagonal start: bit-exact, even parity kept
+    cfg0 = synth.configs_diagonal(3, lat.N, 4, seed=93)
+    cfg_d = torch.tensor(cfg0, device=dev)
+    res = p.peps_sample_sweep(desc, theta_d, cfg_d, 4321, 2, 1)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    got = cfg_d.cpu().numpy()
+    for ch in range(cfg0.shape[0]):
+        r = sampler.sweep(lat, th, cfg0[ch].astype(np.int64), chi, 4321, ch, 2)
+        if r["near_ties"]:
+            continue
+        assert np.array_equal(got[ch], r["S"].astype(np.uint8)), ch
+        assert sum(bin(int(x)).count("1") for x in got[ch]) % 2 == 0
+    # odd total parity: zero amplitude, reported through the status word.
+    # The QR sweep's reflectors may mix the parity sectors of a bond (a valid
+    # gauge), so the device's amplitude is zero only to rounding: at least
+    # 1e-13 below the even configurations' amplitudes.
+    odd = cfg[:2].copy()
+    odd[:, 0] = odd[:, 0] ^ 1          # flip the bra up-occupation of site 0
+    la_o, _, _, st_o = p.peps_eval_batch(desc, theta_d, torch.tensor(odd, device=dev))
+    torch.cuda.synchronize()
+    assert int(st_o.item()) in (-6, -5)
+    la_o = la_o.cpu().numpy()
+    assert np.all(np.isneginf(la_o) | (la_o < la.min() + math.log(1e-13))), (la_o, la)

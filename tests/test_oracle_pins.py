@@ -666,3 +666,26 @@ def test_ed_thermal_mz2_matches_dense_trace():
         ref = np.trace(rho @ mz @ mz) / np.trace(rho)
         assert ed.thermal_mz2(sectors, lat.N, b)[0] == pytest.approx(ref, rel=1e-10)
     assert ed.thermal_mz2(sectors, lat.N, 0.0)[0] == pytest.approx(lat.N / 4, abs=1e-13)
+
+
+def test_parity_even_ansatz_vanishes_on_odd_configurations():
+    """P14: with Z2-even site tensors (open legs even) the contraction is
+    parity-even, so every configuration of odd total fermion parity has
+    rho = 0 exactly, while even ones generally do not; both for the exact
+    contraction and the boundary-MPS amplitude."""
+    lat = Lattice(2, 3, D=2, chi=4, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    th = synth.theta_random_parity_even(2, 3, 2, 4, seed=81)
+    rng = np.random.default_rng(82)
+    n_odd = n_even_nonzero = 0
+    for _ in range(400):
+        S = rng.integers(0, 16, size=lat.N)
+        par = sum(bin(int(x)).count("1") for x in S) & 1
+        a = network.amplitude(lat, th, S)
+        if par:
+            n_odd += 1
+            assert a == 0.0
+            with pytest.raises(measure.ZeroAmplitude):
+                measure.evaluate(lat, th, S, 4, want_O=False)
+        elif a != 0.0:
+            n_even_nonzero += 1
+    assert n_odd > 100 and n_even_nonzero > 100
