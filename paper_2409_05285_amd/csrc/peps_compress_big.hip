@@ -2,15 +2,16 @@
 // on chip (chi * D beyond the register kernel, matrices beyond LDS): the
 // same two-sweep C_chi as the other compression kernels (boundary-MPS
 // contraction with boundary dimension D_c = chi; QR left to right, SVD
-// truncation right to left), one 256-thread workgroup per chain, with the
+// truncation right to left), one 512-thread workgroup per chain, with the
 // dense matrices in the chain's workspace:
 //   * QR of (a p) x b by blocked Householder (Golub & Van Loan, Alg. 5.2.2,
-//     compact WY of Schreiber & Van Loan): panels of up to 16 columns
+//     compact WY of Schreiber & Van Loan): panels of up to NBMAX columns
 //     factorised in LDS, T factors kept, trailing columns updated one per
-//     wave as A - V T^T (V^T A), reading each column twice and writing it once
-//     per panel;
+//     wave as A - V T^T (V^T A), each column loaded into registers once per
+//     panel;
 //   * R B_{c+1} as FP64 MFMA tiles;
-//   * the truncation by one-sided Jacobi (Hestenes) in the workspace;
+//   * the truncation by block one-sided Jacobi (Hestenes): pairs of column
+//     blocks swept in LDS, no rotation accumulation for wide matrices;
 //   * Q_{c-1} (U S) applied panel by panel from the stored reflectors and T.
 #include <math.h>
 
@@ -25,9 +26,10 @@ namespace peps {
 
 namespace {
 
-constexpr int NBMAX = 16;                       // widest panel
+constexpr int NTB = 512;                        // threads per workgroup (two waves per SIMD)
+constexpr int NBMAX = 12;                       // widest panel
 constexpr int PANEL_DOUBLES = 14 * 1024;        // LDS work array: 112 KB (QR panel, Jacobi blocks, W of Q Y)
-constexpr int NWAVE_B = NT / 64;
+constexpr int NWAVE_B = NTB / 64;
 constexpr double JAC_CONV_BIG = 1.0e-8;
 
 // Panel width for a QR with m rows (the panel must fit the LDS array).
@@ -69,7 +71,7 @@ __device__ void absorb_site_to(const Prob& P, const Geo& geo, int dir, int r, in
   const int q = has_prev ? (dir == 0 ? Du : Dd) : 1;
   const int pp = dir == 0 ? Dd : Du;
   const int total = a * Dl * pp * b * Dr;
-  for (int idx = threadIdx.x; idx < total; idx += NT) {
+  for (int idx = threadIdx.x; idx < total; idx += NTB) {
     int rr = idx % Dr, t = idx / Dr;
     const int bq = t % b;
     t /= b;
@@ -103,7 +105,7 @@ __device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus
   for (int j0 = 0; j0 < k; j0 += NB) {
     const int nb = k - j0 < NB ? k - j0 : NB;
     const int rows = m - j0;
-    for (int idx = tid; idx < nb * rows; idx += NT) {
+    for (int idx = tid; idx < nb * rows; idx += NTB) {
       const int t = idx / rows, i = idx % rows;
       panel[idx] = X[(size_t)(j0 + t) * m + j0 + i];
     }
@@ -112,7 +114,7 @@ __device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus
     for (int t = 0; t < nb; ++t) {
       double* pc = panel + t * rows;
       double part = 0.0;
-      for (int i = t + 1 + tid; i < rows; i += NT) part += pc[i] * pc[i];
+      for (int i = t + 1 + tid; i < rows; i += NTB) part += pc[i] * pc[i];
       const double sigma2 = block_sum_b(part, red);
       const double alpha = pc[t];
       double tau = 0.0, scale = 0.0, beta = alpha;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus
         scale = 1.0 / (alpha - beta);
       }
       if (tau != 0.0)
-        for (int i = t + 1 + tid; i < rows; i += NT) pc[i] *= scale;
+        for (int i = t + 1 + tid; i < rows; i += NTB) pc[i] *= scale;
       __syncthreads();
       if (tid == 0) {
         pc[t] = beta;
@@ -168,14 +170,14 @@ __device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus
         for (int t = 0; t < nb; ++t) Tst[(size_t)j0 * NBMAX + s * nb + t] = t >= s ? Tm[s * NBMAX + t] : 0.0;
     }
     // panel back to the matrix
-    for (int idx = tid; idx < nb * rows; idx += NT) {
+    for (int idx = tid; idx < nb * rows; idx += NTB) {
       const int t = idx / rows, i = idx % rows;
       X[(size_t)(j0 + t) * m + j0 + i] = panel[idx];
     }
     __syncthreads();
     // trailing columns: A <- A - V T^T (V^T A), one wave per column; a
     // column of up to 64 RMAX rows is loaded into registers in one batch
-    constexpr int RMAX = 32;
+    constexpr int RMAX = 24;
     const bool staged = rows <= 64 * RMAX;
     for (int col = j0 + nb + wave; col < n; col += NWAVE_B) {
       double* xc = X + (size_t)col * m + j0;
@@ -263,7 +265,7 @@ __device__ __forceinline__ void qr_blocked(double* X, int m, int n, double* taus
 // Y <- Q Y for the Q of a blocked QR (X: reflectors, m rows, k of them;
 // Tst: panel T factors), Y m x ny row-major with leading dimension ny.
 __device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst, double* Y, int ny, double* Wl) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int NB = panel_width(m);
   if (k <= 0) return;
   const int last = ((k - 1) / NB) * NB;
@@ -274,25 +276,43 @@ __device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst
     const double* T = Tst + (size_t)j0 * NBMAX;  // nb x nb
     double* W = Wl;                              // nb x ny
     double* W2 = Wl + NBMAX * ny;                // nb x ny
-    for (int tq = wave; tq < nb * ny; tq += NWAVE_B) {
-      const int t = tq / ny, q = tq % ny;
-      double s = 0.0;
-      for (int i = t + lane; i < rows; i += 64) {
-        const double v = i == t ? 1.0 : V[(size_t)t * m + i];
-        s += v * Y[(size_t)(j0 + i) * ny + q];
+    double* Wp = Wl + 2 * NBMAX * ny;            // partials [rg][nb][ny]
+    // W = V^T Y: thread (rg, q) accumulates the nb sums over rows rg, rg + R,
+    // ... (Y loads coalesced along q, V entries shared by the q threads),
+    // then the R partials are added in a fixed order
+    const int R = NTB / ny > 0 ? NTB / ny : 1;
+    const int rg = tid / ny, q0 = tid % ny;
+    if (rg < R && tid < R * ny) {
+      double wp[NBMAX];
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t) wp[t] = 0.0;
+#pragma unroll 2
+      for (int i = rg; i < rows; i += R) {
+        const double y = Y[(size_t)(j0 + i) * ny + q0];
+#pragma unroll
+        for (int t = 0; t < NBMAX; ++t)
+          if (t < nb && t <= i) wp[t] += (i == t ? 1.0 : V[(size_t)t * m + i]) * y;
       }
-      s = wave_sum64(s);
-      if (lane == 0) W[t * ny + q] = s;
+#pragma unroll
+      for (int t = 0; t < NBMAX; ++t)
+        if (t < nb) Wp[(rg * nb + t) * ny + q0] = wp[t];
     }
     __syncthreads();
-    for (int tq = tid; tq < nb * ny; tq += NT) {
+    for (int tq = tid; tq < nb * ny; tq += NTB) {
+      const int t = tq / ny, q = tq % ny;
+      double s = 0.0;
+      for (int g = 0; g < R; ++g) s += Wp[(g * nb + t) * ny + q];
+      W[t * ny + q] = s;
+    }
+    __syncthreads();
+    for (int tq = tid; tq < nb * ny; tq += NTB) {
       const int t = tq / ny, q = tq % ny;
       double v = 0.0;
       for (int s = t; s < nb; ++s) v += T[t * nb + s] * W[s * ny + q];
       W2[t * ny + q] = v;
     }
     __syncthreads();
-    for (int iq = tid; iq < rows * ny; iq += NT) {
+    for (int iq = tid; iq < rows * ny; iq += NTB) {
       const int i = iq / ny, q = iq % ny;
       double y = Y[(size_t)(j0 + i) * ny + q];
       for (int t = 0; t < nb && t <= i; ++t) {
@@ -305,71 +325,6 @@ __device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst
   }
 }
 
-// One-sided Jacobi (Hestenes) on G (mg x ng, column-major, column stride
-// cs) in the workspace, without accumulating the rotations: every pair of a
-// round-robin round is worked on at once by lp lanes (lp = largest power of
-// two with lp * pairs <= NT), so a round costs one workgroup barrier.
-// Stops after a sweep in which no pair was rotated.
-__device__ void jacobi_ws(double* G, int mg, int ng, int cs, int* flags) {
-  const int tid = threadIdx.x;
-  if (ng < 2) return;
-  const int ne = ng + (ng & 1), npairs = ne / 2;
-  const int q = NT / npairs;
-  const int lp = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
-  const int gpr = NT / lp;
-  const int grp = tid / lp, li = tid % lp;
-  if (tid == 0) { flags[0] = 0; flags[1] = 0; }
-  __syncthreads();
-  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
-    const int fl = sweep & 1;
-    for (int rnd = 0; rnd < ne - 1; ++rnd) {
-      for (int pr = grp; pr < npairs; pr += gpr) {
-        int ci, cj;
-        if (pr == 0) { ci = rnd; cj = ne - 1; }
-        else { ci = (rnd + pr) % (ne - 1); cj = (rnd - pr + ne - 1) % (ne - 1); }
-        if (ci > cj) { const int t = ci; ci = cj; cj = t; }
-        if (cj >= ng) continue;                 // uniform over the lp lanes of the pair
-        double* gi = G + (size_t)ci * cs;
-        double* gj = G + (size_t)cj * cs;
-        double al[4] = {0.0, 0.0, 0.0, 0.0}, be[4] = {0.0, 0.0, 0.0, 0.0}, ga[4] = {0.0, 0.0, 0.0, 0.0};
-        int t = 0;
-#pragma unroll 4
-        for (int i = li; i < mg; i += lp, ++t) {
-          const double x = gi[i], y = gj[i];
-          al[t & 3] += x * x;
-          be[t & 3] += y * y;
-          ga[t & 3] += x * y;
-        }
-        double sa = (al[0] + al[1]) + (al[2] + al[3]);
-        double sb = (be[0] + be[1]) + (be[2] + be[3]);
-        double sg = (ga[0] + ga[1]) + (ga[2] + ga[3]);
-        sa = group_sum(sa, lp);
-        sb = group_sum(sb, lp);
-        sg = group_sum(sg, lp);
-        if (sg != 0.0 && fabs(sg) > JAC_TOL * sqrt(sa) * sqrt(sb)) {
-          const double zeta = (sb - sa) / (2.0 * sg);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt);
-          const double s = c * tt;
-#pragma unroll 4
-          for (int i = li; i < mg; i += lp) {
-            const double x = gi[i], y = gj[i];
-            gi[i] = c * x - s * y;
-            gj[i] = s * x + c * y;
-          }
-          if (li == 0) flags[fl] = 1;
-        }
-      }
-      __syncthreads();
-    }
-    const bool done = flags[fl] == 0;
-    __syncthreads();
-    if (tid == 0) flags[fl] = 0;
-    __syncthreads();
-    if (done) break;
-  }
-}
-
 // One inner round-robin sweep over the nl columns held in LDS (column
 // stride ld; local column j < n1 at slot j, later ones at slot bw + j - n1):
 // one barrier per round.  Returns nonzero (on every thread) when some pair
@@ -377,9 +332,9 @@ __device__ void jacobi_ws(double* G, int mg, int ng, int cs, int* flags) {
 __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int n1, int bw, int* flag) {
   const int tid = threadIdx.x;
   const int ne = nl + (nl & 1), npairs = ne / 2;
-  const int q = NT / npairs;
+  const int q = NTB / npairs;
   const int lp = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
-  const int gpr = NT / lp;
+  const int gpr = NTB / lp;
   const int grp = tid / lp, li = tid % lp;
   if (tid == 0) *flag = 0;
   __syncthreads();
@@ -394,7 +349,7 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int
       double* gj = Gl + (cj < n1 ? cj : bw + cj - n1) * ld;
       // the pair's rows are loaded into registers in one batch (EMAX per
       // lane; longer columns are streamed)
-      constexpr int EMAX = 32;
+      constexpr int EMAX = 16;
       const bool staged = mg <= lp * EMAX;
       double xr[EMAX], yr[EMAX];
       double al[2] = {0.0, 0.0}, be[2] = {0.0, 0.0}, ga[2] = {0.0, 0.0};
@@ -424,11 +379,16 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int
       sa = group_sum(sa, lp);
       sb = group_sum(sb, lp);
       sg = group_sum(sg, lp);
-      if (sg != 0.0 && fabs(sg) > JAC_TOL * sqrt(sa) * sqrt(sb)) {
-        const double zeta = (sb - sa) / (2.0 * sg);
-        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt);
-        const double s = c * tt;
+      if (sg != 0.0 && sg * sg > (JAC_TOL * JAC_TOL) * (sa * sb)) {
+        // Rutishauser's angle from the double angle (d = sb - sa, e = 2 sg):
+        // (c, s) parallel to ((1 + |d|/r) / 2, sign(d) e / (2 r)), normalised
+        // by a correctly rounded 1/sqrt so that c^2 + s^2 = 1 to rounding
+        const double d = sb - sa, e = 2.0 * sg;
+        const double r = sqrt(fma(d, d, e * e));
+        const double h = 0.5 + 0.5 * fabs(d) / r;
+        const double qv = (d >= 0.0 ? 0.5 : -0.5) * e / r;
+        const double w = 1.0 / sqrt(fma(h, h, qv * qv));
+        const double c = h * w, s = qv * w;
         if (staged) {
 #pragma unroll
           for (int u = 0; u < EMAX; ++u) {
@@ -447,7 +407,7 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int
         }
         // a sweep whose rotations all stay below 1e-8 is the last one: the
         // next would be at rounding level (quadratic convergence)
-        if (li == 0 && fabs(sg) > JAC_CONV_BIG * sqrt(sa) * sqrt(sb)) *flag = 1;
+        if (li == 0 && sg * sg > (JAC_CONV_BIG * JAC_CONV_BIG) * (sa * sb)) *flag = 1;
       }
     }
     __syncthreads();
@@ -472,7 +432,7 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
   const int nblk = (ng + bw - 1) / bw;
   auto load = [&](int b, int slot) {
     const int c0 = b * bw, nc = ng - c0 < bw ? ng - c0 : bw;
-    for (int idx = tid; idx < nc * mg; idx += NT) {
+    for (int idx = tid; idx < nc * mg; idx += NTB) {
       const int j = idx / mg, i = idx % mg;
       Gl[(slot * bw + j) * ld + i] = G[(size_t)(c0 + j) * cs + i];
     }
@@ -480,7 +440,7 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
   };
   auto store = [&](int b, int slot, int nc) {
     const int c0 = b * bw;
-    for (int idx = tid; idx < nc * mg; idx += NT) {
+    for (int idx = tid; idx < nc * mg; idx += NTB) {
       const int j = idx / mg, i = idx % mg;
       G[(size_t)(c0 + j) * cs + i] = Gl[(slot * bw + j) * ld + i];
     }
@@ -516,11 +476,11 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
 
 }  // namespace
 
-__global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, const double* __restrict__ theta,
+__global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, const double* __restrict__ theta,
                                                      const uint8_t* __restrict__ configs, double* ws,
                                                      int32_t* status) {
   __shared__ Geo geo;
-  __shared__ double red[NT];
+  __shared__ double red[NTB];
   __shared__ double panel[PANEL_DOUBLES];
   __shared__ double Tm[NBMAX * NBMAX];
   __shared__ double sig[CD_MAX];
@@ -565,7 +525,7 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     qr_blocked(X, m, n, taus_all + (size_t)c * cd, T_all + (size_t)c * cd * NBMAX, panel, Tm, red);
     // R (k x n, row-major, zero below the diagonal)
     double* Rr = w.R;
-    for (int idx = tid; idx < k * n; idx += NT) {
+    for (int idx = tid; idx < k * n; idx += NTB) {
       const int i = idx / n, j = idx % n;
       Rr[idx] = j >= i ? X[(size_t)j * m + i] : 0.0;
     }
@@ -599,7 +559,7 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     const int c = P.L2 - 1;
     const int a = sa[c], pp = sp[c], b = sb[c], m = a * pp;
     const double* X = w.B + (size_t)c * P.BS;
-    for (int idx = tid; idx < a * pp * b; idx += NT) {
+    for (int idx = tid; idx < a * pp * b; idx += NTB) {
       const int i = idx / (pp * b), e = idx % (pp * b), p = e / b, col = e % b;
       w.tmp[idx] = X[(size_t)col * m + i * pp + p];
     }
@@ -618,25 +578,25 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     double* G = w.X;
     double* V = w.X + (size_t)cs * ng;
     const double* M = w.tmp;
-    for (int idx = tid; idx < mg * ng; idx += NT) {
+    for (int idx = tid; idx < mg * ng; idx += NTB) {
       const int j = idx / mg, i = idx % mg;
       G[(size_t)j * cs + i] = tr ? M[(size_t)j * nb + i] : M[(size_t)i * nb + j];
     }
     if (!tr)
-      for (int idx = tid; idx < ng * ng; idx += NT) {
+      for (int idx = tid; idx < ng * ng; idx += NTB) {
         const int j = idx / ng, i = idx % ng;
         V[idx] = (i == j) ? 1.0 : 0.0;
       }
     __syncthreads();
     if (tr) jacobi_blocked(G, mg, ng, cs, panel, flags);
     else wg_jacobi(G, mg, ng, cs, V, ng, flags);
-    for (int j = tid; j < ng; j += NT) {
+    for (int j = tid; j < ng; j += NTB) {
       double s = 0.0;
       for (int i = 0; i < mg; ++i) s += G[(size_t)j * cs + i] * G[(size_t)j * cs + i];
       sig[j] = sqrt(s);
     }
     __syncthreads();
-    for (int j = tid; j < ng; j += NT) {
+    for (int j = tid; j < ng; j += NTB) {
       int rk = 0;
       for (int q = 0; q < ng; ++q)
         if (sig[q] > sig[j] || (sig[q] == sig[j] && q < j)) ++rk;
@@ -647,25 +607,25 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     double* Vt = outT + (size_t)c * P.TS;
     double* US = w.R;   // a x k2, row-major
     if (tr) {
-      for (int idx = tid; idx < nb * ng; idx += NT) {
+      for (int idx = tid; idx < nb * ng; idx += NTB) {
         const int e = idx / ng, j = idx % ng;
         const int q = rnk[j];
         if (q < k2) Vt[q * nb + e] = sig[j] > 0.0 ? G[(size_t)j * cs + e] / sig[j] : 0.0;
       }
       __syncthreads();
-      for (int idx = tid; idx < a * k2; idx += NT) {
+      for (int idx = tid; idx < a * k2; idx += NTB) {
         const int i = idx / k2, q = idx % k2;
         double s = 0.0;
         for (int e = 0; e < nb; ++e) s += M[(size_t)i * nb + e] * Vt[q * nb + e];
         US[idx] = s;
       }
     } else {
-      for (int idx = tid; idx < a * ng; idx += NT) {
+      for (int idx = tid; idx < a * ng; idx += NTB) {
         const int i = idx / ng, j = idx % ng;
         const int q = rnk[j];
         if (q < k2) US[i * k2 + q] = G[(size_t)j * cs + i];
       }
-      for (int idx = tid; idx < nb * ng; idx += NT) {
+      for (int idx = tid; idx < nb * ng; idx += NTB) {
         const int e = idx / ng, j = idx % ng;
         const int q = rnk[j];
         if (q < k2) Vt[q * nb + e] = V[(size_t)j * ng + e];
@@ -675,7 +635,7 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     // A_{c-1} <- Q_{c-1} [U S; 0]: m2 x k2 row-major into tmp
     const int m2 = sa[c - 1] * sp[c - 1];
     const int kq = sb[c - 1];
-    for (int idx = tid; idx < m2 * k2; idx += NT) {
+    for (int idx = tid; idx < m2 * k2; idx += NTB) {
       const int i = idx / k2, q = idx % k2;
       w.tmp[idx] = i < a ? US[i * k2 + q] : 0.0;
     }
@@ -691,10 +651,10 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
   // 4. normalise site 0 and accumulate the log-scale
   const int tot0 = sa[0] * sp[0] * sb[0];
   double part = 0.0;
-  for (int idx = tid; idx < tot0; idx += NT) part += w.tmp[idx] * w.tmp[idx];
+  for (int idx = tid; idx < tot0; idx += NTB) part += w.tmp[idx] * w.tmp[idx];
   const double nrm = sqrt(block_sum_b(part, red));
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int idx = tid; idx < tot0; idx += NT) outT[idx] = w.tmp[idx] * inv;
+  for (int idx = tid; idx < tot0; idx += NTB) outT[idx] = w.tmp[idx] * inv;
   if (tid == 0) {
     lsb[r] = nrm > 0.0 ? ls_prev + log(nrm) : -INFINITY;
     for (int c = 0; c < P.L2; ++c)
@@ -704,7 +664,7 @@ __global__ void __launch_bounds__(NT) k_compress_big(Prob P, int dir, int r, con
     __syncthreads();
     float* o32 = (float*)(ws + (size_t)ch * P.chain_stride + (dir == 0 ? P.off_top32 : P.off_bot32)) +
                  (size_t)r * P.L2 * P.TS;
-    for (int idx = tid; idx < P.L2 * P.TS; idx += NT) o32[idx] = (float)outT[idx];
+    for (int idx = tid; idx < P.L2 * P.TS; idx += NTB) o32[idx] = (float)outT[idx];
   }
 }
 
@@ -712,7 +672,7 @@ size_t compress_big_T_doubles(const Prob& P) { return (size_t)P.L2 * P.chi * P.D
 
 hipError_t launch_compress_big(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                                double* ws, int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_compress_big, dim3(n), dim3(NT), 0, st, P, dir, r, theta, configs, ws, status);
+  hipLaunchKernelGGL(k_compress_big, dim3(n), dim3(NTB), 0, st, P, dir, r, theta, configs, ws, status);
   return hipGetLastError();
 }
 

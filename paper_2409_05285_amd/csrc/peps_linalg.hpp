@@ -144,7 +144,7 @@ __device__ inline void wg_jacobi(double* G, int mg, int ng, int cs, double* V, i
   if (ng < 2) return;
   const int ne = ng + (ng & 1);
   const int npairs = ne / 2;
-  const int gpr = NT / JAC_LANES;  // groups per pass
+  const int gpr = (int)blockDim.x / JAC_LANES;  // groups per pass
   const int grp = tid / JAC_LANES, lane = tid % JAC_LANES;
   if (tid == 0) { flags[0] = 0; flags[1] = 0; }
   __syncthreads();
