@@ -73,7 +73,11 @@ typedef struct {
   int32_t d;         /* single-copy local dimension: 2 spin-1/2, 4 Hubbard        */
   int32_t D, chi;    /* PEPS bond dimension; boundary-MPS dimension (D_c)          */
   int32_t model;     /* PEPS_MODEL_*                                               */
-  double J1, J2;     /* Heisenberg couplings (Benchmark section, Eq. j1j2eq)       */
+  double J1, J2;     /* Heisenberg couplings (Benchmark section, Eq. j1j2eq).  On
+                        the Hubbard lattice J2 adds J2 sum_<<ij>> S_i.S_j over
+                        next-nearest-neighbour pairs (S^z = (n_up - n_dn)/2,
+                        S^+ = c^dag_up c_dn; no Jordan-Wigner sign); 0 gives the
+                        plain Hubbard model                                      */
   double t, U, mu;   /* Hubbard parameters (Benchmark section, Eq. hubbard_model)  */
   int32_t precision; /* PEPS_PREC_*: FP64 throughout, or FP32 contractions with
                         FP64 truncation / reductions / log-scales                  */
@@ -191,7 +195,10 @@ peps_status peps_vjp_batch(const peps_desc* desc, int64_t n, const uint8_t* conf
    are exact multiples of 1/8.  configs [n][N] uint8.  Enqueues one kernel;
    no workspace.  Off-diagonal correlations such as sum S_i.S_j over a bond
    set are local energies of a Hamiltonian with those couplings (J1, J2 of
-   peps_desc; peps_eval_batch), halved. */
+   peps_desc; peps_eval_batch), halved: with J2 = 1 and every other coupling
+   0 (J1 = 0; Hubbard t = U = mu = 0) the mean local energy over 2 M is the
+   next-nearest-neighbour spin correlation F of the Benchmark section, M the
+   number of such pairs. */
 peps_status peps_observables_batch(const peps_desc* desc, int64_t n, const uint8_t* configs, double* out,
                                    peps_stream_t stream);
 

@@ -86,3 +86,18 @@ def thermal_energy(evals, beta):
         w = np.exp(-b * (evals - e0))
         out[k] = float(np.dot(w, evals) / w.sum())
     return out
+
+
+def thermal_specific_heat(evals, beta, N):
+    """Specific heat per site C_v = beta^2 (<E^2> - <E>^2) / N, the canonical
+    fluctuation formula (equal to -beta^2 dE/dbeta / N)."""
+    evals = np.asarray(evals, dtype=np.float64)
+    e0 = evals.min()
+    beta = np.atleast_1d(np.asarray(beta, dtype=np.float64))
+    out = np.empty_like(beta)
+    for k, b in enumerate(beta):
+        w = np.exp(-b * (evals - e0))
+        w /= w.sum()
+        m = float(np.dot(w, evals))
+        out[k] = b * b * float(np.dot(w, (evals - m) ** 2)) / N
+    return out

@@ -20,6 +20,15 @@ Models:
     s = n_up + 2 n_dn; Jordan-Wigner mode order: sites row-major, up before
     down (mode 2 i + sigma).  <t| c^dag_a c_b |s> = (-1)^(number of occupied
     modes strictly between a and b).
+  * Optional next-nearest-neighbour spin exchange on the Hubbard lattice,
+    J2 sum_<<ij>> S_i.S_j with S^z = (n_up - n_dn)/2 and S^+_i =
+    c^dag_{i,up} c_{i,dn}.  J2 = 0 is the plain Hubbard model; with t = U =
+    mu = 0 and J2 = 1 the local energy is the estimator of sum_<<ij>> S_i.S_j,
+    the next-nearest-neighbour spin correlation the Benchmark section reports
+    for the Hubbard model (F, divided by the number of pairs).  S^+_i S^-_j is
+    a product of two on-site bilinears whose modes are adjacent, so it carries
+    no Jordan-Wigner sign: it swaps a singly occupied up digit with a singly
+    occupied down digit.
 """
 from __future__ import annotations
 
@@ -109,6 +118,17 @@ def terms(lat, S):
                     newj = dg[j] ^ (1 << sg)
                     S2 = _with_digit(lat, S, [(i, newi), (j, newj)], side)
                     off.append((S2, -lat.t * sign, (i, j, kind, side)))
+        if lat.J2 != 0.0:
+            for (a, b) in lat.bonds_d():
+                i, j = lat.site(*a), lat.site(*b)
+                for side, dg in ((0, ks), (1, bs)):
+                    szi = 0.5 * ((dg[i] & 1) - ((dg[i] >> 1) & 1))
+                    szj = 0.5 * ((dg[j] & 1) - ((dg[j] >> 1) & 1))
+                    diag += lat.J2 * szi * szj
+                    # singly occupied (digit 1 = up, 2 = down) with opposite spins
+                    if dg[i] in (1, 2) and dg[j] in (1, 2) and dg[i] != dg[j]:
+                        S2 = _with_digit(lat, S, [(i, dg[j]), (j, dg[i])], side)
+                        off.append((S2, 0.5 * lat.J2, (i, j, "d", side)))
         return diag, off
     raise ValueError("unknown model")
 
@@ -156,6 +176,19 @@ def dense_spin_H(lat):
     return H
 
 
+def _fermion_spin_dot(cs, i, j):
+    """S_i.S_j from the Jordan-Wigner mode operators: S^z = (n_up - n_dn)/2,
+    S^+ = c^dag_up c_dn, S^- its transpose."""
+    def spin_ops(k):
+        cu, cd = cs[2 * k], cs[2 * k + 1]
+        sz = 0.5 * (cu.T @ cu - cd.T @ cd)
+        sp = cu.T @ cd
+        return sz, sp
+    szi, spi = spin_ops(i)
+    szj, spj = spin_ops(j)
+    return szi @ szj + 0.5 * (spi @ spj.T + spi.T @ spj)
+
+
 def dense_hubbard_H(lat):
     """Hubbard H as a 4^N x 4^N matrix in the occupation basis.  Modes are
     ordered (site 0 up, site 0 down, site 1 up, ...); the matrix index of a
@@ -182,6 +215,9 @@ def dense_hubbard_H(lat):
         nu = cs[2 * i].T @ cs[2 * i]
         nd = cs[2 * i + 1].T @ cs[2 * i + 1]
         Hf += lat.U * nu @ nd - lat.mu * (nu + nd)
+    if lat.J2 != 0.0:
+        for i, j in ((lat.site(*a), lat.site(*b)) for a, b in lat.bonds_d()):
+            Hf += lat.J2 * _fermion_spin_dot(cs, i, j)
     # mode-basis index: mode 0 most significant bit.  Map to digit basis.
     perm = np.zeros(dimf, dtype=np.int64)
     for idx in range(dimf):

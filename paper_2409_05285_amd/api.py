@@ -9,6 +9,7 @@ and raises on a recorded failure.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from dataclasses import dataclass
 
 import torch
@@ -318,6 +319,42 @@ def thermal_observables(desc: Desc, configs, beta_phys, weights=None):
     N = desc.N
     return {"mz2_per_site": m[1] / N, "chi": beta_phys * m[1] / N, "n_per_site": m[2] / N,
             "docc_per_site": m[3] / N, "mz_per_site": m[0] / N}
+
+
+def nnn_spin_correlation(desc: Desc, theta, configs, weights=None):
+    """F = sum_<<ij>> <S_i.S_j> / M over the M = 2 (L1-1)(L2-1)
+    next-nearest-neighbour pairs (Benchmark section, Hubbard model; also
+    defined for spins): local energies of the Hamiltonian sum_<<ij>> S_i.S_j
+    (J2 = 1, every other coupling 0) from peps_eval_batch, averaged with
+    `weights` (Eq. A1) when given and halved.  Returns (F, per-sample local
+    values); synchronises."""
+    d = dataclasses.replace(desc, J1=0.0, J2=1.0, t=0.0, U=0.0, mu=0.0)
+    _, _, e, status = peps_eval_batch(d, theta, configs)
+    check(status, "nnn_spin_correlation")
+    if weights is None:
+        m = float(e.mean())
+    else:
+        w = weights.to(torch.float64)
+        m = float((w * e).sum() / w.sum())
+    M = 2 * (desc.L1 - 1) * (desc.L2 - 1)
+    return m / (2.0 * M), e
+
+
+def specific_heat(betas, energies, smoothing=None, weights=None):
+    """C_v(beta) = -beta^2 dE/dbeta from energies per site on a beta grid,
+    through a smoothing cubic spline fitted to E(beta) and differentiated
+    (Benchmark section: the specific heat from a spline fit of the energy).
+    `smoothing` is the spline's residual budget (scipy's `s`; None
+    interpolates), `weights` the inverse standard errors.  Host only; returns
+    an array aligned with `betas`."""
+    import numpy as np
+    from scipy.interpolate import UnivariateSpline
+    b = np.asarray(betas, dtype=np.float64)
+    e = np.asarray(energies, dtype=np.float64)
+    if b.ndim != 1 or b.shape != e.shape or b.size < 5 or np.any(np.diff(b) <= 0):
+        raise ValueError("specific_heat: need >= 5 increasing betas and matching energies")
+    spl = UnivariateSpline(b, e, w=weights, k=3, s=0.0 if smoothing is None else smoothing)
+    return -b * b * spl.derivative()(b)
 
 
 class PepsLogAmp(torch.autograd.Function):

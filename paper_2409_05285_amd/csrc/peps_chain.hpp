@@ -129,6 +129,22 @@ __device__ inline bool bond_proposal(const Prob& P, int Sa, int Sb, int k, int& 
   return true;
 }
 
+// Spin exchange S^+_a S^-_b + S^-_a S^+_b on one side (0: ket digits, 1: bra
+// digits) of two sites: the exchanged configuration, or false when the term
+// vanishes.  Heisenberg: the two spins differ.  Hubbard (digit n_up + 2 n_dn):
+// both sites singly occupied with opposite spins; the two on-site bilinears
+// c^dag_up c_dn act on adjacent Jordan-Wigner modes, so the term carries no
+// sign.
+__device__ inline bool spin_exchange(const Prob& P, int Sa, int Sb, int side, int& na, int& nb) {
+  const int a = side == 0 ? ket_of(P, Sa) : bra_of(P, Sa);
+  const int b = side == 0 ? ket_of(P, Sb) : bra_of(P, Sb);
+  if (a == b) return false;
+  if (P.model == PEPS_MODEL_HUBBARD && (a == 0 || a == 3 || b == 0 || b == 3)) return false;
+  na = side == 0 ? merge(P, b, bra_of(P, Sa)) : merge(P, ket_of(P, Sa), b);
+  nb = side == 0 ? merge(P, a, bra_of(P, Sb)) : merge(P, ket_of(P, Sb), a);
+  return true;
+}
+
 __device__ inline bool site_proposal(const Prob& P, int S, int k, int& ns) {
   int s = ket_of(P, S), sp = bra_of(P, S);
   if (P.model == PEPS_MODEL_HEISENBERG) {

@@ -122,12 +122,6 @@ __device__ inline double rsqrt_nr(double x) {
   r = r * fma(-h * r, r, 1.5);
   return r;
 }
-// One Newton step (about 1e-14 relative): enough where the value only sets
-// a rotation angle, which the next sweep corrects, and not its orthogonality.
-__device__ inline double rsqrt_nr1(double x) {
-  const double r = __builtin_amdgcn_rsq(x);
-  return r * fma(-0.5 * x * r, r, 1.5);
-}
 __device__ inline double rcp_nr1(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   return fma(r, fma(-x, r, 1.0), r);
@@ -259,13 +253,14 @@ __device__ void jacobi64(double* G, int mg, int ng, double* V, int* flags) {
           // ((1 + cos 2theta) / 2, sin 2theta / 2).  That vector is
           // normalised by a full-precision 1/sqrt, so c^2 + s^2 = 1 to
           // rounding whatever the error of 1/r, which only perturbs the
-          // angle (the next sweep corrects it).  Out of range of d^2 + e^2:
+          // angle (the next sweep corrects it): 1/r is the hardware
+          // estimate, unrefined.  Out of range of d^2 + e^2:
           // the same angle through the cotangent.
           const double d = be - al, e = 2.0 * ga;
           const double r2 = fma(d, d, e * e);
           double c, s;
           if (r2 < 1.0e300 && r2 > 1.0e-300) {
-            const double u = rsqrt_nr1(r2);
+            const double u = __builtin_amdgcn_rsq(r2);   // sets the angle only
             const double h = fma(0.5 * fabs(d), u, 0.5);
             const double q = (d >= 0.0 ? 0.5 : -0.5) * e * u;
             const double w = rsqrt_nr(fma(h, h, q * q));

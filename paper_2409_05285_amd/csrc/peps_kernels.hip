@@ -287,12 +287,23 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
     }
   }
   if (P.model == PEPS_MODEL_HUBBARD) {
-    // U n_up n_dn - mu (n_up + n_dn) on every site, ket and bra digits
+    // U n_up n_dn - mu (n_up + n_dn) on every site, ket and bra digits;
+    // J2 S^z_i S^z_j on next-nearest-neighbour pairs, S^z = (n_up - n_dn)/2
     for (int side = 0; side < 2; ++side)
       for (int i = 0; i < P.N; ++i) {
         const int dg = side == 0 ? S[i] / P.d : S[i] % P.d;
         const int nu = dg & 1, nd = (dg >> 1) & 1;
         diag += P.U * (nu * nd) - P.mu * (nu + nd);
+        const int rr = i / P.L2, c = i % P.L2;
+        if (P.J2 != 0.0 && rr + 1 < P.L1) {
+          const int zi = nu - nd;   // 2 S^z_i
+          for (int dc = -1; dc <= 1; dc += 2) {
+            if (c + dc < 0 || c + dc >= P.L2) continue;
+            const int dj = side == 0 ? S[i + P.L2 + dc] / P.d : S[i + P.L2 + dc] % P.d;
+            const int zj = (dj & 1) - ((dj >> 1) & 1);
+            diag += P.J2 * 0.25 * zi * zj;
+          }
+        }
       }
   }
   double e = diag;

@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
 
 // Cross-row local-energy terms between rows r and r+1 (two-row strip):
 // vertical bonds (exchanges, or hops with their Jordan-Wigner signs), and
-// next-nearest-neighbour bonds when J2 != 0.
+// the spin exchange on next-nearest-neighbour bonds when J2 != 0.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
                                               double* ws, int32_t* status) {
@@ -456,22 +456,21 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
       const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
       e += bond_coeff(P, S, i, j, k, P.J1) * tracked_ratio(rn, eA.E + sh.Re[c + 1], rho, rhoE);
     }
-    if (P.model == PEPS_MODEL_HEISENBERG) {
-      if (P.J2 != 0.0 && c < P.L2 - 1) {
-        // bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c)
-        for (int orient = 0; orient < 2; ++orient) {
-          const int sa = orient == 0 ? i : i + 1;    // site in row r
-          const int sbs = orient == 0 ? j + 1 : j;   // site in row r+1
-          for (int k = 0; k < 2; ++k) {
-            int na, nb;
-            if (!bond_proposal(P, S[sa], S[sbs], k, na, nb)) continue;
-            int s1c = S[i], s1n = S[i + 1], s2c = S[j], s2n = S[j + 1];
-            if (orient == 0) { s1c = na; s2n = nb; } else { s1n = na; s2c = nb; }
-            const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, s1c, s2c);
-            const Env eB = lstep2_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, s1n, s2n);
-            const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env2_size(P, sh.sc, r, c + 1), sh.red);
-            e += 0.5 * P.J2 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
-          }
+    if (P.J2 != 0.0 && c < P.L2 - 1) {
+      // spin exchange on the bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c), ket
+      // then bra side (the J2 coupling of either model)
+      for (int orient = 0; orient < 2; ++orient) {
+        const int sa = orient == 0 ? i : i + 1;    // site in row r
+        const int sbs = orient == 0 ? j + 1 : j;   // site in row r+1
+        for (int side = 0; side < 2; ++side) {
+          int na, nb;
+          if (!spin_exchange(P, S[sa], S[sbs], side, na, nb)) continue;
+          int s1c = S[i], s1n = S[i + 1], s2c = S[j], s2n = S[j + 1];
+          if (orient == 0) { s1c = na; s2n = nb; } else { s1n = na; s2c = nb; }
+          const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, s1c, s2c);
+          const Env eB = lstep2_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, s1n, s2n);
+          const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env2_size(P, sh.sc, r, c + 1), sh.red);
+          e += 0.5 * P.J2 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
         }
       }
     }

@@ -689,3 +689,89 @@ def test_parity_even_ansatz_vanishes_on_odd_configurations():
         elif a != 0.0:
             n_even_nonzero += 1
     assert n_odd > 100 and n_even_nonzero > 100
+
+
+# ---------------------------------------------------------------------------
+# Next-nearest-neighbour spin correlation on the Hubbard lattice (Benchmark
+# section, F) and the specific heat from E(beta).
+
+def test_terms_hubbard_nnn_exchange_match_jordan_wigner_H():
+    """The J2 S_i.S_j terms of the Hubbard local energy (no Jordan-Wigner sign
+    on the exchange) against S_i.S_j built from the fermion mode operators with
+    explicit sigma^z strings, together with hops, U and mu."""
+    lat = Lattice(2, 3, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0, J2=0.75)
+    rng = np.random.default_rng(5)
+    samples = rng.integers(0, 16, size=(500, 6))
+    _check_terms_against_dense(lat, samples)
+
+
+def test_fermion_spin_dot_is_su2_invariant_with_closed_form_spectrum():
+    """sum_<<ij>> S_i.S_j on 2x2 (pairs (0,3), (1,2)) built from fermion
+    operators commutes with S^z_tot and S^+_tot = sum_i c^dag_i,up c_i,dn
+    (a wrong relative sign of the exchange breaks the second), and its
+    spectrum is the sum of two independent pairs, each with -3/4 (singlet),
+    1/4 (x3, triplet) on the singly occupied states and 0 on the other 12."""
+    from functools import reduce
+    lat = Lattice(2, 2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=0.0, U=0.0, mu=0.0, J2=1.0)
+    H = hamiltonian.dense_H(lat)
+    N, M = 4, 8
+    a = np.array([[0.0, 1.0], [0.0, 0.0]])
+    zz, i2 = np.diag([1.0, -1.0]), np.eye(2)
+    cs = [reduce(np.kron, [zz] * m + [a] + [i2] * (M - m - 1)) for m in range(M)]
+    perm = np.zeros(256, dtype=np.int64)
+    for idx in range(256):
+        occ = [(idx >> (M - 1 - m)) & 1 for m in range(M)]
+        dig = 0
+        for k in range(N):
+            dig = dig * 4 + occ[2 * k] + 2 * occ[2 * k + 1]
+        perm[dig] = idx
+    sp = sum(cs[2 * i].T @ cs[2 * i + 1] for i in range(N))[np.ix_(perm, perm)]
+    sz = sum(0.5 * (cs[2 * i].T @ cs[2 * i] - cs[2 * i + 1].T @ cs[2 * i + 1]) for i in range(N))[np.ix_(perm, perm)]
+    assert np.abs(H @ sp - sp @ H).max() < 1e-14
+    assert np.abs(H @ sz - sz @ H).max() < 1e-14
+    one = np.array([-0.75] + [0.25] * 3 + [0.0] * 12)
+    want = np.sort((one[:, None] + one[None, :]).ravel())
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(H)), want, atol=1e-13)
+
+
+def test_nnn_spin_correlation_vanishes_at_infinite_temperature():
+    """beta = 0 (|I>): only diagonal configurations carry weight, all equally;
+    every exchange target is off-diagonal (rho = 0), and the S^z_i S^z_j
+    values average to 0, so F = 0 (Tr S_i.S_j = 0 for i != j)."""
+    lat = Lattice(2, 3, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=0.0, U=0.0, mu=0.0, J2=1.0)
+    tot = 0.0
+    for s in itertools.product(range(4), repeat=6):
+        S = [x * 4 + x for x in s]
+        diag, off = hamiltonian.terms(lat, S)
+        for S2, _, _ in off:
+            assert any(lat.ket(x) != lat.bra(x) for x in S2)
+        tot += diag
+    assert tot == pytest.approx(0.0, abs=1e-10)
+
+
+def test_thermal_specific_heat_is_the_energy_derivative():
+    """C_v = beta^2 (<E^2> - <E>^2) / N equals -beta^2 dE/dbeta / N (central
+    difference of the ED energy), on 3x3 J1-J2."""
+    lat = Lattice(3, 3, D=1, chi=1, J1=1.0, J2=0.5)
+    ev = ed.spin_spectrum(lat)
+    for b in (0.3, 1.0, 2.5):
+        h = 1e-4
+        de = (ed.thermal_energy(ev, b + h)[0] - ed.thermal_energy(ev, b - h)[0]) / (2 * h)
+        assert ed.thermal_specific_heat(ev, b, lat.N)[0] == pytest.approx(-b * b * de / lat.N, rel=1e-6)
+
+
+def test_specific_heat_spline_matches_fluctuation_formula():
+    """The package's spline-derivative C_v from E(beta)/N on a beta grid (the
+    Benchmark section's procedure) against the exact fluctuation formula, 3x3
+    J1-J2 ED, away from the grid ends."""
+    import paper_2409_05285_amd as p
+    lat = Lattice(3, 3, D=1, chi=1, J1=1.0, J2=0.5)
+    ev = ed.spin_spectrum(lat)
+    betas = np.linspace(0.05, 4.0, 80)
+    e = ed.thermal_energy(ev, betas) / lat.N
+    cv = p.specific_heat(betas, e)
+    exact = ed.thermal_specific_heat(ev, betas, lat.N)
+    inner = slice(3, -3)
+    assert np.max(np.abs(cv[inner] - exact[inner])) <= 1e-3 * np.max(exact)
+    with pytest.raises(ValueError):
+        p.specific_heat(betas[::-1], e)
