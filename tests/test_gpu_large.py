@@ -123,3 +123,52 @@ def test_large_chi_sweep_bit_exact():
     e = float(res["e_loc"].cpu().numpy()[0, 0])
     assert abs(la - m["log_abs"]) <= 1e-9 * max(1.0, abs(m["log_abs"]))
     assert abs(e - m["e_loc"]) <= 1e-9 * max(abs(m["e_loc"]), 1.0)
+
+
+def test_large_chi_last_row_O_matches_central_differences():
+    """The adjoint O rows against central differences of log|psi| (h = 1e-6,
+    FP64) at this lattice's full shape.  For an entry of the last row the
+    identity is exact under truncation: log|psi| = log|rho_{L1-1}|, the top
+    boundary above that row does not depend on it and rho_{L1-1} is linear in
+    it, so d log|psi| / d theta_k = O_k; a sample whose slice at that site
+    differs has derivative 0.  Six entries (largest |O| of a site block, three
+    per sample), both samples evaluated at every shift."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    _say("12x12 J1-J2 D=6 chi=36 O vs central differences")
+    lat = Lattice(L1, L2, D=D, chi=CHI, J1=1.0, J2=J2)
+    desc = p.Desc(L1, L2, D, CHI, J1=1.0, J2=J2)
+    th = synth.theta_random_unit(L1, L2, D, 2, seed=103)
+    cfg = synth.configs_sector(2, lat.N, 2, seed=1203)
+    cfg_d = torch.tensor(cfg, device=dev)
+    theta_d = torch.tensor(th, device=dev)
+    O, la0, st = p.peps_grad_batch(desc, theta_d, cfg_d)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    O = O.cpu().numpy()
+    poff, _ = lat.param_offsets()
+    ooff, _ = lat.orow_offsets()
+    r = L1 - 1
+    picks = []
+    for j, cols in ((0, (1, 5, 10)), (1, (0, 6, 11))):
+        for c in cols:
+            i = lat.site(r, c)
+            bs = lat.block_size(r, c)
+            q = int(np.argmax(np.abs(O[j, ooff[i]:ooff[i] + bs])))
+            picks.append((i, int(cfg[j, i]), bs, q))
+    h = 1e-6
+    for (i, s, bs, q) in picks:
+        k = poff[i] + s * bs + q
+        vals = []
+        for sgn in (1.0, -1.0):
+            t = th.copy()
+            t[k] += sgn * h
+            la, _, _, st = p.peps_eval_batch(desc, torch.tensor(t, device=dev), cfg_d)
+            torch.cuda.synchronize()
+            assert p.check(st) == 0
+            vals.append(la.cpu().numpy())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        for j in range(2):
+            want = O[j, ooff[i] + q] if int(cfg[j, i]) == s else 0.0
+            print("[fd] site %d slice %d entry %d sample %d: O %.12f fd %.12f" % (i, s, q, j, want, fd[j]), flush=True)
+            assert abs(fd[j] - want) <= 1e-5 * max(1.0, abs(want)), (i, q, j, fd[j], want)
