@@ -325,26 +325,72 @@ __device__ void apply_q_blocked(const double* X, int m, int k, const double* Tst
   }
 }
 
-// One inner round-robin sweep over the nl columns held in LDS (column
-// stride ld; local column j < n1 at slot j, later ones at slot bw + j - n1):
-// one barrier per round.  Returns nonzero (on every thread) when some pair
-// was rotated.
-__device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int n1, int bw, int* flag) {
+// 1 / sqrt(x) from the hardware estimate and two Newton steps (double
+// precision).
+__device__ inline double rsqrt2(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
+// Pair (ci, cj) of round rnd of the circle (round-robin) order on ne
+// (even) columns, or false when it touches the padding column ne - 1 >= n.
+__device__ inline bool circle_pair(int rnd, int pr, int ne, int n, int& ci, int& cj) {
+  if (pr == 0) { ci = rnd; cj = ne - 1; }
+  else { ci = (rnd + pr) % (ne - 1); cj = (rnd - pr + ne - 1) % (ne - 1); }
+  if (ci > cj) { const int t = ci; ci = cj; cj = t; }
+  return cj < n;
+}
+
+// Pair schedules of one LDS pass over two column blocks of n1 and n2
+// columns (local columns 0..n1-1 and n1..n1+n2-1):
+//   SWEEP_ALL    every pair of the n1 + n2 columns (circle order);
+//   SWEEP_INTRA  the pairs inside each block, both blocks side by side;
+//   SWEEP_CROSS  the n1 n2 pairs between the blocks: in round t column a
+//                of the first block meets column (a + t) mod max(n1, n2)
+//                of the second.
+enum { SWEEP_ALL = 0, SWEEP_INTRA = 1, SWEEP_CROSS = 2 };
+
+// One pass over the columns held in LDS (column stride ld; local column
+// j < n1 at slot j, later ones at slot bw + j - n1) in the given schedule:
+// one barrier per round.  Returns nonzero (on every thread) when some
+// rotation was above the stopping threshold.
+__device__ __forceinline__ int lds_sweep(double* Gl, int mg, int n1, int n2, int ld, int bw, int mode, int* flag) {
   const int tid = threadIdx.x;
-  const int ne = nl + (nl & 1), npairs = ne / 2;
+  const int nl = n1 + n2;
+  const int ne = nl + (nl & 1);
+  const int e1 = n1 + (n1 & 1), e2 = n2 + (n2 & 1);
+  const int mx = n1 > n2 ? n1 : n2;
+  const int npairs = mode == SWEEP_ALL ? ne / 2 : (mode == SWEEP_INTRA ? e1 / 2 + e2 / 2 : n1);
+  const int rounds = mode == SWEEP_ALL ? ne - 1 : (mode == SWEEP_INTRA ? (e1 > e2 ? e1 : e2) - 1 : mx);
+  if (npairs <= 0 || rounds <= 0) return 0;
   const int q = NTB / npairs;
   const int lp = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : (q >= 2 ? 2 : 1)));
   const int gpr = NTB / lp;
   const int grp = tid / lp, li = tid % lp;
   if (tid == 0) *flag = 0;
   __syncthreads();
-  for (int rnd = 0; rnd < ne - 1; ++rnd) {
+  for (int rnd = 0; rnd < rounds; ++rnd) {
     for (int pr = grp; pr < npairs; pr += gpr) {
       int ci, cj;
-      if (pr == 0) { ci = rnd; cj = ne - 1; }
-      else { ci = (rnd + pr) % (ne - 1); cj = (rnd - pr + ne - 1) % (ne - 1); }
-      if (ci > cj) { const int t = ci; ci = cj; cj = t; }
-      if (cj >= nl) continue;
+      if (mode == SWEEP_ALL) {
+        if (!circle_pair(rnd, pr, ne, nl, ci, cj)) continue;
+      } else if (mode == SWEEP_INTRA) {
+        if (pr < e1 / 2) {
+          if (rnd >= e1 - 1 || !circle_pair(rnd, pr, e1, n1, ci, cj)) continue;
+        } else {
+          if (rnd >= e2 - 1 || !circle_pair(rnd, pr - e1 / 2, e2, n2, ci, cj)) continue;
+          ci += n1;
+          cj += n1;
+        }
+      } else {
+        const int b = (pr + rnd) % mx;
+        if (b >= n2) continue;
+        ci = pr;
+        cj = n1 + b;
+      }
       double* gi = Gl + (ci < n1 ? ci : bw + ci - n1) * ld;
       double* gj = Gl + (cj < n1 ? cj : bw + cj - n1) * ld;
       // the pair's rows are loaded into registers in one batch (EMAX per
@@ -381,13 +427,24 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int
       sg = group_sum(sg, lp);
       if (sg != 0.0 && sg * sg > (JAC_TOL * JAC_TOL) * (sa * sb)) {
         // Rutishauser's angle from the double angle (d = sb - sa, e = 2 sg):
-        // (c, s) parallel to ((1 + |d|/r) / 2, sign(d) e / (2 r)), normalised
-        // by a correctly rounded 1/sqrt so that c^2 + s^2 = 1 to rounding
+        // (c, s) parallel to ((1 + |d|/r) / 2, sign(d) e / (2 r)).  1/r is
+        // the hardware estimate (it only sets the angle, which the next
+        // sweep corrects); the normalisation uses a refined 1/sqrt, so that
+        // c^2 + s^2 = 1 to rounding.  Outside the estimate's range of
+        // d^2 + e^2 the divisions are exact.
         const double d = sb - sa, e = 2.0 * sg;
-        const double r = sqrt(fma(d, d, e * e));
-        const double h = 0.5 + 0.5 * fabs(d) / r;
-        const double qv = (d >= 0.0 ? 0.5 : -0.5) * e / r;
-        const double w = 1.0 / sqrt(fma(h, h, qv * qv));
+        const double r2 = fma(d, d, e * e);
+        double h, qv;
+        if (r2 < 1.0e300 && r2 > 1.0e-300) {
+          const double u = __builtin_amdgcn_rsq(r2);
+          h = fma(0.5 * fabs(d), u, 0.5);
+          qv = (d >= 0.0 ? 0.5 : -0.5) * e * u;
+        } else {
+          const double r = sqrt(r2);
+          h = 0.5 + 0.5 * fabs(d) / r;
+          qv = (d >= 0.0 ? 0.5 : -0.5) * e / r;
+        }
+        const double w = rsqrt2(fma(h, h, qv * qv));
         const double c = h * w, s = qv * w;
         if (staged) {
 #pragma unroll
@@ -418,10 +475,13 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int nl, int ld, int
 }
 
 // Block one-sided Jacobi on G (mg x ng, column-major, stride cs) in the
-// workspace: the columns form blocks of bw; every pair of blocks (round-
-// robin over blocks) is loaded into LDS (2 bw columns), swept once there,
-// and written back.  An outer sweep without any rotation ends it.  With a
-// single block the block is swept in LDS until no pair rotates.
+// workspace: the columns form blocks of bw.  An outer sweep first rotates
+// the pairs inside every block (two blocks per LDS pass), then, for every
+// pair of blocks (round-robin over blocks), loads both into LDS (2 bw
+// columns), rotates the pairs between them once and writes them back: each
+// column pair once per outer sweep, as in the cyclic method.  An outer sweep
+// whose rotations all stay below the stopping threshold is the last.  With
+// a single block the block is swept in LDS until no pair rotates.
 __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs, double* Gl, int* flags) {
   const int tid = threadIdx.x;
   if (ng < 2) return;
@@ -449,7 +509,7 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
     load(0, 0);
     __syncthreads();
     for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep)
-      if (!lds_sweep(Gl, mg, ng, ld, ng, bw, flags)) break;
+      if (!lds_sweep(Gl, mg, ng, 0, ld, bw, SWEEP_ALL, flags)) break;
     store(0, 0, ng);
     __syncthreads();
     return;
@@ -457,6 +517,14 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
   const int nbe = nblk + (nblk & 1);
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
     int any = 0;
+    for (int b = 0; b < nblk; b += 2) {
+      const int n1 = load(b, 0), n2 = b + 1 < nblk ? load(b + 1, 1) : 0;
+      __syncthreads();
+      any |= lds_sweep(Gl, mg, n1, n2, ld, bw, SWEEP_INTRA, flags + 1);
+      store(b, 0, n1);
+      if (n2) store(b + 1, 1, n2);
+      __syncthreads();
+    }
     for (int rnd = 0; rnd < nbe - 1; ++rnd)
       for (int pr = 0; pr < nbe / 2; ++pr) {
         int b1, b2;
@@ -465,7 +533,7 @@ __device__ __forceinline__ void jacobi_blocked(double* G, int mg, int ng, int cs
         if (b1 >= nblk || b2 >= nblk) continue;
         const int n1 = load(b1, 0), n2 = load(b2, 1);
         __syncthreads();
-        any |= lds_sweep(Gl, mg, n1 + n2, ld, n1, bw, flags + 1);
+        any |= lds_sweep(Gl, mg, n1, n2, ld, bw, SWEEP_CROSS, flags + 1);
         store(b1, 0, n1);
         store(b2, 1, n2);
         __syncthreads();
