@@ -385,8 +385,9 @@ def main():
     ap.add_argument("--tau", type=float, default=0.02)
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-4, help="energy error bar of the mixed path (relative)")
-    ap.add_argument("--cool-steps", type=int, default=10,
-                    help="FP64 SR steps from the identity before the cooled-state energy check")
+    ap.add_argument("--cool-steps", type=int, default=50,
+                    help="FP64 SR steps from the identity before the cooled-state energy check "
+                         "(beta_phys = 4 * steps * tau = 4 by default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both",
                     help="run one precision only (profiling runs); the JSON line then carries that path")
