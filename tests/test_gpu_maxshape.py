@@ -1,0 +1,107 @@
+"""Bond dimension D = 8 and the largest boundary shape the library accepts.
+
+* 4x4, D = 8, chi = 16 (chi D = 128): evaluation, O rows and one sweep
+  against the oracle, FP64 and mixed, at the bars of the other parity tests.
+* 6x6, D = 8, chi = 64 (chi D = 512, the limit): the interior sites reach
+  4096 x 512 QR matrices and 512-column truncations, so the workspace-resident
+  kernel's streamed paths (QR columns and Jacobi columns longer than its
+  register batches) run; evaluation and O rows of two samples in FP64 against
+  the oracle.  The bars are those of the 12x12, chi = 36 lattice (1e-9 on
+  log|psi| and E_loc, 1e-8 on O), for the same reason: many truncations of a
+  large matrix, conditioned at that level.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import measure, sampler
+from oracle.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _check(p, lat, desc, th, cfg, chi, tol_e, tol_o, mixed):
+    dev = _dev()
+    theta_d = torch.tensor(th, device=dev)
+    cfg_d = torch.tensor(cfg, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    la, sg, el, st = p.peps_eval_batch(desc, theta_d, cfg_d)
+    O, _, st2 = p.peps_grad_batch(desc, theta_d, cfg_d)
+    torch.cuda.synchronize()
+    print("[time] device eval + grad of %d samples: %.2f s" % (cfg.shape[0], time.perf_counter() - t0), flush=True)
+    assert p.check(st) == 0 and p.check(st2) == 0
+    ref = measure.evaluate_batch(lat, th, cfg, chi)
+    la, sg, el, O = (x.cpu().numpy() for x in (la, sg, el, O))
+    assert np.all(np.abs(la - ref["log_abs"]) <= tol_e * np.maximum(1.0, np.abs(ref["log_abs"]))), (la, ref["log_abs"])
+    assert np.array_equal(sg, ref["sign"])
+    emag = max(np.abs(ref["e_loc"]).mean(), 1e-300)
+    assert np.all(np.abs(el - ref["e_loc"]) <= tol_e * np.maximum(np.abs(ref["e_loc"]), emag)), (el, ref["e_loc"])
+    if mixed:
+        for i in range(O.shape[0]):
+            assert np.all(np.abs(O[i] - ref["O"][i]) <= 1e-4 * np.abs(ref["O"][i]).max())
+    else:
+        assert np.all(np.abs(O - ref["O"]) <= tol_o * np.maximum(1.0, np.abs(ref["O"])))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_bond_dimension_8(mixed):
+    import paper_2409_05285_amd as p
+    _say("4x4 D=8 chi=16", "mixed" if mixed else "fp64")
+    lat = Lattice(4, 4, D=8, chi=16)
+    desc = p.Desc(4, 4, 8, 16, precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = synth.theta_random_unit(4, 4, 8, 2, seed=7)
+    cfg = synth.configs_sector(3, 16, 2, seed=44)
+    tol = 1e-4 if mixed else 1e-10
+    _check(p, lat, desc, th, cfg, 16, tol, 1e-9, mixed)
+
+
+def test_bond_dimension_8_sweep_bit_exact():
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    _say("4x4 D=8 chi=16 sweep")
+    lat = Lattice(4, 4, D=8, chi=16)
+    desc = p.Desc(4, 4, 8, 16)
+    th = synth.theta_random_unit(4, 4, 8, 2, seed=7)
+    cfg = synth.configs_diagonal(3, 16, 2, seed=45)
+    cfg_d = torch.tensor(cfg, device=dev)
+    res = p.peps_sample_sweep(desc, torch.tensor(th, device=dev), cfg_d, 5, 0, 1)
+    torch.cuda.synchronize()
+    assert p.check(res["status"]) == 0
+    got = cfg_d.cpu().numpy()
+    acc = res["n_accept"].cpu().numpy()
+    compared = 0
+    for ch in range(cfg.shape[0]):
+        r = sampler.sweep(lat, th, cfg[ch].astype(np.int64), 16, 5, ch, 0, tie_tol=1e-12)
+        if r["near_ties"]:
+            continue
+        compared += 1
+        assert np.array_equal(got[ch], r["S"].astype(np.uint8)), ch
+        assert np.array_equal(acc[ch], r["n_accept"]), ch
+    assert compared >= 2
+
+
+def test_largest_boundary_shape():
+    import paper_2409_05285_amd as p
+    _say("6x6 D=8 chi=64 (chi D = 512)")
+    lat = Lattice(6, 6, D=8, chi=64)
+    desc = p.Desc(6, 6, 8, 64)
+    th = synth.theta_random_unit(6, 6, 8, 2, seed=7)
+    cfg = synth.configs_sector(2, 36, 2, seed=46)
+    _check(p, lat, desc, th, cfg, 64, 1e-9, 1e-8, False)
