@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--D", type=int, default=4)
     ap.add_argument("--chi", type=int, default=16)
     ap.add_argument("--J2", type=float, default=0.0, help="next-nearest-neighbour coupling (J1 = 1)")
+    ap.add_argument("--model", choices=["heisenberg", "hubbard"], default="heisenberg",
+                    help="hubbard (with --only): t = 1, U = 8, mu = 4, d^2 = 16, random parity-even tensors")
     ap.add_argument("--chains", type=int, default=1024)
     ap.add_argument("--cg-iters", type=int, default=200)
     ap.add_argument("--tau", type=float, default=0.02)
@@ -408,11 +410,21 @@ def main():
     dev = torch.device("cuda:0")
     L1 = L2 = args.L
     D, chi, n = args.D, args.chi, args.chains
-    desc64 = p.Desc(L1, L2, D, chi, J2=args.J2)
-    descmx = p.Desc(L1, L2, D, chi, J2=args.J2, precision=p.PREC_MIXED)
     seed_theta, seed = 102, 20240905
-    theta0 = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
-    configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
+    if args.model == "hubbard":
+        if args.only == "both":
+            print("--model hubbard needs --only fp64 or --only mixed", file=sys.stderr)
+            sys.exit(2)
+        hub = dict(d=4, model=p.MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0, J2=args.J2)
+        desc64 = p.Desc(L1, L2, D, chi, **hub)
+        descmx = p.Desc(L1, L2, D, chi, precision=p.PREC_MIXED, **hub)
+        theta0 = torch.tensor(synth.theta_random_parity_even(L1, L2, D, 4, seed=seed_theta), device=dev)
+        configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 4, seed=7), device=dev)
+    else:
+        desc64 = p.Desc(L1, L2, D, chi, J2=args.J2)
+        descmx = p.Desc(L1, L2, D, chi, J2=args.J2, precision=p.PREC_MIXED)
+        theta0 = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
+        configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
@@ -423,7 +435,8 @@ def main():
 
     if args.only != "both":
         r = run_path(p, torch, desc64 if args.only == "fp64" else descmx, theta0, configs0, args, seed)
-        print(json.dumps({"only": args.only, "lattice": [L1, L2], "D": D, "chi": chi, "J2": args.J2, "chains": n,
+        print(json.dumps({"only": args.only, "model": args.model, "lattice": [L1, L2], "D": D, "chi": chi,
+                          "J2": args.J2, "chains": n,
                           "sweeps_per_step": args.sweeps, "samples_per_s": round(r["samples_per_s"], 2),
                           "ms_per_step": round(r["ms_per_step"], 3),
                           "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
