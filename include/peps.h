@@ -112,7 +112,10 @@ const char* peps_status_string(peps_status s);
    (Eq. 3), ratios taken from one-row strips (terms inside a row) or
    two-row strips (terms across rows).
    configs [n][N] uint8; log_abs [n] f64; sign [n] int8; e_loc [n] f64
-   (e_loc may be NULL); status: one device int32. */
+   (e_loc may be NULL); status: one device int32.  A sample whose amplitude
+   is exactly zero gets log_abs = -inf, sign 0 and an undefined (NaN) local
+   energy, and the status records PEPS_ERR_ZERO_AMPLITUDE; non-finite data
+   give NaN and PEPS_ERR_NONFINITE (the first error of a call is kept). */
 peps_status peps_eval_batch(const peps_desc* desc, const double* theta, int32_t n,
                             const uint8_t* configs, double* log_abs, int8_t* sign,
                             double* e_loc, int32_t* status, void* ws, size_t ws_bytes,

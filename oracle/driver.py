@@ -14,13 +14,18 @@ from . import measure, sampler, sr
 
 
 def cool(lat, theta0, configs0, chi, seed, n_steps, sweeps_per_step, tau, eps,
-         max_iter=200, rtol=1e-10, alpha=2, log=None):
+         max_iter=200, rtol=1e-10, alpha=2, log=None, gsweep0=0, step0=0):
+    """n_steps SR steps from (theta0, configs0).  The Metropolis uniforms are
+    positional in (chain, global sweep, slot), so a run resumed from saved
+    (theta, configs, gsweep, step) with gsweep0 and step0 continues the same
+    chain of states; every history record carries the global sweep index
+    the next step would start from."""
     theta = np.array(theta0, dtype=np.float64, copy=True)
     configs = np.array(configs0, dtype=np.int64, copy=True)
     n_chains = configs.shape[0]
-    gsweep = 0
+    gsweep = gsweep0
     history = []
-    for step in range(n_steps):
+    for step in range(step0, step0 + n_steps):
         samples, e_list, o_list = [], [], []
         for k in range(sweeps_per_step):
             for ch in range(n_chains):
@@ -37,7 +42,7 @@ def cool(lat, theta0, configs0, chi, seed, n_steps, sweeps_per_step, tau, eps,
         e = np.array(e_list)
         rec = {"step": step, "beta_phys": 4.0 * tau * step, "E_per_site": sol["ebar"] / (2 * lat.N),
                "sigma": float(e.std(ddof=1) / np.sqrt(len(e)) / (2 * lat.N)) if len(e) > 1 else 0.0,
-               "cg_iters": sol["iters"]}
+               "cg_iters": sol["iters"], "gsweep": gsweep}
         history.append(rec)
         if log is not None:
             log(rec)

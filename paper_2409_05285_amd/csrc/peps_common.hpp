@@ -173,4 +173,15 @@ __device__ inline void set_status(int32_t* status, int code) {
   if (status) atomicCAS(status, 0, code);
 }
 
+// Singular value from a column's squared norm, for ranking the columns of a
+// truncation: a non-finite norm (NaN or Inf in the data) is reported, and a
+// NaN ranks last, so that the ranks still form a permutation of the columns.
+__device__ inline double rank_norm(double sq, int32_t* status) {
+  if (!isfinite(sq)) {
+    set_status(status, PEPS_ERR_NONFINITE);
+    if (sq != sq) return -1.0;
+  }
+  return sqrt(sq);
+}
+
 }  // namespace peps

@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(NTC, 4) k_compress2(Prob P, int dir, int r, co
           s += x * x;
         }
         s = row16_sum(s);
-        if (l16 == 0) sig[j] = sqrt(s);
+        if (l16 == 0) sig[j] = rank_norm(s, status);
       }
     }
     __syncthreads();

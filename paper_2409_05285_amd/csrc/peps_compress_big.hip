@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, co
     for (int j = tid; j < ng; j += NTB) {
       double s = 0.0;
       for (int i = 0; i < mg; ++i) s += G[(size_t)j * cs + i] * G[(size_t)j * cs + i];
-      sig[j] = sqrt(s);
+      sig[j] = rank_norm(s, status);
     }
     __syncthreads();
     for (int j = tid; j < ng; j += NTB) {

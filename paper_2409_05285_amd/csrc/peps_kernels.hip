@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const d
     for (int j = tid; j < ng; j += NT) {
       double s = 0.0;
       for (int i = 0; i < mg; ++i) s += G[j * cs + i] * G[j * cs + i];
-      sig[j] = sqrt(s);
+      sig[j] = rank_norm(s, status);
     }
     __syncthreads();
     for (int j = tid; j < ng; j += NT) {
@@ -256,7 +256,7 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
   const double la = ep[2 * P.L1];
   if (log_abs) log_abs[out_off + ch] = la;
   if (sign) sign[out_off + ch] = (int8_t)ep[2 * P.L1 + 1];
-  if (!isfinite(la)) set_status(status, PEPS_ERR_NONFINITE);
+  if (isnan(la) || la == INFINITY) set_status(status, PEPS_ERR_NONFINITE);   // -inf: a zero amplitude
   if (!want_e || !e_loc) return;
   double diag = 0.0;
   if (P.model == PEPS_MODEL_HEISENBERG) {

@@ -369,10 +369,12 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
   const double rho = (double)b.R[0];
   const int rhoE = sh.Re[0];
   if (rho == 0.0 || !isfinite(rho)) {
+    // a zero amplitude has log|psi| = -inf (sign 0); its local energy and O
+    // row are undefined
     set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
     if (tid == 0) {
       w.epart[r] = NAN;
-      if (r == P.L1 - 1) { w.epart[2 * P.L1] = NAN; w.epart[2 * P.L1 + 1] = 0.0; }
+      if (r == P.L1 - 1) { w.epart[2 * P.L1] = rho == 0.0 ? -INFINITY : NAN; w.epart[2 * P.L1 + 1] = 0.0; }
     }
     return;
   }
