@@ -28,8 +28,17 @@ import torch
 from . import api
 
 
+def _mean_and_stderr(values, w):
+    """Weighted mean over all samples of [S, n] values and the standard
+    error of the per-chain weighted means."""
+    m = float((w * values).sum() / w.sum())
+    chain = (w * values).sum(axis=0) / w.sum(axis=0)
+    se = float(chain.std(ddof=1) / np.sqrt(chain.size)) if chain.size > 1 else 0.0
+    return m, se
+
+
 def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, seed, cg_iters=200, rtol=1e-10,
-         step0=0, gsweep0=0, log=None):
+         step0=0, gsweep0=0, log=None, observables=False):
     """Run n_steps SR steps; theta (float64 [N_p], device) and configs (uint8
     [n_chains, N], device) are updated in place.  `log`: a text stream that
     receives one JSON line per step.  Returns the list of records:
@@ -38,7 +47,12 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
       and sweep (horizontal exchange, site move, vertical exchange), CG
       iterations and relative residual |r| / |b|, |dtheta|, samples/s of the
       step (wall clock), and gsweep, the global sweep index the next step
-      starts from."""
+      starts from.
+    With observables=True each record also holds, from the same samples
+    and weights (Benchmark section), with standard errors: <M_z^2>/N and the
+    susceptibility beta_phys <M_z^2>/N, the particle number and double
+    occupancy per site (Hubbard), and the next-nearest-neighbour spin
+    correlation F (one more evaluation of the samples, before the update)."""
     n = configs.shape[0]
     S = int(sweeps_per_step)
     N = desc.N
@@ -66,6 +80,12 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
         if desc.alpha == 1:
             w = np.exp(la - la.max())
             weights = torch.tensor(w.reshape(S * n), device=dev)
+        obs = None
+        if observables:
+            samples = out["configs"].view(S * n, N)
+            vals = api.peps_observables_batch(desc, samples).cpu().numpy().reshape(S, n, -1)
+            _, f_loc = api.nnn_spin_correlation(desc, theta, samples)
+            obs = (vals, f_loc.cpu().numpy().reshape(S, n))
         dtheta, _, stats, _ = api.sr_cg_solve(desc, out["configs"].view(S * n, N), out["O"].view(S * n, nnz),
                                               out["e_loc"].view(S * n), tau, eps, cg_iters, rtol, weights=weights,
                                               want_g=False, theta=theta, status=status)
@@ -83,6 +103,14 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
                "cg_iters": int(st[2]), "cg_rel_residual": float(st[1] / st[3]) if st[3] > 0 else 0.0,
                "dtheta_norm": float(np.linalg.norm(dtheta.cpu().numpy())), "samples_per_s": n * S / wall,
                "gsweep": gsweep}
+        if obs is not None:
+            vals, f_loc = obs
+            M = 2 * (desc.L1 - 1) * (desc.L2 - 1)
+            for k, name in ((1, "mz2_per_site"), (2, "n_per_site"), (3, "docc_per_site")):
+                m, se = _mean_and_stderr(vals[:, :, k] / N, w)
+                rec[name], rec[name + "_stderr"] = m, se
+            rec["chi"] = rec["beta_phys"] * rec["mz2_per_site"]
+            rec["F"], rec["F_stderr"] = _mean_and_stderr(f_loc / (2.0 * M), w)
         records.append(rec)
         if log is not None:
             log.write(json.dumps(rec) + "\n")

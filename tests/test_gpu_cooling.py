@@ -110,7 +110,10 @@ def test_cooling_4x4_matches_ed():
 def test_cooling_hubbard_2x2_matches_ed():
     """The same check for the Hubbard model (t = 1, U = 8, mu = 4) on 2x2:
     Jordan-Wigner signs, the Hubbard proposals and the d^2 = 16 SR path
-    through the whole loop, run by the package's cooling driver.  D = 8,
+    through the whole loop, run by the package's cooling driver, with the
+    double occupancy and the next-nearest-neighbour spin correlation F of the
+    same samples against their ED values (bar 3 sigma + 0.05 |ED| + 0.002).
+    D = 8,
     chi = 16 (exact contraction), theta = identity + N(0, 0.05^2), 64
     chains, 60 sweeps per step, alpha = 1, tau = 0.01, 25 steps; ED from
     the oracle's dense Hamiltonian (fermion operators with explicit
@@ -135,16 +138,40 @@ def test_cooling_hubbard_2x2_matches_ed():
                                                            U=8.0, mu=4.0)))
     theta = torch.tensor(synth.theta_identity(L1, L2, D, 4, noise=0.05, seed=101), device=dev)
     configs = torch.tensor(synth.configs_diagonal(n_chains, N, 4, seed=101), device=dev)
-    recs = p.cool(desc, theta, configs, steps + 1, sweeps, tau, eps, 4242, cg_iters=200)
+    recs = p.cool(desc, theta, configs, steps + 1, sweeps, tau, eps, 4242, cg_iters=200, observables=True)
+    # thermal expectations Tr(exp(-beta H) A) / Z in the eigenbasis of H:
+    # double occupancy (diagonal in the digit basis, site 0 most significant)
+    # and the next-nearest-neighbour S_i.S_j from fermion operators
+    lat0 = Lattice(L1, L2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    ev, V = np.linalg.eigh(hamiltonian.dense_H(lat0))
+    digits = np.array([[(x >> (2 * (N - 1 - i))) & 3 for i in range(N)] for x in range(4 ** N)])
+    docc_op = np.diag((digits == 3).sum(axis=1).astype(float) / N)
+    M = 2 * (L1 - 1) * (L2 - 1)
+    f_op = hamiltonian.dense_H(Lattice(L1, L2, D=1, chi=1, d=4, model=MODEL_HUBBARD, t=0.0, U=0.0, mu=0.0,
+                                       J2=1.0)) / M
+    diag_d = np.einsum("in,ij,jn->n", V, docc_op, V)
+    diag_f = np.einsum("in,ij,jn->n", V, f_op, V)
+
+    def thermal(dg, beta):
+        w = np.exp(-beta * (ev - ev.min()))
+        return float(w @ dg / w.sum())
+
     worst = 0.0
+    checks = []
     for r in recs:
-        e_ed = float(ed.thermal_energy(evals, r["beta_phys"])[0]) / N
-        bar = 3 * r["E_stderr"] + 0.02 * abs(e_ed)
-        worst = max(worst, abs(r["E_per_site"] - e_ed) / bar)
-        print(f"[cool] step {r['step']} beta {r['beta_phys']:.2f} E/N {r['E_per_site']:.5f} +- {r['E_stderr']:.5f} "
-              f"ED {e_ed:.5f}", flush=True)
+        b = r["beta_phys"]
+        e_ed = float(ed.thermal_energy(evals, b)[0]) / N
+        d_ed, f_ed = thermal(diag_d, b), thermal(diag_f, b)
+        rows = [(r["E_per_site"], e_ed, 3 * r["E_stderr"] + 0.02 * abs(e_ed)),
+                (r["docc_per_site"], d_ed, 3 * r["docc_per_site_stderr"] + 0.05 * abs(d_ed) + 0.002),
+                (r["F"], f_ed, 3 * r["F_stderr"] + 0.05 * abs(f_ed) + 0.002)]
+        worst = max([worst] + [abs(x - y) / bar for x, y, bar in rows])
+        checks.append((r["step"], b, rows))
+        print(f"[cool] step {r['step']} beta {b:.2f} E/N {r['E_per_site']:.5f} +- {r['E_stderr']:.5f} ED {e_ed:.5f}  "
+              f"docc {r['docc_per_site']:.5f} +- {r['docc_per_site_stderr']:.5f} ED {d_ed:.5f}  "
+              f"F {r['F']:.5f} +- {r['F_stderr']:.5f} ED {f_ed:.5f}", flush=True)
         sys.stdout.flush()
     print("[cool] worst deviation / bar", worst, flush=True)
-    for r in recs:
-        e_ed = float(ed.thermal_energy(evals, r["beta_phys"])[0]) / N
-        assert abs(r["E_per_site"] - e_ed) <= 3 * r["E_stderr"] + 0.02 * abs(e_ed), (r, e_ed)
+    for step, b, rows in checks:
+        for x, y, bar in rows:
+            assert abs(x - y) <= bar, (step, b, x, y, bar)
