@@ -21,5 +21,5 @@ ed           exact diagonalisation (sector by sector) and thermal energies
 sampler      Metropolis sweep over configurations S = (s, s')
 measure      per-sample log|psi|, sign, E_loc and log-derivative row O
 sr           sample reductions, SR matvec, conjugate gradient, dense solve
-driver       cooling loop from the beta = 0 identity state
+cooling      cooling loop from the beta = 0 identity state
 """

@@ -9,5 +9,5 @@ from .api import (Desc, PepsLogAmp, check, new_status, peps_eval_batch, peps_gra
                   peps_sample_sweep, peps_slot_count, peps_vjp_batch, peps_workspace_bytes, sr_cg_solve,
                   workspace_bytes, peps_observables_batch, thermal_observables, OBS_NAMES,
                   nnn_spin_correlation, specific_heat)
-from .driver import cool  # noqa: F401
+from .cooling import cool  # noqa: F401
 from ._lib import LIB_PATH, MODEL_HEISENBERG, MODEL_HUBBARD, PREC_FP64, PREC_MIXED, PepsError  # noqa: F401

@@ -110,7 +110,7 @@ def test_cooling_4x4_matches_ed():
 def test_cooling_hubbard_2x2_matches_ed():
     """The same check for the Hubbard model (t = 1, U = 8, mu = 4) on 2x2:
     Jordan-Wigner signs, the Hubbard proposals and the d^2 = 16 SR path
-    through the whole loop, run by the package's cooling driver, with the
+    through the whole loop, run by the package's cooling loop, with the
     double occupancy and the next-nearest-neighbour spin correlation F of the
     same samples against their ED values (bar 3 sigma + 0.05 |ED| + 0.002).
     D = 8,

@@ -1,4 +1,4 @@
-"""The cooling driver (paper_2409_05285_amd.cool): one JSON record per SR
+"""The cooling loop (paper_2409_05285_amd.cool): one JSON record per SR
 step with the documented fields; its steps equal the same library calls
 made directly, bit for bit; a run resumed from (theta, configs, gsweep,
 step) equals the uninterrupted run; the reweighted (alpha = 1) path runs."""
@@ -31,10 +31,10 @@ def _state(dev):
     return th, cfg
 
 
-def test_driver_records_and_direct_calls():
+def test_cooling_loop_records_and_direct_calls():
     dev = _dev()
     import paper_2409_05285_amd as p
-    print("[case] driver", flush=True)
+    print("[case] cooling loop", flush=True)
     sys.stdout.flush()
     desc = p.Desc(4, 4, 2, 4)
     seed, S, tau, eps = 99, 3, 0.02, 1e-4
@@ -66,10 +66,10 @@ def test_driver_records_and_direct_calls():
     assert r2[0]["E_per_site"] == recs[1]["E_per_site"] and r2[0]["beta_phys"] == recs[1]["beta_phys"]
 
 
-def test_driver_reweighted_sampling():
+def test_cooling_loop_reweighted_sampling():
     dev = _dev()
     import paper_2409_05285_amd as p
-    print("[case] driver alpha = 1", flush=True)
+    print("[case] cooling loop alpha = 1", flush=True)
     desc = p.Desc(4, 4, 2, 4, alpha=1)
     th, cfg = _state(dev)
     recs = p.cool(desc, th, cfg, 2, 2, 0.02, 1e-4, 5, cg_iters=40)

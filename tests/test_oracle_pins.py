@@ -782,17 +782,17 @@ def test_resume_from_saved_state_is_bit_exact(tmp_path):
     slot), so n SR steps, a save of (theta, configs, global sweep, step) to
     .npz and a reload, then n more steps give exactly the state of 2n
     uninterrupted steps."""
-    from oracle import driver
+    from oracle import cooling
     lat = Lattice(2, 3, D=2, chi=4)
     th0 = synth.theta_identity(2, 3, 2, 2, noise=1e-2, seed=3)
     cfg0 = synth.configs_diagonal(3, 6, 2, seed=4)
     kw = dict(chi=4, seed=77, sweeps_per_step=2, tau=0.02, eps=1e-4, max_iter=50)
-    th_a, cfg_a, hist_a = driver.cool(lat, th0, cfg0, n_steps=4, **kw)
-    th_1, cfg_1, hist_1 = driver.cool(lat, th0, cfg0, n_steps=2, **kw)
+    th_a, cfg_a, hist_a = cooling.cool(lat, th0, cfg0, n_steps=4, **kw)
+    th_1, cfg_1, hist_1 = cooling.cool(lat, th0, cfg0, n_steps=2, **kw)
     path = tmp_path / "state.npz"
     np.savez(path, theta=th_1, configs=cfg_1, gsweep=hist_1[-1]["gsweep"], step=len(hist_1))
     st = np.load(path)
-    th_b, cfg_b, hist_b = driver.cool(lat, st["theta"], st["configs"], n_steps=2, gsweep0=int(st["gsweep"]),
+    th_b, cfg_b, hist_b = cooling.cool(lat, st["theta"], st["configs"], n_steps=2, gsweep0=int(st["gsweep"]),
                                       step0=int(st["step"]), **kw)
     assert np.array_equal(th_a, th_b)
     assert np.array_equal(cfg_a, cfg_b)
