@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--D", type=int, default=4)
     ap.add_argument("--chi", type=int, default=16)
     ap.add_argument("--J2", type=float, default=0.0, help="next-nearest-neighbour coupling (J1 = 1)")
+    ap.add_argument("--graph", action="store_true",
+                    help="with --only: also time a one-sweep step eagerly and as a replayed HIP graph")
     ap.add_argument("--model", choices=["heisenberg", "hubbard"], default="heisenberg",
                     help="hubbard (with --only): t = 1, U = 8, mu = 4, d^2 = 16, random parity-even tensors")
     ap.add_argument("--chains", type=int, default=1024)
@@ -434,13 +436,18 @@ def main():
         del src, dst
 
     if args.only != "both":
-        r = run_path(p, torch, desc64 if args.only == "fp64" else descmx, theta0, configs0, args, seed)
-        print(json.dumps({"only": args.only, "model": args.model, "lattice": [L1, L2], "D": D, "chi": chi,
-                          "J2": args.J2, "chains": n,
-                          "sweeps_per_step": args.sweeps, "samples_per_s": round(r["samples_per_s"], 2),
-                          "ms_per_step": round(r["ms_per_step"], 3),
-                          "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
-                          "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}), flush=True)
+        desc = desc64 if args.only == "fp64" else descmx
+        r = run_path(p, torch, desc, theta0, configs0, args, seed)
+        line = {"only": args.only, "model": args.model, "lattice": [L1, L2], "D": D, "chi": chi,
+                "J2": args.J2, "chains": n,
+                "sweeps_per_step": args.sweeps, "samples_per_s": round(r["samples_per_s"], 2),
+                "ms_per_step": round(r["ms_per_step"], 3),
+                "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
+                "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}
+        if args.graph:
+            print("[bench] one-sweep step, eager and replayed graph", file=sys.stderr, flush=True)
+            line["graph_replay"] = graph_rate(p, torch, desc, theta0, configs0, args, seed)
+        print(json.dumps(line), flush=True)
         return
 
     def progress(msg):
