@@ -799,3 +799,75 @@ def test_resume_from_saved_state_is_bit_exact(tmp_path):
     assert [h["E_per_site"] for h in hist_a[2:]] == [h["E_per_site"] for h in hist_b]
     # and the run did move: the second half differs from the first
     assert not np.array_equal(th_1, th_a)
+
+
+# ---------------------------------------------------------------------------
+# Simple update (the high-temperature alternative to SR): a gate is applied
+# exactly whenever no singular value is dropped.
+
+def _su_product_state(lat, D, seed):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(lat.n_params)
+    for r in range(lat.L1):
+        for c in range(lat.L2):
+            T = lat.site_tensor(th, r, c)
+            T[:, 0, 0, 0, 0] = rng.standard_normal(lat.d2)
+    return th
+
+
+def _amplitudes(lat, th):
+    return np.array([network.amplitude(lat, th, S) for S in network.all_configs(lat)])
+
+
+def _parallel(a, b):
+    c = float(a @ b) / float(b @ b)
+    return np.linalg.norm(a - c * b) / np.linalg.norm(a)
+
+
+def test_simple_update_step_is_exact_without_truncation():
+    """From a product state on 2x2 with D = 16, every bond's rank after one
+    step stays <= 16 (the doubled gate has operator Schmidt rank <= 16), so
+    no value is dropped and the step equals the dense product of the four
+    bond gates, in the update order, applied to the product vector."""
+    from oracle import simple_update as su
+    lat = Lattice(2, 2, D=16, chi=16)
+    th = _su_product_state(lat, 16, 81)
+    lam = np.ones((su.n_bonds(lat), 16))
+    psi = _amplitudes(lat, th).reshape((4,) * lat.N)
+    tau = 0.3
+    G = su.gate(lat, tau, lat.J1).reshape(4, 4, 4, 4)
+    for (i, j, _, _, _) in su.bonds(lat):
+        psi = np.moveaxis(np.tensordot(G, psi, axes=([2, 3], [i, j])), [0, 1], [i, j])
+    su.su_step(lat, th, lam, tau)
+    got = _amplitudes(lat, su.absorb(lat, th, lam))
+    assert _parallel(got, psi.reshape(-1)) < 1e-12
+    # and the gates did something
+    assert _parallel(_amplitudes(lat, _su_product_state(lat, 16, 81)), psi.reshape(-1)) > 1e-3
+
+
+def test_simple_update_identity_gate_keeps_the_state():
+    """tau = 0: every gate is the identity and every two-site matrix has rank
+    <= D, so a step only changes the gauge: the absorbed PEPS has the same
+    amplitudes up to a factor, for a random D = 2 PEPS on 2 x 3."""
+    from oracle import simple_update as su
+    lat = Lattice(2, 3, D=2, chi=4)
+    th = synth.theta_random_unit(2, 3, 2, 2, seed=82)
+    before = _amplitudes(lat, th)
+    lam = np.ones((su.n_bonds(lat), 2))
+    su.su_step(lat, th, lam, 0.0)
+    assert _parallel(_amplitudes(lat, su.absorb(lat, th, lam)), before) < 1e-12
+    assert np.all(lam.max(axis=1) == 1.0)
+
+
+def test_simple_update_gate_closed_form():
+    """The doubled gate factorises into exp(-tau h) on the ket digits and
+    exp(-tau h) on the bra digits, and exp(-tau h) of S_i.S_j is e^{-tau/4}
+    on the triplet and e^{3 tau/4} on the singlet."""
+    from oracle import simple_update as su
+    lat = Lattice(2, 2, D=1, chi=1)
+    tau = 0.37
+    G = su.gate(lat, tau, 1.0)
+    ev = np.sort(np.linalg.eigvalsh(G))
+    t, s = np.exp(-tau / 4), np.exp(3 * tau / 4)
+    want = np.sort(np.outer([t, t, t, s], [t, t, t, s]).ravel())
+    np.testing.assert_allclose(ev, want, rtol=1e-13)
