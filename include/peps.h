@@ -64,7 +64,7 @@ typedef enum {
 
 enum { PEPS_MODEL_HEISENBERG = 0, PEPS_MODEL_HUBBARD = 1 };
 enum { PEPS_PREC_FP64 = 0, PEPS_PREC_MIXED = 1 };
-enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3 };
+enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3, PEPS_WS_SU = 4 };
 enum { PEPS_N_MOVE_TYPES = 3 }; /* horizontal exchange, site move, vertical exchange */
 enum { PEPS_N_OBS = 4 };        /* local values per sample of peps_observables_batch */
 
@@ -204,6 +204,33 @@ peps_status peps_vjp_batch(const peps_desc* desc, int64_t n, const uint8_t* conf
    number of such pairs. */
 peps_status peps_observables_batch(const peps_desc* desc, int64_t n, const uint8_t* configs, double* out,
                                    peps_stream_t stream);
+
+/* Simple-update imaginary-time evolution, the paper's alternative to SR at
+   the highest temperatures (the paragraph on the simple-update method after
+   Appendix A; the scheme of Jiang, Weng and Xiang): n_steps first-order
+   Trotter steps of tau, each applying exp(-tau calH_b) = exp(-tau J1 h) (x)
+   exp(-tau J1 h), h = S_i.S_j, to every nearest-neighbour bond in four groups
+   of disjoint bonds (horizontal bonds with c even, c odd; vertical bonds with
+   r even, r odd), with bond weights lambda standing in for the environment.
+   One step of tau evolves like one SR step of tau (beta_phys = 4 n tau).  Per
+   bond: the other legs of both sites are multiplied by their weights, the
+   two-site tensor gets the gate and an SVD, the D largest values are kept
+   (lambda_b = kept / largest), and the other legs are divided by their
+   weights again (a weight at or below 1e-12 of its bond's largest counts as
+   zero).  theta [N_p] and lambdas [n_bonds][D] f64 are updated in place;
+   n_bonds = L1 (L2-1) + (L1-1) L2, horizontal bonds row-major first, then
+   vertical bonds row-major; start from lambdas = 1.  Spin-1/2 Heisenberg
+   with J2 = 0 and D <= 8 only (else PEPS_ERR_UNSUPPORTED).  ws: at least
+   peps_workspace_bytes(desc, 0, PEPS_WS_SU).  Non-finite singular values
+   are reported in status. */
+peps_status peps_simple_update(const peps_desc* desc, double* theta, double* lambdas, double tau, int32_t n_steps,
+                               int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
+
+/* The plain PEPS of a simple-update state: theta_out = theta with
+   sqrt(lambda_b) multiplied into both ends of every bond (the input of
+   sampling and SR).  theta_out [N_p] may not alias theta. */
+peps_status peps_su_absorb(const peps_desc* desc, const double* theta, const double* lambdas, double* theta_out,
+                           peps_stream_t stream);
 
 /* ---- instrumentation (not part of the method) --------------------------- */
 

@@ -8,6 +8,6 @@ from .api import (Desc, PepsLogAmp, check, new_status, peps_eval_batch, peps_gra
                   peps_orow_count, peps_param_count, peps_profile_enable, peps_profile_read,
                   peps_sample_sweep, peps_slot_count, peps_vjp_batch, peps_workspace_bytes, sr_cg_solve,
                   workspace_bytes, peps_observables_batch, thermal_observables, OBS_NAMES,
-                  nnn_spin_correlation, specific_heat)
+                  nnn_spin_correlation, specific_heat, peps_simple_update, peps_su_absorb, su_bond_count)
 from .cooling import cool  # noqa: F401
 from ._lib import LIB_PATH, MODEL_HEISENBERG, MODEL_HUBBARD, PREC_FP64, PREC_MIXED, PepsError  # noqa: F401

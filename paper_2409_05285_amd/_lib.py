@@ -22,7 +22,7 @@ STATUS = {
 }
 MODEL_HEISENBERG, MODEL_HUBBARD = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR = 0, 1, 2, 3
+WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR, WS_SU = 0, 1, 2, 3, 4
 N_OBS = 4   # peps_observables_batch: M_z, M_z^2, particle number, double occupancy
 
 
@@ -74,6 +74,11 @@ def _load():
     lib.peps_vjp_batch.restype = c_int32
     lib.peps_observables_batch.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p]
     lib.peps_observables_batch.restype = c_int32
+    lib.peps_simple_update.argtypes = [P, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p, c_size_t,
+                                       c_void_p]
+    lib.peps_simple_update.restype = c_int32
+    lib.peps_su_absorb.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.peps_su_absorb.restype = c_int32
     lib.peps_profile_enable.argtypes = [c_int32]
     lib.peps_profile_enable.restype = None
     lib.peps_profile_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
@@ -84,5 +89,6 @@ def _load():
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
-           "peps_vjp_batch", "peps_observables_batch", "peps_profile_enable", "peps_profile_read"]
+           "peps_vjp_batch", "peps_observables_batch", "peps_simple_update", "peps_su_absorb",
+           "peps_profile_enable", "peps_profile_read"]
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

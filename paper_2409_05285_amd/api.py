@@ -321,6 +321,41 @@ def thermal_observables(desc: Desc, configs, beta_phys, weights=None):
             "docc_per_site": m[3] / N, "mz_per_site": m[0] / N}
 
 
+def su_bond_count(desc: Desc) -> int:
+    """Bonds of the lattice: L1 (L2-1) horizontal, then (L1-1) L2 vertical."""
+    return desc.L1 * (desc.L2 - 1) + (desc.L1 - 1) * desc.L2
+
+
+def peps_simple_update(desc: Desc, theta, lambdas, tau, n_steps, status=None, ws=None):
+    """n_steps simple-update steps of tau in place on theta (float64 [N_p])
+    and the bond weights lambdas (float64 [n_bonds, D], start from ones);
+    returns status."""
+    if not theta.is_contiguous():
+        raise ValueError("theta is updated in place and must be contiguous")
+    theta = _theta(desc, theta)
+    dev = theta.device
+    nb = su_bond_count(desc)
+    if lambdas.dtype != torch.float64 or tuple(lambdas.shape) != (nb, desc.D) or not lambdas.is_contiguous():
+        raise ValueError("lambdas must be contiguous float64 [n_bonds, D]")
+    _check_dev(theta, lambdas)
+    status = new_status(dev) if status is None else status
+    ws = _own_ws(ws, "su", peps_workspace_bytes(desc, 0, _lib.WS_SU), dev)
+    _raise(LIB.peps_simple_update(ctypes.byref(desc.c()), _ptr(theta), _ptr(lambdas), float(tau), int(n_steps),
+                                  _ptr(status), _ptr(ws), ws.numel(), _stream()), "peps_simple_update")
+    return status
+
+
+def peps_su_absorb(desc: Desc, theta, lambdas):
+    """The plain PEPS of a simple-update state: sqrt(lambda) on both ends of
+    every bond (a new tensor)."""
+    theta = _theta(desc, theta)
+    _check_dev(theta, lambdas)
+    out = torch.empty_like(theta)
+    _raise(LIB.peps_su_absorb(ctypes.byref(desc.c()), _ptr(theta), _ptr(lambdas.contiguous()), _ptr(out), _stream()),
+           "peps_su_absorb")
+    return out
+
+
 def nnn_spin_correlation(desc: Desc, theta, configs, weights=None):
     """F = sum_<<ij>> <S_i.S_j> / M over the M = 2 (L1-1)(L2-1)
     next-nearest-neighbour pairs (Benchmark section, Hubbard model; also

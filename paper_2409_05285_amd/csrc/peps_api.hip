@@ -186,6 +186,9 @@ peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, si
     case PEPS_WS_SWEEP:
       *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P);
       return PEPS_OK;
+    case PEPS_WS_SU:
+      *bytes = (size_t)su_max_group(P) * ((su_bond_doubles(P) + 31) & ~(size_t)31) * sizeof(double);
+      return PEPS_OK;
     case PEPS_WS_SR:
       *bytes = sr_workspace_bytes(P, n);
       return PEPS_OK;
@@ -360,6 +363,35 @@ peps_status peps_observables_batch(const peps_desc* d, int64_t n, const uint8_t*
   if (!configs || !out) return PEPS_ERR_ARG;
   Prob P = make_prob(d);
   HIP_TRY(launch_observables(P, n, configs, out, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
+static bool su_supported(const peps_desc* d) {
+  return d->model == PEPS_MODEL_HEISENBERG && d->J2 == 0.0 && d->D <= MAX_SU_D;
+}
+
+peps_status peps_simple_update(const peps_desc* d, double* theta, double* lambdas, double tau, int32_t n_steps,
+                               int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream) {
+  if (!desc_ok(d) || n_steps < 0 || !isfinite(tau)) return PEPS_ERR_ARG;
+  if (!su_supported(d)) return PEPS_ERR_UNSUPPORTED;
+  if (n_steps == 0) return PEPS_OK;
+  if (!theta || !lambdas || !ws) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  size_t need = 0;
+  peps_workspace_bytes(d, 0, PEPS_WS_SU, &need);
+  if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < n_steps; ++s) HIP_TRY(launch_su_step(P, theta, lambdas, tau, (double*)ws, status, st));
+  return PEPS_OK;
+}
+
+peps_status peps_su_absorb(const peps_desc* d, const double* theta, const double* lambdas, double* theta_out,
+                           peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  if (!su_supported(d)) return PEPS_ERR_UNSUPPORTED;
+  if (!theta || !lambdas || !theta_out) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  HIP_TRY(launch_su_absorb(P, theta, lambdas, theta_out, (hipStream_t)stream));
   return PEPS_OK;
 }
 

@@ -52,6 +52,15 @@ hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const 
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int32_t* status, hipStream_t st);
 
+// Simple update (spin-1/2 Heisenberg, J2 = 0, D <= MAX_SU_D): one Trotter
+// step of tau over the four bond groups; sqrt(lambda) absorbed into theta.
+constexpr int MAX_SU_D = 8;
+size_t su_bond_doubles(const Prob& P);
+int su_max_group(const Prob& P);
+hipError_t launch_su_step(const Prob& P, double* theta, double* lam, double tau, double* ws, int32_t* status,
+                          hipStream_t st);
+hipError_t launch_su_absorb(const Prob& P, const double* theta, const double* lam, double* out, hipStream_t st);
+
 size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
                      const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
