@@ -38,7 +38,7 @@ def _mean_and_stderr(values, w):
 
 
 def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, seed, cg_iters=200, rtol=1e-10,
-         step0=0, gsweep0=0, log=None, observables=False):
+         step0=0, gsweep0=0, log=None, observables=False, su_steps=0):
     """Run n_steps SR steps; theta (float64 [N_p], device) and configs (uint8
     [n_chains, N], device) are updated in place.  `log`: a text stream that
     receives one JSON line per step.  Returns the list of records:
@@ -52,7 +52,11 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
     and weights (Benchmark section), with standard errors: <M_z^2>/N and the
     susceptibility beta_phys <M_z^2>/N, the particle number and double
     occupancy per site (Hubbard), and the next-nearest-neighbour spin
-    correlation F (one more evaluation of the samples, before the update)."""
+    correlation F (one more evaluation of the samples, before the update).
+    su_steps > 0: first that many simple-update steps of tau from unit bond
+    weights (the high-temperature alternative to SR; spin-1/2 Heisenberg with
+    J2 = 0), the weights absorbed into theta, then n_steps SR steps numbered
+    from step0 + su_steps (so beta_phys keeps counting 4 tau per step)."""
     n = configs.shape[0]
     S = int(sweeps_per_step)
     N = desc.N
@@ -68,6 +72,13 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
     }
     n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
     gsweep = int(gsweep0)
+    if su_steps > 0:
+        lam = torch.ones((api.su_bond_count(desc), desc.D), dtype=torch.float64, device=dev)
+        api.peps_simple_update(desc, theta, lam, tau, su_steps, status=status)
+        theta.copy_(api.peps_su_absorb(desc, theta, lam))
+        torch.cuda.synchronize()
+        api.check(status, "simple update")
+        step0 = step0 + su_steps
     records = []
     for step in range(step0, step0 + n_steps):
         torch.cuda.synchronize()

@@ -175,3 +175,40 @@ def test_cooling_hubbard_2x2_matches_ed():
     for step, b, rows in checks:
         for x, y, bar in rows:
             assert abs(x - y) <= bar, (step, b, x, y, bar)
+
+
+def test_simple_update_then_sr_4x4_matches_ed():
+    """The paper's alternative at high temperature: simple-update steps from
+    beta = 0 (bond weights standing in for the environment), then SR.  Same
+    4x4 recipe as the first test, with the first 10 steps (beta_phys up to
+    0.4) done by the simple update and 16 SR steps after them, through the
+    cooling loop: E/N and <M_z^2>/N of the SR steps against ED (bars as
+    above)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2409_05285_amd as p
+    dev = torch.device("cuda:0")
+    L1 = L2 = 4
+    D, chi, n_chains, sweeps, tau, eps = 4, 16, 64, 60, 0.01, 1e-4
+    N = L1 * L2
+    desc = p.Desc(L1, L2, D, chi, alpha=1)
+    theta = torch.tensor(synth.theta_identity(L1, L2, D, 2, noise=0.05, seed=101), device=dev)
+    configs = torch.tensor(synth.configs_diagonal(n_chains, N, 2, seed=101), device=dev)
+    recs = p.cool(desc, theta, configs, 16, sweeps, tau, eps, 4242, cg_iters=200, observables=True, su_steps=10)
+    assert recs[0]["step"] == 10 and abs(recs[0]["beta_phys"] - 0.4) < 1e-12
+    worst = 0.0
+    for r in recs:
+        b = r["beta_phys"]
+        e_ed, m_ed = _ed_energy(b), _ed(b, "Mz2_per_site")
+        be = 3 * r["E_stderr"] + 0.02 * abs(e_ed)
+        bm = 3 * r["mz2_per_site_stderr"] + 0.05 * abs(m_ed)
+        worst = max(worst, abs(r["E_per_site"] - e_ed) / be, abs(r["mz2_per_site"] - m_ed) / bm)
+        print(f"[cool] step {r['step']} beta {b:.2f} E/N {r['E_per_site']:.5f} +- {r['E_stderr']:.5f} ED {e_ed:.5f}  "
+              f"<Mz^2>/N {r['mz2_per_site']:.5f} +- {r['mz2_per_site_stderr']:.5f} ED {m_ed:.5f}", flush=True)
+        sys.stdout.flush()
+    print("[cool] worst deviation / bar", worst, flush=True)
+    for r in recs:
+        b = r["beta_phys"]
+        assert abs(r["E_per_site"] - _ed_energy(b)) <= 3 * r["E_stderr"] + 0.02 * abs(_ed_energy(b)), r
+        m_ed = _ed(b, "Mz2_per_site")
+        assert abs(r["mz2_per_site"] - m_ed) <= 3 * r["mz2_per_site_stderr"] + 0.05 * abs(m_ed), r
