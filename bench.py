@@ -313,6 +313,29 @@ def graph_rate(p, torch, desc, theta0, configs0, args, seed):
             "sweeps_run": int(ctr.item())}
 
 
+def simple_update_rate(p, torch, desc, steps=20, tau=0.01):
+    """Device time of one simple-update step (every bond of the lattice once)
+    from the identity plus noise, averaged over `steps` steps after two
+    untimed ones; None where the model has no simple update."""
+    import synth
+    if desc.model != p.MODEL_HEISENBERG or desc.J2 != 0.0 or desc.D > 8:
+        return None
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(synth.theta_identity(desc.L1, desc.L2, desc.D, 2, noise=1e-2, seed=96), device=dev)
+    lam = torch.ones((p.su_bond_count(desc), desc.D), dtype=torch.float64, device=dev)
+    p.peps_simple_update(desc, theta, lam, tau, 2)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    st = p.peps_simple_update(desc, theta, lam, tau, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    p.check(st, "simple update")
+    return {"ms_per_step": round(ev0.elapsed_time(ev1) / steps, 3), "bonds": p.su_bond_count(desc), "steps": steps,
+            "note": "one first-order Trotter step over every nearest-neighbour bond (FP64), for the highest "
+                    "temperatures before SR"}
+
+
 def energy_error(p, torch, desc64, descmx, theta, configs):
     """Local energies of the same samples and parameters from both
     precisions: relative error of the mean energy, the same error in units
@@ -468,6 +491,7 @@ def main():
     graph64 = graph_rate(p, torch, desc64, theta0, configs0, args, seed)
     graphmx = graph_rate(p, torch, descmx, theta0, configs0, args, seed)
     progress("graph replays done")
+    su = simple_update_rate(p, torch, desc64)
     eval64 = eval_rate(p, torch, desc64, r64["theta"], r64["configs"])
     evalmx = eval_rate(p, torch, descmx, r64["theta"], r64["configs"])
     best = rmx if mixed_ok else r64
@@ -544,6 +568,7 @@ def main():
                          "note": "one-sweep step (1024 samples, SR on them) eager vs captured once as a HIP "
                                  "graph and replayed"},
         "host_wall_ms_per_step": round(best["wall"] * 1e3 / args.steps, 3),
+        "simple_update": su,
     }
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
