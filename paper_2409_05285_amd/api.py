@@ -349,6 +349,8 @@ def peps_su_absorb(desc: Desc, theta, lambdas):
     """The plain PEPS of a simple-update state: sqrt(lambda) on both ends of
     every bond (a new tensor)."""
     theta = _theta(desc, theta)
+    if lambdas.dtype != torch.float64 or tuple(lambdas.shape) != (su_bond_count(desc), desc.D):
+        raise ValueError("lambdas must be float64 [n_bonds, D]")
     _check_dev(theta, lambdas)
     out = torch.empty_like(theta)
     _raise(LIB.peps_su_absorb(ctypes.byref(desc.c()), _ptr(theta), _ptr(lambdas.contiguous()), _ptr(out), _stream()),

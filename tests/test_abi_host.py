@@ -76,3 +76,26 @@ def test_workspace_and_errors():
     # workspace too small
     assert LIB.peps_eval_batch(ctypes.byref(ok), ctypes.c_void_p(8), 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                ctypes.c_void_p(8), None, None, ctypes.c_void_p(8), 16, None) == -4
+
+
+def test_simple_update_entry_points_refuse_unsupported_cases():
+    """The simple update covers the spin-1/2 Heisenberg model with J2 = 0 and
+    D <= 8: other descriptors are refused before any pointer is touched; its
+    workspace query scales with the largest bond group."""
+    import paper_2409_05285_amd as p
+    from paper_2409_05285_amd._lib import LIB
+    ok = p.Desc(4, 4, 2, 4)
+    assert p.peps_workspace_bytes(ok, 0, 4) > 0
+    assert p.peps_workspace_bytes(p.Desc(8, 8, 2, 4), 0, 4) > p.peps_workspace_bytes(ok, 0, 4)
+    for bad, code in ((p.Desc(4, 4, 2, 4, d=4, model=1), -2), (p.Desc(4, 4, 2, 4, J2=0.5), -2),
+                      (p.Desc(4, 4, 9, 9), -2)):
+        c = bad.c()
+        assert LIB.peps_simple_update(ctypes.byref(c), None, None, 0.01, 1, None, None, 0, None) == code
+        assert LIB.peps_su_absorb(ctypes.byref(c), None, None, None, None) == code
+    c = ok.c()
+    # zero steps is a no-op; missing buffers and a short workspace are argument errors
+    assert LIB.peps_simple_update(ctypes.byref(c), None, None, 0.01, 0, None, None, 0, None) == 0
+    assert LIB.peps_simple_update(ctypes.byref(c), None, None, 0.01, 1, None, None, 0, None) == -1
+    assert LIB.peps_simple_update(ctypes.byref(c), ctypes.c_void_p(8), ctypes.c_void_p(8), 0.01, 1, None,
+                                  ctypes.c_void_p(8), 16, None) == -4
+    assert LIB.peps_simple_update(ctypes.byref(c), None, None, float("nan"), 1, None, None, 0, None) == -1
