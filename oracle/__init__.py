@@ -22,4 +22,6 @@ sampler      Metropolis sweep over configurations S = (s, s')
 measure      per-sample log|psi|, sign, E_loc and log-derivative row O
 sr           sample reductions, SR matvec, conjugate gradient, dense solve
 cooling      cooling loop from the beta = 0 identity state
+observables  local values of diagonal thermal observables, estimators
+simple_update  simple-update Trotter evolution with bond weights
 """
