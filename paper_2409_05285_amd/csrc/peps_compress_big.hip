@@ -10,8 +10,10 @@
 //     wave as A - V T^T (V^T A), each column loaded into registers once per
 //     panel;
 //   * R B_{c+1} as FP64 MFMA tiles;
-//   * the truncation by block one-sided Jacobi (Hestenes): pairs of column
-//     blocks swept in LDS, no rotation accumulation for wide matrices;
+//   * the truncation by block one-sided Jacobi (Hestenes): per outer sweep
+//     the pairs inside every column block, then the pairs between the two
+//     blocks of every block pair, each pass in LDS (every column pair once
+//     per outer sweep), no rotation accumulation for wide matrices;
 //   * Q_{c-1} (U S) applied panel by panel from the stored reflectors and T.
 #include <math.h>
 

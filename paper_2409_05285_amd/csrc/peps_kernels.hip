@@ -1,5 +1,6 @@
 // LDS-resident boundary-row compression (the general-shape fallback, one
-// workgroup per chain, FP64) and the per-sample output kernel.
+// workgroup per chain, FP64), the per-sample output kernel and the local
+// values of the diagonal observables.
 #include <math.h>
 
 #include "peps_chain.hpp"
