@@ -1,5 +1,5 @@
 // C ABI of the library: descriptor validation, workspace layout, and the
-// launch sequences of the four device calls (declared in include/peps.h).
+// launch sequences of the device calls (declared in include/peps.h).
 #include <math.h>
 #include <string.h>
 

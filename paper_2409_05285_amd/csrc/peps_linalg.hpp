@@ -1,4 +1,5 @@
-// Workgroup-level dense factorisations in FP64, operating on LDS.
+// Workgroup-level dense factorisations in FP64, on matrices in LDS or in a
+// workspace in device memory.
 //
 //  * Householder QR (Golub & Van Loan, Alg. 5.2.1, LAPACK dgeqr2/dorg2r
 //    conventions): reflector H = I - tau v v^T with v_0 = 1, R's diagonal
