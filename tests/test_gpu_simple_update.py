@@ -30,7 +30,7 @@ def _dev():
 
 
 @pytest.mark.parametrize("L1,L2,D,start", [(4, 4, 2, "random"), (3, 4, 3, "random"), (4, 4, 4, "random"),
-                                           (4, 4, 4, "identity")])
+                                           (4, 4, 4, "identity"), (3, 3, 6, "random"), (3, 3, 8, "random")])
 def test_simple_update_matches_oracle(L1, L2, D, start):
     dev = _dev()
     import paper_2409_05285_amd as p
