@@ -19,7 +19,8 @@
 //      values kept (NaN-safe ranking), lambda_b = kept / largest;
 //   5. T_i = Q_i U, T_j = Q_j V, the other legs divided by their weights
 //      again (a weight at or below 1e-12 of its bond's largest counts as 0).
-// Work matrices live in the workspace (one slice per workgroup).
+// Work matrices live in the workspace (one slice per workgroup); for D <= 4
+// the Jacobi rotations run on copies in LDS.
 #include <math.h>
 
 #include "peps_common.hpp"
@@ -32,6 +33,7 @@ namespace {
 
 constexpr int SU_NT = 256;
 constexpr double SU_LAMBDA_CUT = 1.0e-12;
+constexpr int SU_LDS_NT = 64;    // two-site matrices up to 64 x 64 (D <= 4) are rotated in LDS
 
 struct SuBond {
   int i, j, li, lj, k;   // sites, legs (0 l, 1 u, 2 r, 3 d) and bond index
@@ -165,12 +167,25 @@ __device__ void su_gather(const Prob& P, const SuSite& s, const double* theta, c
 
 // G = X V (in place), V = I on entry: then sigma, Q = G / sigma (in place),
 // and R (n x n, row-major) = diag(sigma) V^T.
+// With `lds` (room for m n + n n doubles) the rotations run on copies there.
 __device__ void su_factor(const Prob& P, const SuSite& s, double* X, double* V, double* R, double* sig,
-                          int* flags, int32_t* status) {
+                          int* flags, int32_t* status, double* lds) {
   const int n = P.d2 * P.D;
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   __syncthreads();
-  wg_jacobi(X, s.m, n, s.m, V, n, flags);
+  if (lds) {
+    double* Xl = lds;
+    double* Vl = lds + (size_t)s.m * n;
+    for (int idx = threadIdx.x; idx < s.m * n; idx += blockDim.x) Xl[idx] = X[idx];
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) Vl[idx] = V[idx];
+    __syncthreads();
+    wg_jacobi(Xl, s.m, n, s.m, Vl, n, flags);
+    for (int idx = threadIdx.x; idx < s.m * n; idx += blockDim.x) X[idx] = Xl[idx];
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) V[idx] = Vl[idx];
+    __syncthreads();
+  } else {
+    wg_jacobi(X, s.m, n, s.m, V, n, flags);
+  }
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     double q = 0.0;
     for (int o = 0; o < s.m; ++o) q += X[(size_t)c * s.m + o] * X[(size_t)c * s.m + o];
@@ -234,8 +249,10 @@ __global__ void __launch_bounds__(SU_NT) k_su_bond(Prob P, int group, double* th
   su_gather(P, si, theta, lam, Xi);
   su_gather(P, sj, theta, lam, Xj);
   __syncthreads();
-  su_factor(P, si, Xi, Vi, Ri, sig_i, flags, status);
-  su_factor(P, sj, Xj, Vj, Rj, sig_j, flags, status);
+  extern __shared__ double su_lds[];
+  const bool small = nt <= SU_LDS_NT;   // dynamic LDS of 2 nt^2 doubles, >= m n + n n for D <= 4
+  su_factor(P, si, Xi, Vi, Ri, sig_i, flags, status, small ? su_lds : nullptr);
+  su_factor(P, sj, Xj, Vj, Rj, sig_j, flags, status, small ? su_lds : nullptr);
   // Theta (nt x nt, column-major): row (c_i, S_i'), column (S_j', c_j)
   const double* lb = lam + (size_t)bd.k * P.D;
   for (int idx = threadIdx.x; idx < nt * nt; idx += blockDim.x) {
@@ -254,7 +271,24 @@ __global__ void __launch_bounds__(SU_NT) k_su_bond(Prob P, int group, double* th
   }
   for (int idx = threadIdx.x; idx < nt * nt; idx += blockDim.x) Vt[idx] = (idx / nt == idx % nt) ? 1.0 : 0.0;
   __syncthreads();
-  wg_jacobi(Th, nt, nt, nt, Vt, nt, flags);
+  if (small) {
+    // small two-site matrices: the rotations run on copies in LDS
+    double* Tl = su_lds;
+    double* Vl = su_lds + nt * nt;
+    for (int idx = threadIdx.x; idx < nt * nt; idx += blockDim.x) {
+      Tl[idx] = Th[idx];
+      Vl[idx] = Vt[idx];
+    }
+    __syncthreads();
+    wg_jacobi(Tl, nt, nt, nt, Vl, nt, flags);
+    for (int idx = threadIdx.x; idx < nt * nt; idx += blockDim.x) {
+      Th[idx] = Tl[idx];
+      Vt[idx] = Vl[idx];
+    }
+    __syncthreads();
+  } else {
+    wg_jacobi(Th, nt, nt, nt, Vt, nt, flags);
+  }
   for (int q = threadIdx.x; q < nt; q += blockDim.x) {
     double ssq = 0.0;
     for (int r = 0; r < nt; ++r) ssq += Th[(size_t)q * nt + r] * Th[(size_t)q * nt + r];
@@ -331,7 +365,9 @@ hipError_t launch_su_step(const Prob& P, double* theta, double* lam, double tau,
   for (int g = 0; g < 4; ++g) {
     const int nb = su_group_size(P, g);
     if (nb == 0) continue;
-    hipLaunchKernelGGL(k_su_bond, dim3(nb), dim3(SU_NT), 0, st, P, g, theta, lam, et, es, ws, stride, status);
+    const int nt = 4 * P.d2 * P.D;
+    const size_t lds = nt <= SU_LDS_NT ? 2 * (size_t)nt * nt * sizeof(double) : 0;
+    hipLaunchKernelGGL(k_su_bond, dim3(nb), dim3(SU_NT), lds, st, P, g, theta, lam, et, es, ws, stride, status);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
