@@ -1,7 +1,8 @@
 """Edge cases of the device path against the oracle: the smallest lattice,
 bond dimension 1 (product states), boundary dimension 1 (every cut truncated
 to one value), the widest row (L2 = 32) and the largest site count
-(L1 L2 = 256); and empty batches for every entry point (no-ops).
+(L1 L2 = 256); empty batches for every entry point (no-ops); and the exact
+beta = 0 state, whose truncations are fully degenerate, against closed forms.
 Bars as in the other FP64 parity tests."""
 import sys
 
@@ -89,3 +90,53 @@ def test_empty_batches_are_noops():
     p.peps_sample_sweep(desc, theta, cfg, 1, 0, 0, measure=False)
     torch.cuda.synchronize()
     assert torch.equal(cfg, before)
+
+
+def _closed_form_identity(L1, L2, D, J1, J2, cfg):
+    """beta = 0 state |I> (every site's slice (s, s) is 1 at bond index 0):
+    for a diagonal configuration rho = 1, and every off-diagonal term of
+    H (x) I + I (x) H^T leads to a configuration with s != s', where rho = 0,
+    so E_loc = 2 H_ss = 2 sum_<ij> J Sz_i Sz_j over nearest and next-nearest
+    neighbours; the derivative of rho by the slice entry with every leg at 0
+    is 1 and by every other entry 0 (method section, Eqs. 4, 8 and 9)."""
+    sz = 0.5 - (cfg // 2).astype(np.float64)          # digit 0 = spin up
+    sz = sz.reshape(cfg.shape[0], L1, L2)
+    h = J1 * ((sz[:, :, :-1] * sz[:, :, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, :] * sz[:, 1:, :]).sum(axis=(1, 2)))
+    h += J2 * ((sz[:, :-1, :-1] * sz[:, 1:, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, 1:] * sz[:, 1:, :-1]).sum(axis=(1, 2)))
+    row = []
+    for r in range(L1):
+        for c in range(L2):
+            n = (1 if c == 0 else D) * (1 if r == 0 else D) * (1 if c == L2 - 1 else D) * (1 if r == L1 - 1 else D)
+            blk = np.zeros(n)
+            blk[0] = 1.0
+            row.append(blk)
+    return 2.0 * h, np.concatenate(row)
+
+
+@pytest.mark.parametrize("L1,L2,D,chi,J2,mixed", [(8, 8, 4, 16, 0.0, False), (8, 8, 4, 16, 0.0, True),
+                                                  (4, 4, 6, 36, 0.5, False), (4, 4, 6, 36, 0.5, True)])
+def test_beta0_identity_closed_forms(L1, L2, D, chi, J2, mixed):
+    """The exact beta = 0 state, where every truncated cut has one nonzero
+    singular value and the rest are exactly zero (the fully degenerate case
+    of the truncation), against its closed forms: log|psi| = 0, sign +1,
+    E_loc = 2 H_ss and the O rows, on the register-resident (chi D = 64) and
+    the workspace (chi D = 216) compression paths."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    print("[case] beta0 identity", L1, L2, D, chi, J2, mixed, flush=True)
+    sys.stdout.flush()
+    desc = p.Desc(L1, L2, D, chi, J2=J2, precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = torch.tensor(synth.theta_identity(L1, L2, D, 2), device=dev)
+    cfg = synth.configs_diagonal(32, L1 * L2, 2, seed=57)
+    cfg_d = torch.tensor(cfg, device=dev)
+    la, sg, el, st = p.peps_eval_batch(desc, th, cfg_d)
+    O, la2, st2 = p.peps_grad_batch(desc, th, cfg_d)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    e_ref, o_ref = _closed_form_identity(L1, L2, D, 1.0, J2, cfg)
+    la, sg, el, la2, O = la.cpu().numpy(), sg.cpu().numpy(), el.cpu().numpy(), la2.cpu().numpy(), O.cpu().numpy()
+    tol = 1e-4 if mixed else 1e-10
+    assert np.all(np.abs(la) <= tol) and np.all(np.abs(la2) <= tol), (np.abs(la).max(), np.abs(la2).max())
+    assert np.all(sg == 1)
+    assert np.all(np.abs(el - e_ref) <= tol * np.maximum(1.0, np.abs(e_ref))), np.abs(el - e_ref).max()
+    assert np.all(np.abs(O - o_ref[None, :]) <= (1e-4 if mixed else 1e-9)), np.abs(O - o_ref[None, :]).max()
