@@ -176,25 +176,30 @@ def test_reweighted_sweep_bit_exact(L1, L2, D, chi):
         assert np.array_equal(acc[ch], a), ch
 
 
-def test_identity_sweep_flips_every_site():
+@pytest.mark.parametrize("L1,L2,D,chi,mixed", [(4, 4, 2, 4, False), (8, 8, 4, 16, False), (8, 8, 4, 16, True),
+                                               (4, 4, 6, 36, False)])
+def test_identity_sweep_flips_every_site(L1, L2, D, chi, mixed):
+    """At the exact beta = 0 state every site move (s, s) -> (1-s, 1-s) has
+    ratio 1 and is accepted, and every bond move leads to s != s' (rho = 0)
+    and is rejected: one sweep flips every site once."""
     dev = _dev()
     import paper_2409_05285_amd as p
-    lat = Lattice(4, 4, D=2, chi=4)
-    desc = p.Desc(4, 4, 2, 4)
-    th = synth.theta_identity(4, 4, 2, 2)
-    cfg = synth.configs_diagonal(8, 16, 2, seed=9)
-    _say("identity sweep")
+    N = L1 * L2
+    desc = p.Desc(L1, L2, D, chi, precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = synth.theta_identity(L1, L2, D, 2)
+    cfg = synth.configs_diagonal(8, N, 2, seed=9)
+    _say(f"identity sweep {L1}x{L2} D={D} chi={chi} mixed={mixed}")
     cfg_d = torch.tensor(cfg, device=dev)
     res = p.peps_sample_sweep(desc, torch.tensor(th, device=dev), cfg_d, 1, 0, 1)
     torch.cuda.synchronize()
     assert p.check(res["status"]) == 0
     acc = res["n_accept"].cpu().numpy()
-    assert np.all(acc[:, 0] == 0) and np.all(acc[:, 2] == 0) and np.all(acc[:, 1] == 16)
+    assert np.all(acc[:, 0] == 0) and np.all(acc[:, 2] == 0) and np.all(acc[:, 1] == N)
     s = cfg // 2
     flipped = (1 - s) * 2 + (1 - s)
     assert np.array_equal(cfg_d.cpu().numpy(), flipped.astype(np.uint8))
-    # beta = 0: E_loc(s,s) = 2 H_ss (diagonal only) and log|psi| = 0
-    assert np.allclose(res["log_abs"].cpu().numpy(), 0.0, atol=1e-12)
+    # beta = 0: log|psi| = 0
+    assert np.allclose(res["log_abs"].cpu().numpy(), 0.0, atol=1e-4 if mixed else 1e-12)
 
 
 def test_weighted_sr_cg_matches_oracle():
