@@ -113,6 +113,46 @@ def _closed_form_identity(L1, L2, D, J1, J2, cfg):
     return 2.0 * h, np.concatenate(row)
 
 
+def _closed_form_identity_hubbard(L1, L2, D, U, mu, J2, cfg):
+    """The same for the Hubbard model (digit s = n_up + 2 n_dn): the
+    diagonal of H is U n_up n_dn - mu (n_up + n_dn) per site plus
+    J2 Sz_i Sz_j, Sz = (n_up - n_dn) / 2, on next-nearest neighbours."""
+    s = (cfg // 4).reshape(cfg.shape[0], L1, L2)
+    nu, nd = (s & 1).astype(np.float64), ((s >> 1) & 1).astype(np.float64)
+    sz = 0.5 * (nu - nd)
+    h = (U * nu * nd - mu * (nu + nd)).sum(axis=(1, 2))
+    h += J2 * ((sz[:, :-1, :-1] * sz[:, 1:, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, 1:] * sz[:, 1:, :-1]).sum(axis=(1, 2)))
+    _, o = _closed_form_identity(L1, L2, D, 0.0, 0.0, cfg)
+    return 2.0 * h, o
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_beta0_identity_closed_forms_hubbard(mixed):
+    """The exact beta = 0 state of the Hubbard model (d^2 = 16, 6 x 6, D = 4,
+    chi = 16, U = 8, mu = 4, J2 = 0.6) against its closed forms."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    print("[case] beta0 identity hubbard", mixed, flush=True)
+    sys.stdout.flush()
+    L1 = L2 = 6
+    desc = p.Desc(L1, L2, 4, 16, d=4, model=p.MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0, J2=0.6,
+                  precision=p.PREC_MIXED if mixed else p.PREC_FP64)
+    th = torch.tensor(synth.theta_identity(L1, L2, 4, 4), device=dev)
+    cfg = synth.configs_diagonal(32, L1 * L2, 4, seed=58)
+    cfg_d = torch.tensor(cfg, device=dev)
+    la, sg, el, st = p.peps_eval_batch(desc, th, cfg_d)
+    O, la2, st2 = p.peps_grad_batch(desc, th, cfg_d)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    e_ref, o_ref = _closed_form_identity_hubbard(L1, L2, 4, 8.0, 4.0, 0.6, cfg)
+    la, sg, el, la2, O = la.cpu().numpy(), sg.cpu().numpy(), el.cpu().numpy(), la2.cpu().numpy(), O.cpu().numpy()
+    tol = 1e-4 if mixed else 1e-10
+    assert np.all(np.abs(la) <= tol) and np.all(np.abs(la2) <= tol)
+    assert np.all(sg == 1)
+    assert np.all(np.abs(el - e_ref) <= tol * np.maximum(1.0, np.abs(e_ref))), np.abs(el - e_ref).max()
+    assert np.all(np.abs(O - o_ref[None, :]) <= (1e-4 if mixed else 1e-9)), np.abs(O - o_ref[None, :]).max()
+
+
 @pytest.mark.parametrize("L1,L2,D,chi,J2,mixed", [(8, 8, 4, 16, 0.0, False), (8, 8, 4, 16, 0.0, True),
                                                   (4, 4, 6, 36, 0.5, False), (4, 4, 6, 36, 0.5, True)])
 def test_beta0_identity_closed_forms(L1, L2, D, chi, J2, mixed):
