@@ -180,3 +180,64 @@ def test_beta0_identity_closed_forms(L1, L2, D, chi, J2, mixed):
     assert np.all(sg == 1)
     assert np.all(np.abs(el - e_ref) <= tol * np.maximum(1.0, np.abs(e_ref))), np.abs(el - e_ref).max()
     assert np.all(np.abs(O - o_ref[None, :]) <= (1e-4 if mixed else 1e-9)), np.abs(O - o_ref[None, :]).max()
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_beta0_sr_step_closed_form(weighted):
+    """SR at the exact beta = 0 state from closed-form inputs (8 x 8, D = 4,
+    512 diagonal samples): a sample's O row is 1 on the zero-leg entry of
+    its own slice (s_j, s_j) at every site j, so only the 2 N indicator
+    parameters are active.  There g_k = sum_i p_i [S_j(i) = S] (E_i - Ebar)
+    (the sample covariance of a spin with the energy: zero in expectation,
+    as the exact gradient at the identity is, but not for a finite sample),
+    the metric is the covariance of the indicators, and
+    (S + eps 1) dtheta = -tau g (Eqs. 5-7) is solved densely on the host;
+    every other entry of g and dtheta is zero.  With weights, all |rho| = 1
+    as the alpha = 1 reweighting gives there."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    print("[case] beta0 SR closed form, weighted", weighted, flush=True)
+    sys.stdout.flush()
+    L1 = L2 = 8
+    D, N, tau, eps = 4, 64, 0.02, 1e-4
+    desc = p.Desc(L1, L2, D, 16, alpha=1 if weighted else 2)
+    cfg = synth.configs_diagonal(512, N, 2, seed=59)
+    n = cfg.shape[0]
+    e_ref, o_ref = _closed_form_identity(L1, L2, D, 1.0, 0.0, cfg)
+    O = torch.tensor(np.ascontiguousarray(np.tile(o_ref, (n, 1))), device=dev)
+    E = torch.tensor(e_ref, device=dev)
+    w = torch.ones(n, dtype=torch.float64, device=dev) if weighted else None
+    dth, g, stats, st = p.sr_cg_solve(desc, torch.tensor(cfg, device=dev), O, E, tau, eps, 400, 1e-12, weights=w)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    g, dth, stats = g.cpu().numpy(), dth.cpu().numpy(), stats.cpu().numpy()
+    # parameter index of the zero-leg entry of slice S at site j: site-major
+    # blocks of d^2 slices, each slice the product of the site's leg dims
+    off, bsz = [], []
+    po = 0
+    for r in range(L1):
+        for c in range(L2):
+            b = (1 if c == 0 else D) * (1 if r == 0 else D) * (1 if c == L2 - 1 else D) * (1 if r == L1 - 1 else D)
+            off.append(po)
+            bsz.append(b)
+            po += 4 * b
+    assert po == g.size
+    X = np.zeros((n, 2 * N))                     # indicator of (s_j = 0) and (s_j = 1)
+    idx = np.zeros(2 * N, dtype=np.int64)
+    for j in range(N):
+        for s_ in range(2):
+            X[:, 2 * j + s_] = (cfg[:, j] // 2 == s_)
+            idx[2 * j + s_] = off[j] + (3 * s_) * bsz[j]
+    pw = np.full(n, 1.0 / n)
+    ebar = pw @ e_ref
+    g_act = X.T @ (pw * (e_ref - ebar))
+    xbar = pw @ X
+    S = (X * pw[:, None]).T @ X - np.outer(xbar, xbar)
+    d_act = np.linalg.solve(S + eps * np.eye(2 * N), -tau * g_act)
+    g_ref = np.zeros(g.size)
+    g_ref[idx] = g_act
+    d_ref = np.zeros(g.size)
+    d_ref[idx] = d_act
+    assert abs(stats[0] - ebar) <= 1e-12 * max(1.0, abs(ebar))
+    assert np.abs(g - g_ref).max() <= 1e-12 * max(1.0, np.abs(g_ref).max()), np.abs(g - g_ref).max()
+    assert np.abs(dth - d_ref).max() <= 1e-8 * np.abs(d_ref).max(), (np.abs(dth - d_ref).max(), np.abs(d_ref).max())
