@@ -10,20 +10,21 @@ row), then the stochastic-reconfiguration solve by conjugate gradient on all
 whole steps (one sample = one chain's sweep + measurement; the SR solve is
 inside the timed region).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweeps 200] [--cg-iters 200]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s T]
 
-Both precisions run the same K steps from the same state: FP64 throughout,
-and mixed (FP32 MFMA strip contractions with FP64 QR/SVD, reductions and
-SR).  The energy error is |E_mixed - E_fp64| / |E_fp64| of the mean local
-energy over the same samples and parameters, taken on a cooled state (the
-beta = 0 identity plus noise after --cool-steps FP64 SR steps) and reported
-also on the random-tensor state of the timed run.  `value` is the mixed
-path's rate when the cooled-state error is within --tol, else the FP64
+Warm-up: W one-sweep steps of each precision (sweep, measurement, SR on
+those 1024 samples, update).  Timed: up to K full steps of the mixed path
+(FP32 MFMA strip contractions, FP64 QR/SVD, reductions and SR), stopping
+after the step that ends past the wall budget T; `steps` reports how many
+were timed.  The plain FP64 path runs at most --fp64-steps full steps from
+the same state for the comparison.  Energy error (the precision gate of
+`value`): local energies of the same samples and parameters from both
+precisions, on the random state after the timed steps and on a cooled state
+(identity plus N(0, 0.05^2) noise, cooled through the package's cooling loop
+with |rho| sampling up to beta_phys = 0.3 and |rho|^2 after it, to
+beta_phys = 4): the mean, the 99th percentile and the largest per-sample
+relative error must all lie within --tol on both, else `value` is the FP64
 rate.
-
-A one-sweep step is also run eagerly and captured once as a HIP graph
-(device sweep counter, caller-owned workspaces) and replayed;
-`graph_replay` reports both rates.
 
 Prints one JSON line.  The CPU baseline is the FP64 oracle (tests only,
 never the product path) timed on a bounded sample on this host.
@@ -42,6 +43,10 @@ sys.path.insert(0, ROOT)
 MI355X_HBM_GBS = 8000.0
 MI355X_FP64_TFLOPS = 78.6
 MI355X_FP32_MFMA_TFLOPS = 157.3
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -127,6 +132,14 @@ def sweep_compression_flops(L1, L2, D, chi):
     return total, n
 
 
+def model_row_flops(L2, D, chi):
+    """Work of one boundary-row compression in the per-sample model of the
+    measurement plan: L2 [2 chi^2 D^4 (absorption) + 4 chi^3 D^4 (QR) +
+    16 chi^3 D^3 (SVD and product)] flops per chain and row, every site
+    counted at full bond dimensions."""
+    return L2 * (2 * chi ** 2 * D ** 4 + 4 * chi ** 3 * D ** 4 + 16 * chi ** 3 * D ** 3)
+
+
 # ---------------------------------------------------------------------------
 def _oracle_worker(args):
     L1, L2, D, chi, seed_theta, ch, seed = args
@@ -151,7 +164,7 @@ def cpu_baseline(L1, L2, D, chi, seed_theta, seed, cg_iters, target_core_s=20.0)
 
     import numpy as np
     cores = len(os.sched_getaffinity(0))
-    workers = max(1, min(cores, 16))
+    workers = max(1, min(cores, 16))   # the box grants one GPU's share of 16 host cores
     # one probe sample sizes the bounded run
     t_probe, _, _, _ = _oracle_worker((L1, L2, D, chi, seed_theta, 0, seed))
     n_samples = int(max(workers, min(8 * workers, round(target_core_s / max(t_probe, 1e-3)))))
@@ -172,10 +185,22 @@ def cpu_baseline(L1, L2, D, chi, seed_theta, seed, cg_iters, target_core_s=20.0)
         t1 = time.perf_counter()
         sr.sr_solve(lat, cfg, O, e, 0.02, 1e-4, cg_iters, 0.0)
         t_cg = time.perf_counter() - t1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n_samples / (wall + t_cg), "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "cores_visible": cores, "cpu_model": cpu_model,
             "sample": f"{n_samples} chains x 1 sweep + measurement of the same workload on {workers} processes "
                       f"({wall:.1f} s wall), then oracle CG with {cg_iters} iterations on those samples "
                       f"({t_cg:.1f} s); NumPy FP64, one BLAS thread per process during sampling"}
+
+
 
 
 # ---------------------------------------------------------------------------
@@ -186,10 +211,12 @@ def measured_traffic(kernel, L, D, chi, chains):
     counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
-    if not os.path.exists(path) or (L, D, chi, chains) != (8, 4, 16, 1024):
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if [L, D, chi, chains] != rec.get("workload_key"):
+        return None
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
@@ -199,72 +226,98 @@ def measured_traffic(kernel, L, D, chi, chains):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def run_path(p, torch, desc, theta0, configs0, args, seed):
-    """Times args.steps steps of one precision from the given state; returns
-    timings, the per-class kernel profile and the final state.  A step is
-    args.sweeps sweeps of every chain in one library call (the bottom
-    boundaries of each measurement serve the next sweep), with a
-    measurement after every sweep, then one SR solve on all n*sweeps
-    samples and the parameter update."""
-    dev = theta0.device
-    n = configs0.shape[0]
-    S = args.sweeps
-    theta = theta0.clone()
-    configs = configs0.clone()
-    nnz = p.peps_orow_count(desc)
-    out = {
-        "log_abs": torch.empty((S, n), dtype=torch.float64, device=dev),
-        "sign": torch.empty((S, n), dtype=torch.int8, device=dev),
-        "e_loc": torch.empty((S, n), dtype=torch.float64, device=dev),
-        "O": torch.empty((S, n, nnz), dtype=torch.float64, device=dev),
-        "configs": torch.empty((S, n, desc.N), dtype=torch.uint8, device=dev),
-    }
-    n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
-    status = p.new_status(dev)
-    gsweep = [0]
-    last = {}
+class Path:
+    """One precision's state and buffers for full steps (args.sweeps sweeps
+    of every chain in one library call, a measurement after each, then one
+    SR solve on all n * sweeps samples and the update)."""
 
-    def step():
-        p.peps_sample_sweep(desc, theta, configs, seed, gsweep[0], S, n_accept=n_accept, status=status, out=out)
-        gsweep[0] += S
-        _, _, stats, _ = p.sr_cg_solve(desc, out["configs"].view(S * n, desc.N), out["O"].view(S * n, nnz),
-                                       out["e_loc"].view(S * n), args.tau, args.eps, args.cg_iters, 1e-10,
-                                       want_g=False, theta=theta, status=status)
-        last["stats"] = stats
+    def __init__(self, p, torch, desc, theta0, configs0, args, seed):
+        self.p, self.torch, self.desc, self.args, self.seed = p, torch, desc, args, seed
+        dev = theta0.device
+        n = configs0.shape[0]
+        self.n = n
+        self.theta = theta0.clone()
+        self.configs = configs0.clone()
+        self.nnz = p.peps_orow_count(desc)
+        self.n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
+        self.status = p.new_status(dev)
+        self.gsweep = 0
+        # room for every traced launch of one full step (about 8 L1 per sweep)
+        self.trace = p.Trace(16 * desc.L1 * args.sweeps + 64)
+        self.out = None
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    p.check(status, "warmup")
-    n_accept.zero_()
+    def _buffers(self, S):
+        t = self.torch
+        dev = self.theta.device
+        n = self.n
+        if self.out is None or self.out["e_loc"].shape[0] != S:
+            self.out = None
+            self.out = {"log_abs": t.empty((S, n), dtype=t.float64, device=dev),
+                        "sign": t.empty((S, n), dtype=t.int8, device=dev),
+                        "e_loc": t.empty((S, n), dtype=t.float64, device=dev),
+                        "O": t.empty((S, n, self.nnz), dtype=t.float64, device=dev),
+                        "configs": t.empty((S, n, self.desc.N), dtype=t.uint8, device=dev)}
+        return self.out
 
-    p.peps_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = p.peps_profile_read()
-    p.peps_profile_enable(False)
-    p.check(status, "timed steps")
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    st = last["stats"].cpu().numpy()
-    acc = n_accept.cpu().numpy().sum(axis=0) / (n * S * args.steps)
-    del out
-    return {"ms_per_step": ms_per_step, "samples_per_s": n * S / (ms_per_step / 1e3), "wall": wall, "prof": prof,
-            "stats": st, "accept": acc, "theta": theta, "configs": configs}
+    def step(self, S, trace=None):
+        p, a, n = self.p, self.args, self.n
+        out = self._buffers(S)
+        p.peps_sample_sweep(self.desc, self.theta, self.configs, self.seed, self.gsweep, S, n_accept=self.n_accept,
+                            status=self.status, out=out, trace=trace)
+        self.gsweep += S
+        _, _, stats, _ = p.sr_cg_solve(self.desc, out["configs"].view(S * n, self.desc.N),
+                                       out["O"].view(S * n, self.nnz), out["e_loc"].view(S * n), a.tau, a.eps,
+                                       a.cg_iters, 1e-10, want_g=False, theta=self.theta, status=self.status,
+                                       trace=trace)
+        return stats
+
+    def warmup(self, k):
+        for _ in range(k):
+            self.step(1)
+        self.torch.cuda.synchronize()
+        self.p.check(self.status, "warmup")
+
+    def timed(self, max_steps, budget_s, label):
+        """Up to max_steps full steps, stopping after the one that ends past
+        budget_s of wall time; HIP events on torch's current stream (the
+        library's stream) bracket the whole run."""
+        t, p = self.torch, self.p
+        S = self.args.sweeps
+        self._buffers(S)
+        self.n_accept.zero_()
+        t.cuda.synchronize()
+        p.check(self.status, "before timed steps")
+        self.trace.read()
+        ev0, ev1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        k, stats = 0, None
+        prof = {}
+        while k < max_steps:
+            stats = self.step(S, trace=self.trace)
+            k += 1
+            t.cuda.synchronize()
+            for c, (ms, cnt) in self.trace.read().items():
+                a, b = prof.get(c, (0.0, 0))
+                prof[c] = (a + ms, b + cnt)
+            el = time.perf_counter() - t0
+            progress(f"{label}: step {k} done, {el:.1f} s")
+            if el >= budget_s:
+                break
+        ev1.record()
+        t.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        p.check(self.status, "timed steps")
+        ms_per_step = ev0.elapsed_time(ev1) / k
+        acc = (self.n_accept.sum(dim=0).to(t.float64) / float(self.n * S * k)).cpu().numpy()
+        return {"steps": k, "ms_per_step": ms_per_step, "samples_per_s": self.n * S / (ms_per_step / 1e3),
+                "wall": wall, "prof": prof, "stats": stats.cpu().numpy(), "accepted_per_sweep": acc}
 
 
-def graph_rate(p, torch, desc, theta0, configs0, args, seed):
+def graph_rate(p, torch, desc, theta0, configs0, args, seed, k=3):
     """A one-sweep step (sweep, measurement, SR on those n samples, update)
     run eagerly and, captured once in a HIP graph (caller-owned workspaces,
-    device sweep counter), replayed: ms per step of both, args.steps each
-    after args.warmup eager steps."""
+    device sweep counter), replayed: ms per step of both, k each."""
     dev = theta0.device
     n = configs0.shape[0]
     nnz = p.peps_orow_count(desc)
@@ -286,7 +339,7 @@ def graph_rate(p, torch, desc, theta0, configs0, args, seed):
         p.sr_cg_solve(desc, configs, out["O"][0], out["e_loc"][0], args.tau, args.eps, args.cg_iters, 1e-10,
                       want_g=False, theta=theta, status=status, ws=ws_sr)
 
-    def timed(fn, k):
+    def timed(fn):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
@@ -296,16 +349,14 @@ def graph_rate(p, torch, desc, theta0, configs0, args, seed):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / k
 
-    k = max(args.steps, 3)
-    for _ in range(args.warmup):
-        step()
+    step()
     torch.cuda.synchronize()
-    eager_ms = timed(step, k)
+    eager_ms = timed(step)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
     torch.cuda.synchronize()
-    graph_ms = timed(graph.replay, k)
+    graph_ms = timed(graph.replay)
     p.check(status, "graph replays")
     del graph
     return {"eager_ms_per_step": round(eager_ms, 3), "graph_ms_per_step": round(graph_ms, 3),
@@ -339,8 +390,10 @@ def simple_update_rate(p, torch, desc, steps=20, tau=0.01):
 def energy_error(p, torch, desc64, descmx, theta, configs):
     """Local energies of the same samples and parameters from both
     precisions: relative error of the mean energy, the same error in units
-    of the mean |E_loc| and of the Monte Carlo standard error, and per-sample
-    relative errors (scale max(|E_i|, mean |E|))."""
+    of the Monte Carlo standard error, per-sample relative errors (scale
+    max(|E_i|, mean |E|)), and the fraction of samples the mixed path
+    measured again in FP64 (their local energies equal the FP64 path's bit
+    for bit, the others differ by FP32 rounding)."""
     import numpy as np
     _, _, e64, s1 = p.peps_eval_batch(desc64, theta, configs)
     _, _, emx, s2 = p.peps_eval_batch(descmx, theta, configs)
@@ -354,29 +407,26 @@ def energy_error(p, torch, desc64, descmx, theta, configs):
     return {"n_samples": int(e64.size),
             "E_per_site_fp64": float(e64.mean() / (2 * desc64.N)),
             "mean_E_rel": float(dE / abs(e64.mean())),
-            "dE_over_mean_abs_E": float(dE / np.abs(e64).mean()),
             "dE_over_stderr": float(dE / max(e64.std() / np.sqrt(e64.size), 1e-300)),
             "sample_rel_median": float(np.median(rel)),
             "sample_rel_p99": float(np.quantile(rel, 0.99)),
-            "sample_rel_max": float(rel.max())}
+            "sample_rel_max": float(rel.max()),
+            "fp64_remeasured_fraction": float(np.mean(emx == e64))}
 
 
-def cooled_state(p, torch, desc64, L1, L2, D, n, steps, tau, eps, cg_iters, seed):
-    """theta and configurations after `steps` FP64 SR steps from the beta = 0
-    identity plus N(0, 1e-3^2) noise (beta_phys = 4 * steps * tau)."""
+def cooled_state(p, torch, L1, L2, D, chi, n, steps, sweeps, tau, eps, cg_iters, seed):
+    """theta and configurations after `steps` SR steps of the cooling loop
+    (FP64) from the beta = 0 identity plus N(0, 0.05^2) noise: |rho|
+    sampling with the Eq. A1 weights up to beta_phys = 0.3, |rho|^2 after it
+    (beta_phys = 4 steps tau at the end).  Returns (theta, configs, last
+    record)."""
     import synth
     dev = torch.device("cuda:0")
-    theta = torch.tensor(synth.theta_identity(L1, L2, D, 2, noise=1e-3, seed=101), device=dev)
+    desc = p.Desc(L1, L2, D, chi, alpha=1)
+    theta = torch.tensor(synth.theta_identity(L1, L2, D, 2, noise=0.05, seed=101), device=dev)
     configs = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=8), device=dev)
-    status = p.new_status(dev)
-    for k in range(steps):
-        res = p.peps_sample_sweep(desc64, theta, configs, seed, k, 1, status=status)
-        p.sr_cg_solve(desc64, configs, res["O"][0], res["e_loc"][0], tau, eps, cg_iters, 1e-10, want_g=False,
-                      theta=theta, status=status)
-    p.peps_sample_sweep(desc64, theta, configs, seed, steps, 1, measure=False, status=status)
-    torch.cuda.synchronize()
-    p.check(status, "cooling")
-    return theta, configs
+    recs = p.cool(desc, theta, configs, steps + 1, sweeps, tau, eps, seed, cg_iters=cg_iters, alpha_switch_beta=0.3)
+    return theta, configs, recs[-1]
 
 
 def eval_rate(p, torch, desc, theta, configs, reps=3):
@@ -396,8 +446,11 @@ def eval_rate(p, torch, desc, theta, configs, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="most full SR steps timed (mixed path)")
+    ap.add_argument("--warmup", type=int, default=2, help="one-sweep warm-up steps per precision")
+    ap.add_argument("--budget-s", type=float, default=120.0,
+                    help="wall-time budget of the timed mixed steps (the step that crosses it is the last)")
+    ap.add_argument("--fp64-steps", type=int, default=2, help="most full FP64 steps for the comparison")
     ap.add_argument("--sweeps", type=int, default=200, help="sweeps (samples per chain) per SR step")
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--D", type=int, default=4)
@@ -413,9 +466,11 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-4, help="energy error bar of the mixed path (relative)")
     ap.add_argument("--cool-steps", type=int, default=50,
-                    help="FP64 SR steps from the identity before the cooled-state energy check "
-                         "(beta_phys = 4 * steps * tau = 4 by default)")
+                    help="SR steps of the cooled-state energy check (beta_phys = 4 * steps * tau = 4 by default)")
+    ap.add_argument("--cool-sweeps", type=int, default=4, help="sweeps per SR step of the cooled-state check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the graph replay, evaluation-only and simple-update figures")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both",
                     help="run one precision only (profiling runs); the JSON line then carries that path")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -426,6 +481,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
               "path is a design note, not an implemented mode", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
 
     import torch
 
@@ -450,6 +506,7 @@ def main():
         descmx = p.Desc(L1, L2, D, chi, J2=args.J2, precision=p.PREC_MIXED)
         theta0 = torch.tensor(synth.theta_random_unit(L1, L2, D, 2, seed=seed_theta), device=dev)
         configs0 = torch.tensor(synth.configs_diagonal(n, L1 * L2, 2, seed=7), device=dev)
+    progress(f"setup done ({time.perf_counter() - t_start:.1f} s)")
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
@@ -460,65 +517,82 @@ def main():
 
     if args.only != "both":
         desc = desc64 if args.only == "fp64" else descmx
-        r = run_path(p, torch, desc, theta0, configs0, args, seed)
+        path = Path(p, torch, desc, theta0, configs0, args, seed)
+        path.warmup(args.warmup)
+        r = path.timed(args.steps, args.budget_s, args.only)
         line = {"only": args.only, "model": args.model, "lattice": [L1, L2], "D": D, "chi": chi,
-                "J2": args.J2, "chains": n,
+                "J2": args.J2, "chains": n, "steps": r["steps"],
                 "sweeps_per_step": args.sweeps, "samples_per_s": round(r["samples_per_s"], 2),
                 "ms_per_step": round(r["ms_per_step"], 3),
-                "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
+                "kernel_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["prof"].items()},
                 "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}
         if args.graph:
-            print("[bench] one-sweep step, eager and replayed graph", file=sys.stderr, flush=True)
+            progress("one-sweep step, eager and replayed graph")
             line["graph_replay"] = graph_rate(p, torch, desc, theta0, configs0, args, seed)
         print(json.dumps(line), flush=True)
         return
 
-    def progress(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    pmx = Path(p, torch, descmx, theta0, configs0, args, seed)
+    p64 = Path(p, torch, desc64, theta0, configs0, args, seed)
+    pmx.warmup(args.warmup)
+    p64.warmup(args.warmup)
+    progress(f"warm-up done ({time.perf_counter() - t_start:.1f} s)")
+    # both paths restart from the same state for the timed steps
+    pmx = Path(p, torch, descmx, theta0, configs0, args, seed)
+    rmx = pmx.timed(args.steps, args.budget_s, "mixed")
+    progress(f"mixed path: {rmx['steps']} steps, {rmx['ms_per_step']:.1f} ms per step")
+    p64 = Path(p, torch, desc64, theta0, configs0, args, seed)
+    r64 = p64.timed(min(args.fp64_steps, args.steps), args.budget_s, "fp64")
+    progress(f"fp64 path: {r64['steps']} steps, {r64['ms_per_step']:.1f} ms per step")
 
-    r64 = run_path(p, torch, desc64, theta0, configs0, args, seed)
-    progress(f"fp64 path: {r64['ms_per_step']:.1f} ms per step")
-    rmx = run_path(p, torch, descmx, theta0, configs0, args, seed)
-    progress(f"mixed path: {rmx['ms_per_step']:.1f} ms per step")
-    # energy error on the FP64 path's final samples and parameters, and on a
-    # cooled (physical) state
-    err_random = energy_error(p, torch, desc64, descmx, r64["theta"], r64["configs"])
-    th_c, cfg_c = cooled_state(p, torch, desc64, L1, L2, D, n, args.cool_steps, args.tau, args.eps, args.cg_iters,
-                               seed)
+    # precision gate: the same samples and parameters through both paths, on
+    # the random state after the FP64 steps and on a cooled state
+    err_random = energy_error(p, torch, desc64, descmx, p64.theta, p64.configs)
+    th_c, cfg_c, rec_c = cooled_state(p, torch, L1, L2, D, chi, n, args.cool_steps, args.cool_sweeps, args.tau,
+                                      args.eps, args.cg_iters, seed)
     err_cooled = energy_error(p, torch, desc64, descmx, th_c, cfg_c)
-    mixed_ok = err_cooled["mean_E_rel"] <= args.tol
-    progress("energy error checks done")
-    graph64 = graph_rate(p, torch, desc64, theta0, configs0, args, seed)
-    graphmx = graph_rate(p, torch, descmx, theta0, configs0, args, seed)
-    progress("graph replays done")
-    su = simple_update_rate(p, torch, desc64)
-    eval64 = eval_rate(p, torch, desc64, r64["theta"], r64["configs"])
-    evalmx = eval_rate(p, torch, descmx, r64["theta"], r64["configs"])
+    gate = {name: all(e[k] <= args.tol for k in ("mean_E_rel", "sample_rel_p99", "sample_rel_max"))
+            for name, e in (("random", err_random), ("cooled", err_cooled))}
+    mixed_ok = all(gate.values())
+    progress(f"energy error checks done ({time.perf_counter() - t_start:.1f} s)")
+    extras = {}
+    if not args.no_extras:
+        extras["graph_replay"] = {"fp64": graph_rate(p, torch, desc64, theta0, configs0, args, seed),
+                                  "mixed": graph_rate(p, torch, descmx, theta0, configs0, args, seed),
+                                  "note": "one-sweep step (1024 samples, SR on them) eager vs captured once as a "
+                                          "HIP graph and replayed"}
+        extras["simple_update"] = simple_update_rate(p, torch, desc64)
+        extras["eval_samples_per_s"] = {"fp64": round(eval_rate(p, torch, desc64, p64.theta, p64.configs), 1),
+                                        "mixed": round(eval_rate(p, torch, descmx, p64.theta, p64.configs), 1)}
+        progress(f"extras done ({time.perf_counter() - t_start:.1f} s)")
     best = rmx if mixed_ok else r64
     prof = best["prof"]
 
-    # dominant kernel class and its roofline
+    # dominant kernel class and its roofline: the row compression against the
+    # FP64 peak, work per launch = model flops per chain and row x chains
     dom = max(prof, key=lambda k: prof[k][0])
     comp_flops, comp_n = sweep_compression_flops(L1, L2, D, chi)
-    if dom == "compress":
-        ms, launches = prof["compress"]
-        avg_ms = ms / launches
-        flops_per_launch = comp_flops / comp_n * n
-        achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / MI355X_FP64_TFLOPS, 4),
-                "traffic": measured_traffic("k_compress2", L1, D, chi, n), "traffic_unit": "HBM bytes/launch",
-                "kernel": "k_compress2", "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_launch": flops_per_launch}
-    else:
-        ms, launches = prof[dom]
-        roof = {"bound": "alu", "achieved": None, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": dom, "avg_launch_ms": round(ms / max(launches, 1), 4)}
+    ms, launches = prof["compress"]
+    avg_ms = ms / max(launches, 1)
+    model_fl = model_row_flops(L2, D, chi) * n
+    exact_fl = comp_flops / comp_n * n
+    achieved = model_fl / (avg_ms / 1e3) / 1e12
+    traffic = measured_traffic("k_compress2", L1, D, chi, n)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / MI355X_FP64_TFLOPS, 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": "k_compress2", "kernel_class_share": round(ms / sum(v[0] for v in prof.values()), 4),
+            "dominant_class": dom, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "flops_per_launch": model_fl,
+            "flops_model": "L2 (2 chi^2 D^4 + 4 chi^3 D^4 + 16 chi^3 D^3) per chain and row",
+            "exact_dims_flops_per_launch": exact_fl,
+            "exact_dims_achieved": round(exact_fl / (avg_ms / 1e3) / 1e12, 3),
+            "exact_dims_frac": round(exact_fl / (avg_ms / 1e3) / 1e12 / MI355X_FP64_TFLOPS, 4)}
 
     # SR: O is read twice per CG iteration (O x, then O^T y), plus the
     # gradient pass
     nnz = p.peps_orow_count(desc64)
-    sr_ms = prof["sr"][0] / args.steps
+    sr_ms = prof["sr"][0] / best["steps"]
     cg_it = int(best["stats"][2])
     sr_bytes = (2 * cg_it + 1) * n * args.sweeps * nnz * 8
     sr_roof = {"bound": "hbm", "achieved": round(sr_bytes / (sr_ms / 1e3) / 1e9, 1), "peak": MI355X_HBM_GBS,
@@ -526,19 +600,22 @@ def main():
                "kernel": "sr_cg_solve", "ms_per_solve": round(sr_ms, 3), "cg_iters": cg_it}
 
     def summary(r):
-        return {"samples_per_s": round(r["samples_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 3),
-                "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in r["prof"].items()},
-                "accept_rate": {"h": round(float(r["accept"][0]), 3), "site": round(float(r["accept"][1]), 3),
-                                "v": round(float(r["accept"][2]), 3)},
+        return {"steps": r["steps"], "samples_per_s": round(r["samples_per_s"], 2),
+                "ms_per_step": round(r["ms_per_step"], 3),
+                "kernel_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["prof"].items()},
+                "accepted_moves_per_chain_and_sweep": {"h": round(float(r["accepted_per_sweep"][0]), 3),
+                                                       "site": round(float(r["accepted_per_sweep"][1]), 3),
+                                                       "v": round(float(r["accepted_per_sweep"][2]), 3)},
                 "E_per_site_last_step": float(r["stats"][0]) / (2 * L1 * L2),
-                "cg_iters_last_step": int(r["stats"][2])}
+                "cg_iters_last_step": int(r["stats"][2]), "cg_converged_last_step": bool(r["stats"][4] == 0.0)}
 
     line = {
         "metric": "PEPS-VMC samples/s (amp+O_k+E_loc) FP32-MFMA vs FP64 at stated energy error",
         "value": round(best["samples_per_s"], 2),
         "unit": "samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": best["steps"],
+        "steps_requested": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(best["ms_per_step"], 3),
         "higher_is_better": True,
@@ -555,24 +632,25 @@ def main():
                    "precision": "mixed (FP32 MFMA strips, FP64 QR/SVD/SR)" if mixed_ok else "fp64"},
         "roofline": roof,
         "roofline_sr": sr_roof,
-        "sr_steps_per_s": round(1e3 / best["ms_per_step"], 3),
+        "sr_steps_per_s": round(1e3 / best["ms_per_step"], 4),
         "fp64": summary(r64),
         "mixed": summary(rmx),
         "mixed_vs_fp64": round(rmx["samples_per_s"] / r64["samples_per_s"], 4),
-        "energy_error": {"tol": args.tol, "within_tol": mixed_ok,
-                         "cooled": dict(err_cooled, beta_phys=4 * args.cool_steps * args.tau,
-                                        state=f"identity + noise after {args.cool_steps} FP64 SR steps"),
-                         "random": dict(err_random, state="random unit-Frobenius tensors after the timed steps")},
-        "eval_samples_per_s": {"fp64": round(eval64, 1), "mixed": round(evalmx, 1)},
-        "graph_replay": {"fp64": graph64, "mixed": graphmx,
-                         "note": "one-sweep step (1024 samples, SR on them) eager vs captured once as a HIP "
-                                 "graph and replayed"},
-        "host_wall_ms_per_step": round(best["wall"] * 1e3 / args.steps, 3),
-        "simple_update": su,
+        "energy_error": {"tol": args.tol, "within_tol": mixed_ok, "gate": gate,
+                         "cooled": dict(err_cooled, beta_phys=rec_c["beta_phys"],
+                                        E_per_site_cooling=rec_c["E_per_site"],
+                                        E_stderr_cooling=rec_c["E_stderr"],
+                                        state=f"identity + N(0, 0.05^2) noise after {args.cool_steps} SR steps "
+                                              f"of {n} chains x {args.cool_sweeps} sweeps (alpha 1 below "
+                                              f"beta_phys 0.3, then 2)"),
+                         "random": dict(err_random, state="random unit-Frobenius tensors after the FP64 steps")},
+        "host_wall_ms_per_step": round(best["wall"] * 1e3 / best["steps"], 3),
     }
+    line.update(extras)
     if not args.no_cpu_baseline:
-        progress("CPU oracle baseline")
+        progress(f"CPU oracle baseline ({time.perf_counter() - t_start:.1f} s)")
         line["cpu_baseline"] = cpu_baseline(L1, L2, D, chi, seed_theta, seed, args.cg_iters)
+    line["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(line), flush=True)
 
 

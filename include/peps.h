@@ -34,9 +34,13 @@
  *
  * Errors.  Shape and argument errors are returned before anything is
  * enqueued.  A failed launch returns PEPS_ERR_HIP.  Data-dependent failures
- * (non-finite parameters, a zero amplitude, CG breakdown) are recorded in
- * the device word `status` (0 = fine, otherwise a peps_status value, first
- * failure wins), which the caller reads after its own synchronisation.
+ * (non-finite parameters, a zero amplitude, CG breakdown, a configuration
+ * digit outside [0, d^2)) are recorded in the device word `status` (0 =
+ * fine, otherwise a peps_status value; the first error wins), which the
+ * caller reads after its own synchronisation.  Digits are read only after
+ * a range check: a digit >= d^2 records PEPS_ERR_ARG and is read as 0, so
+ * that no kernel indexes theta or a parameter vector out of range (the
+ * results of such a sample are then meaningless).
  */
 #ifndef PEPS_H
 #define PEPS_H
@@ -79,10 +83,31 @@ typedef struct {
                         S^+ = c^dag_up c_dn; no Jordan-Wigner sign); 0 gives the
                         plain Hubbard model                                      */
   double t, U, mu;   /* Hubbard parameters (Benchmark section, Eq. hubbard_model)  */
-  int32_t precision; /* PEPS_PREC_*: FP64 throughout, or FP32 contractions with
-                        FP64 truncation / reductions / log-scales                  */
+  int32_t precision; /* PEPS_PREC_*: FP64 throughout, or FP32 strip contractions
+                        with FP64 truncation / reductions / log-scales.  In the
+                        mixed form every measurement (log|psi|, E_loc, O row)
+                        also estimates its own rounding error from the FP32
+                        strips; a sample whose estimate exceeds 1e-5 (relative
+                        to its amplitudes, or to max(|E_loc|, 1)) is measured
+                        again with the FP64 strips, so its outputs equal the
+                        FP64 path's.  Metropolis ratios stay FP32.             */
   int32_t alpha;     /* sampling weight |rho|^alpha: 2, or 1 (Appendix A, Eq. A1)  */
+  int32_t fermionic; /* 0: plain tensors.  1 (Hubbard only): the tensors are
+                        Z2-graded and parity-even (Method section, fPEPS
+                        paragraph): every site tensor is nonzero only where
+                        p(S) + p(l) + p(u) + p(r) + p(d) is even, p(S) the
+                        fermion-number parity of the digits (s, s') and a bond
+                        index even for index < D/2.  A configuration of odd
+                        total parity then has amplitude exactly 0; the device
+                        decides it from the digits in integer arithmetic and
+                        reports it as a zero amplitude without contracting     */
 } peps_desc;
+
+/* Instrumentation handle (not part of the method): a caller-owned record of
+   HIP event pairs around the kernel launches of the device calls that
+   receive it.  NULL everywhere means no instrumentation.  A trace is used by
+   one stream at a time; the library keeps no state of its own. */
+typedef struct peps_trace peps_trace;
 
 /* ---- host, pure ------------------------------------------------------- */
 
@@ -119,7 +144,7 @@ const char* peps_status_string(peps_status s);
 peps_status peps_eval_batch(const peps_desc* desc, const double* theta, int32_t n,
                             const uint8_t* configs, double* log_abs, int8_t* sign,
                             double* e_loc, int32_t* status, void* ws, size_t ws_bytes,
-                            peps_stream_t stream);
+                            peps_trace* trace, peps_stream_t stream);
 
 /* Log-derivatives O_k(S) = d rho / d theta_k / rho (Method section, Eq. 8)
    of n fixed configurations, one compressed row each: O_rows [n][nnz] f64.
@@ -128,7 +153,8 @@ peps_status peps_eval_batch(const peps_desc* desc, const double* theta, int32_t 
    log_abs may be NULL. */
 peps_status peps_grad_batch(const peps_desc* desc, const double* theta, int32_t n,
                             const uint8_t* configs, double* O_rows, double* log_abs,
-                            int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
+                            int32_t* status, void* ws, size_t ws_bytes, peps_trace* trace,
+                            peps_stream_t stream);
 
 /* n_sweeps Metropolis sweeps of n_chains independent chains (Method section:
    MCMC over S; acceptance min(1, |R|^alpha)), each sweep followed by a
@@ -155,26 +181,50 @@ peps_status peps_sample_sweep(const peps_desc* desc, const double* theta, int32_
                               uint64_t* sweep_counter, int32_t n_sweeps, double* log_abs,
                               int8_t* sign, double* e_loc, double* O_rows, uint8_t* sample_configs,
                               int32_t* n_accept, int32_t* status, void* ws, size_t ws_bytes,
-                              peps_stream_t stream);
+                              peps_trace* trace, peps_stream_t stream);
 
 /* Stochastic-reconfiguration update (Method section, Eqs. 5-7 and 10):
    Ebar = <E>, obar = <O>, g = <O (E - Ebar)>, S x = <O (O.x - obar.x)>,
    and (S + eps 1) dtheta = -tau g solved by conjugate gradient from
    dtheta = 0, never forming S: each iteration applies O (gather) then O^T
-   (scatter).  Averages are uniform over the n_s samples, or weighted by
-   `weights` [n_s] (Appendix A, Eq. A1) when it is not NULL.  The residual
-   test ||r|| <= rtol ||b|| (b = -tau g) is taken before each iteration;
-   at most max_iter iterations.
+   (scatter).  The averages <f> = sum_i w_i f_i / sum_i w_i take their
+   weights from, in this order: `weights` [n_s] when not NULL; else, when
+   `log_abs` [n_s] is not NULL, w_i = |rho_i|^(2 - alpha) formed on the
+   device from the log-amplitudes (relative to their largest, so no value
+   overflows): uniform for alpha = 2, and |rho_i| for samples drawn from
+   |rho| (alpha = 1, Appendix A, Eq. A1); else uniform.  The residual test
+   ||r|| <= rtol ||b|| (b = -tau g) is taken before each iteration; at most
+   max_iter iterations.
    configs [n_s][N] uint8; O_rows [n_s][nnz]; e_loc [n_s];
    dtheta [N_p] out; g_out [N_p] out or NULL; theta [N_p] in/out or NULL:
    when given, the update theta <- theta + dtheta (Eq. 5) is applied too;
-   stats [4] device f64 out: Ebar, final ||r||, iterations, ||b||.
-   CG breakdown is reported in `status` (theta is then left unchanged). */
+   stats [PEPS_SR_NSTATS] device f64 out: Ebar, final ||r||, iterations,
+   ||b||, and 1 if the solve stopped at max_iter with ||r|| > rtol ||b||
+   (else 0).  That case also records PEPS_WARN_CG_NOT_CONVERGED in `status`
+   when no error is recorded there (a warning never replaces an error; an
+   error replaces a warning).  CG breakdown is reported in `status` (theta
+   is then left unchanged). */
+enum { PEPS_SR_NSTATS = 5 };
 peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* configs,
-                        const double* O_rows, const double* weights, const double* e_loc,
-                        double tau, double eps, int32_t max_iter, double rtol,
+                        const double* O_rows, const double* weights, const double* log_abs,
+                        const double* e_loc, double tau, double eps, int32_t max_iter, double rtol,
                         double* dtheta, double* g_out, double* theta, double* stats,
-                        int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream);
+                        int32_t* status, void* ws, size_t ws_bytes, peps_trace* trace,
+                        peps_stream_t stream);
+
+/* Sample statistics of k per-sample quantities (Method section: the
+   averages of Eqs. 6-7 and in_en; Appendix A, Eq. A1 for alpha = 1):
+   values [n_sweeps * n_chains][k] f64, sample index i = sweep * n_chains +
+   chain (the row order of peps_sample_sweep's outputs).  Weights as in
+   sr_cg_solve: `weights` [n_sweeps * n_chains] when not NULL, else
+   |rho_i|^(2 - alpha) from log_abs when it is not NULL, else uniform.
+   out [k][2] f64: the weighted mean over all samples, and the standard
+   error of the mean estimated from the n_chains per-chain weighted means
+   (their sample standard deviation over sqrt(n_chains); 0 when n_chains =
+   1).  One kernel, fixed summation order; no workspace. */
+peps_status peps_sample_stats(const peps_desc* desc, int32_t n_sweeps, int32_t n_chains, int32_t k,
+                              const double* values, const double* weights, const double* log_abs,
+                              double* out, peps_stream_t stream);
 
 /* Vector-Jacobian product of the log-amplitudes (Eq. 8: O_i is the gradient
    of log|rho(S_i)| with respect to theta): grad = sum_i cot_i O_i, scattered
@@ -234,29 +284,33 @@ peps_status peps_su_absorb(const peps_desc* desc, const double* theta, const dou
 
 /* ---- instrumentation (not part of the method) --------------------------- */
 
-/* Kernel classes timed by the profiler. */
+/* Kernel classes of a trace. */
 enum {
   PEPS_K_COMPRESS = 0, /* boundary row absorption + QR/SVD truncation       */
   PEPS_K_MOVES1 = 1,   /* Metropolis passes inside a row (one-row strips)   */
   PEPS_K_MOVES2 = 2,   /* vertical exchanges (two-row strips)               */
   PEPS_K_MEAS1 = 3,    /* O rows, in-row E_loc terms, log|psi|              */
   PEPS_K_MEAS2 = 4,    /* cross-row E_loc terms                             */
-  PEPS_K_FINAL = 5,    /* per-sample outputs                                */
-  PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve or
-                          peps_vjp_batch call                               */
+  PEPS_K_FINAL = 5,    /* per-sample outputs (and the FP64 re-evaluation of
+                          ill-conditioned samples of the mixed path)        */
+  PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve call       */
   PEPS_N_KCLASS = 7
 };
 
-/* Start (on = 1) or stop (on = 0) bracketing every launch of the calls
-   above with HIP events on the call's stream, and clear the accumulators.
-   Host only; the library keeps one global table. */
-void peps_profile_enable(int32_t on);
+/* Host: a trace with room for `capacity` timed launches (two HIP events
+   each, created on the current device).  NULL if capacity < 1 or an event
+   cannot be created.  Launches beyond the capacity are not timed. */
+peps_trace* peps_trace_create(int32_t capacity);
 
-/* Synchronise the recorded events and add, per kernel class, the summed
-   duration in milliseconds to ms[PEPS_N_KCLASS] and the number of timed
-   launches (sr_cg_solve counts as one) to launches[PEPS_N_KCLASS]; then
-   clear.  Returns PEPS_ERR_HIP if an event query failed. */
-peps_status peps_profile_read(double* ms, int64_t* launches);
+/* Host: releases the events and the handle (NULL is a no-op). */
+void peps_trace_destroy(peps_trace* trace);
+
+/* Host: synchronises the recorded events and adds, per kernel class, the
+   summed duration in milliseconds to ms[PEPS_N_KCLASS] and the number of
+   timed launches (one sr_cg_solve call counts as one) to
+   launches[PEPS_N_KCLASS]; then empties the trace.  PEPS_ERR_ARG for a NULL
+   trace, PEPS_ERR_HIP if an event query failed. */
+peps_status peps_trace_read(peps_trace* trace, double* ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

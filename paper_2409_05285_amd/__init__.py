@@ -4,8 +4,8 @@ The computation lives in libpeps.so (HIP for gfx950, C ABI in
 include/peps.h); this package only marshals arguments.  Importing it fails
 if the library has not been built (python paper_2409_05285_amd/build.py).
 """
-from .api import (Desc, PepsLogAmp, check, new_status, peps_eval_batch, peps_grad_batch,  # noqa: F401
-                  peps_orow_count, peps_param_count, peps_profile_enable, peps_profile_read,
+from .api import (Desc, PepsLogAmp, Trace, check, new_status, peps_eval_batch, peps_grad_batch,  # noqa: F401
+                  peps_orow_count, peps_param_count, peps_sample_stats,
                   peps_sample_sweep, peps_slot_count, peps_vjp_batch, peps_workspace_bytes, sr_cg_solve,
                   workspace_bytes, peps_observables_batch, thermal_observables, OBS_NAMES,
                   nnn_spin_correlation, specific_heat, peps_simple_update, peps_su_absorb, su_bond_count)

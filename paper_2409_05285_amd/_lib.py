@@ -20,6 +20,7 @@ STATUS = {
     -4: "workspace too small", -5: "non-finite value", -6: "zero strip amplitude", -7: "CG breakdown",
     1: "CG not converged",
 }
+STATUS_HIP = -3
 MODEL_HEISENBERG, MODEL_HUBBARD = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR, WS_SU = 0, 1, 2, 3, 4
@@ -31,7 +32,7 @@ class PepsDesc(ctypes.Structure):
         ("L1", c_int32), ("L2", c_int32), ("d", c_int32), ("D", c_int32), ("chi", c_int32),
         ("model", c_int32),
         ("J1", c_double), ("J2", c_double), ("t", c_double), ("U", c_double), ("mu", c_double),
-        ("precision", c_int32), ("alpha", c_int32),
+        ("precision", c_int32), ("alpha", c_int32), ("fermionic", c_int32),
     ]
 
 
@@ -57,18 +58,18 @@ def _load():
     lib.peps_status_string.argtypes = [c_int32]
     lib.peps_status_string.restype = ctypes.c_char_p
     lib.peps_eval_batch.argtypes = [P, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                    c_void_p, c_size_t, c_void_p]
+                                    c_void_p, c_size_t, c_void_p, c_void_p]
     lib.peps_eval_batch.restype = c_int32
     lib.peps_grad_batch.argtypes = [P, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                    c_size_t, c_void_p]
+                                    c_size_t, c_void_p, c_void_p]
     lib.peps_grad_batch.restype = c_int32
     lib.peps_sample_sweep.argtypes = [P, c_void_p, c_int32, c_void_p, c_uint64, c_uint64, c_void_p, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                      c_size_t, c_void_p]
+                                      c_size_t, c_void_p, c_void_p]
     lib.peps_sample_sweep.restype = c_int32
-    lib.sr_cg_solve.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32,
-                                c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
-                                c_void_p]
+    lib.sr_cg_solve.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_size_t, c_void_p, c_void_p]
     lib.sr_cg_solve.restype = c_int32
     lib.peps_vjp_batch.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.peps_vjp_batch.restype = c_int32
@@ -79,16 +80,22 @@ def _load():
     lib.peps_simple_update.restype = c_int32
     lib.peps_su_absorb.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.peps_su_absorb.restype = c_int32
-    lib.peps_profile_enable.argtypes = [c_int32]
-    lib.peps_profile_enable.restype = None
-    lib.peps_profile_read.argtypes = [POINTER(c_double), POINTER(c_int64)]
-    lib.peps_profile_read.restype = c_int32
+    lib.peps_sample_stats.argtypes = [P, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+    lib.peps_sample_stats.restype = c_int32
+    lib.peps_trace_create.argtypes = [c_int32]
+    lib.peps_trace_create.restype = c_void_p
+    lib.peps_trace_destroy.argtypes = [c_void_p]
+    lib.peps_trace_destroy.restype = None
+    lib.peps_trace_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+    lib.peps_trace_read.restype = c_int32
     return lib
 
 
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
-           "peps_vjp_batch", "peps_observables_batch", "peps_simple_update", "peps_su_absorb",
-           "peps_profile_enable", "peps_profile_read"]
+           "peps_vjp_batch", "peps_observables_batch", "peps_sample_stats", "peps_simple_update",
+           "peps_su_absorb", "peps_trace_create", "peps_trace_destroy", "peps_trace_read"]
+SR_NSTATS = 5   # sr_cg_solve stats: Ebar, |r|, iterations, |b|, not-converged flag
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

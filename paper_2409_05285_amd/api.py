@@ -34,10 +34,11 @@ class Desc:
     mu: float = 0.0
     precision: int = _lib.PREC_FP64
     alpha: int = 2
+    fermionic: int = 0
 
     def c(self):
         return PepsDesc(self.L1, self.L2, self.d, self.D, self.chi, self.model, self.J1, self.J2, self.t,
-                        self.U, self.mu, self.precision, self.alpha)
+                        self.U, self.mu, self.precision, self.alpha, self.fermionic)
 
     @property
     def N(self):
@@ -137,7 +138,42 @@ def _configs(desc, configs):
         raise ValueError("configs must be uint8 [n, L1*L2]")
     if not configs.is_contiguous():
         raise ValueError("configs must be contiguous")
+    # digits must lie in [0, d^2); checked here unless a graph is being
+    # captured (the library's kernels check on the device as well and record
+    # PEPS_ERR_ARG in the status word)
+    if configs.numel() > 0 and not (configs.is_cuda and torch.cuda.is_current_stream_capturing()):
+        if int(configs.max()) >= desc.d * desc.d:
+            raise ValueError("configuration digits must lie in [0, d^2)")
     return configs
+
+
+class Trace:
+    """Instrumentation handle (peps_trace): HIP events around the kernel
+    launches of the calls it is passed to.  `read()` synchronises and returns
+    {kernel class: (total ms, launches)} and empties the trace."""
+
+    def __init__(self, capacity=1 << 16):
+        self.h = LIB.peps_trace_create(int(capacity))
+        if not self.h:
+            raise PepsError(_lib.STATUS_HIP, "peps_trace_create")
+
+    def read(self):
+        ms = (ctypes.c_double * len(_lib.KCLASS))()
+        cnt = (ctypes.c_int64 * len(_lib.KCLASS))()
+        _raise(LIB.peps_trace_read(self.h, ms, cnt), "peps_trace_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KCLASS)}
+
+    def close(self):
+        if self.h:
+            LIB.peps_trace_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _tr(trace):
+    return ctypes.c_void_p(trace.h) if trace is not None else None
 
 
 def new_status(device):
@@ -151,7 +187,7 @@ def check(status, where="device"):
     return code
 
 
-def peps_eval_batch(desc: Desc, theta, configs, want_e=True, status=None):
+def peps_eval_batch(desc: Desc, theta, configs, want_e=True, status=None, trace=None):
     """(log_abs [n] f64, sign [n] i8, e_loc [n] f64 or None, status)."""
     theta = _theta(desc, theta)
     configs = _configs(desc, configs)
@@ -165,12 +201,12 @@ def peps_eval_batch(desc: Desc, theta, configs, want_e=True, status=None):
     nb = peps_workspace_bytes(desc, n, _lib.WS_EVAL)
     ws = _ws("chain", nb, dev)
     code = LIB.peps_eval_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(log_abs), _ptr(sign),
-                               _ptr(e_loc), _ptr(status), _ptr(ws), ws.numel(), _stream())
+                               _ptr(e_loc), _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_eval_batch")
     return log_abs, sign, e_loc, status
 
 
-def peps_grad_batch(desc: Desc, theta, configs, status=None):
+def peps_grad_batch(desc: Desc, theta, configs, status=None, trace=None):
     """(O_rows [n, nnz] f64, log_abs [n] f64, status)."""
     theta = _theta(desc, theta)
     configs = _configs(desc, configs)
@@ -182,13 +218,14 @@ def peps_grad_batch(desc: Desc, theta, configs, status=None):
     status = new_status(dev) if status is None else status
     ws = _ws("chain", peps_workspace_bytes(desc, n, _lib.WS_GRAD), dev)
     code = LIB.peps_grad_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(O), _ptr(log_abs),
-                               _ptr(status), _ptr(ws), ws.numel(), _stream())
+                               _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_grad_batch")
     return O, log_abs, status
 
 
 def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measure=True, want_O=True,
-                      n_accept=None, status=None, out=None, sweep_counter=None, ws=None, want_configs=False):
+                      n_accept=None, status=None, out=None, sweep_counter=None, ws=None, want_configs=False,
+                      trace=None):
     """Runs n_sweeps sweeps in place on `configs`.  Returns a dict with
     log_abs / sign / e_loc [n_sweeps, n] and O [n_sweeps, n, nnz] (when
     measured), configs [n_sweeps, n, N] (the configuration of every
@@ -235,7 +272,7 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
     code = LIB.peps_sample_sweep(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(seed), int(sweep0),
                                  _ptr(sweep_counter), int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
                                  _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(res.get("configs")),
-                                 _ptr(n_accept), _ptr(status), _ptr(ws), ws.numel(), _stream())
+                                 _ptr(n_accept), _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_sample_sweep")
     res["n_accept"] = n_accept
     res["status"] = status
@@ -243,10 +280,13 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
 
 
 def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, weights=None, want_g=True,
-                theta=None, status=None, ws=None):
-    """(dtheta [N_p], g [N_p] or None, stats [4] = (Ebar, |r|, iters, |b|), status).
-    When `theta` (float64 [N_p], device) is given it is updated in place:
-    theta += dtheta.  `ws`: optional caller-owned workspace of at least
+                theta=None, status=None, ws=None, log_abs=None, trace=None):
+    """(dtheta [N_p], g [N_p] or None, stats [5] = (Ebar, |r|, iters, |b|,
+    not-converged flag), status).  Averages are weighted by `weights` [n_s]
+    when given, else by |rho|^(2 - alpha) formed on the device from
+    `log_abs` [n_s] when given (Eq. A1), else uniform.  When `theta`
+    (float64 [N_p], device) is given it is updated in place: theta +=
+    dtheta.  `ws`: optional caller-owned workspace of at least
     workspace_bytes(desc, n_s, "sr") bytes."""
     configs = _configs(desc, configs)
     n_s = configs.shape[0]
@@ -254,22 +294,48 @@ def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, we
         raise ValueError("O_rows must be contiguous float64 [n_s, nnz]")
     if e_loc.dtype != torch.float64 or e_loc.shape != (n_s,):
         raise ValueError("e_loc must be float64 [n_s]")
-    _check_dev(configs, O_rows, e_loc, weights, theta)
+    for name, v in (("weights", weights), ("log_abs", log_abs)):
+        if v is not None and (v.dtype != torch.float64 or v.shape != (n_s,) or not v.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 [n_s] tensor" % name)
+    _check_dev(configs, O_rows, e_loc, weights, theta, log_abs)
     dev = O_rows.device
     n_p = peps_param_count(desc)
     if theta is not None and (theta.dtype != torch.float64 or theta.shape != (n_p,) or not theta.is_contiguous()):
         raise ValueError("theta must be a contiguous float64 vector of length N_p")
     dtheta = torch.empty(n_p, dtype=torch.float64, device=dev)
     g = torch.empty(n_p, dtype=torch.float64, device=dev) if want_g else None
-    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    stats = torch.zeros(_lib.SR_NSTATS, dtype=torch.float64, device=dev)
     status = new_status(dev) if status is None else status
     ws = _own_ws(ws, "sr", peps_workspace_bytes(desc, n_s, _lib.WS_SR), dev)
-    code = LIB.sr_cg_solve(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights),
+    code = LIB.sr_cg_solve(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights), _ptr(log_abs),
                            _ptr(e_loc.contiguous()), float(tau), float(eps), int(max_iter), float(rtol),
                            _ptr(dtheta), _ptr(g), _ptr(theta), _ptr(stats), _ptr(status), _ptr(ws), ws.numel(),
-                           _stream())
+                           _tr(trace), _stream())
     _raise(code, "sr_cg_solve")
     return dtheta, g, stats, status
+
+
+def peps_sample_stats(desc: Desc, values, n_chains, log_abs=None, weights=None):
+    """Weighted means and standard errors of per-sample quantities:
+    values [n_sweeps * n_chains, k] (or [n_sweeps * n_chains]) float64 in
+    the sample order of peps_sample_sweep; weights `weights` when given,
+    else |rho|^(2 - alpha) from `log_abs` when given, else uniform.  Returns
+    a device tensor [k, 2] (mean, standard error of the mean from the
+    per-chain means)."""
+    v = values if values.dim() == 2 else values.reshape(-1, 1)
+    if v.dtype != torch.float64 or not v.is_contiguous():
+        raise ValueError("values must be contiguous float64")
+    n_s, k = v.shape
+    if n_chains < 1 or n_s % n_chains != 0:
+        raise ValueError("the sample count must be a multiple of n_chains")
+    for name, x in (("log_abs", log_abs), ("weights", weights)):
+        if x is not None and (x.dtype != torch.float64 or x.numel() != n_s or not x.is_contiguous()):
+            raise ValueError("%s must be contiguous float64 with one entry per sample" % name)
+    _check_dev(v, log_abs, weights)
+    out = torch.empty((k, 2), dtype=torch.float64, device=v.device)
+    _raise(LIB.peps_sample_stats(ctypes.byref(desc.c()), n_s // n_chains, int(n_chains), k, _ptr(v), _ptr(weights),
+                                 _ptr(log_abs), _ptr(out), _stream()), "peps_sample_stats")
+    return out
 
 
 def peps_vjp_batch(desc: Desc, configs, O_rows, cot):
@@ -304,21 +370,25 @@ def peps_observables_batch(desc: Desc, configs):
     return out
 
 
-def thermal_observables(desc: Desc, configs, beta_phys, weights=None):
-    """Sample estimates at inverse temperature beta_phys: per-site <M_z^2>/N,
-    susceptibility beta <M_z^2> / N (<M_z>^2 := 0), <n>/N and double
-    occupancy <D>/N, weighted by `weights` (Eq. A1) when given.  Host
-    floats; synchronises."""
+def thermal_observables(desc: Desc, configs, beta_phys, n_chains=None, log_abs=None, weights=None):
+    """Sample estimates at inverse temperature beta_phys, reduced on the
+    device (peps_sample_stats): per-site <M_z^2>/N, the susceptibility
+    beta <M_z^2> / N (<M_z>^2 := 0), <n>/N and the double occupancy <D>/N,
+    each with its standard error from the per-chain means (n_chains chains,
+    samples in sweep-major order; default: one chain per sample), weighted
+    by |rho|^(2 - alpha) from `log_abs` when given (Eq. A1).  Host floats;
+    synchronises."""
     v = peps_observables_batch(desc, configs)
-    if weights is None:
-        m = v.mean(dim=0)
-    else:
-        w = weights.to(torch.float64)
-        m = (w[:, None] * v).sum(dim=0) / w.sum()
-    m = m.cpu().tolist()
+    n = configs.shape[0]
+    st = peps_sample_stats(desc, v, n if n_chains is None else n_chains, log_abs, weights).cpu().numpy()
     N = desc.N
-    return {"mz2_per_site": m[1] / N, "chi": beta_phys * m[1] / N, "n_per_site": m[2] / N,
-            "docc_per_site": m[3] / N, "mz_per_site": m[0] / N}
+    out = {}
+    for q, name in enumerate(("mz_per_site", "mz2_per_site", "n_per_site", "docc_per_site")):
+        out[name] = float(st[q, 0]) / N
+        out[name + "_stderr"] = float(st[q, 1]) / N
+    out["chi"] = beta_phys * out["mz2_per_site"]
+    out["chi_stderr"] = beta_phys * out["mz2_per_site_stderr"]
+    return out
 
 
 def su_bond_count(desc: Desc) -> int:
@@ -358,23 +428,22 @@ def peps_su_absorb(desc: Desc, theta, lambdas):
     return out
 
 
-def nnn_spin_correlation(desc: Desc, theta, configs, weights=None):
+def nnn_spin_correlation(desc: Desc, theta, configs, n_chains=None, log_abs=None, weights=None):
     """F = sum_<<ij>> <S_i.S_j> / M over the M = 2 (L1-1)(L2-1)
     next-nearest-neighbour pairs (Benchmark section, Hubbard model; also
     defined for spins): local energies of the Hamiltonian sum_<<ij>> S_i.S_j
-    (J2 = 1, every other coupling 0) from peps_eval_batch, averaged with
-    `weights` (Eq. A1) when given and halved.  Returns (F, per-sample local
+    (J2 = 1, every other coupling 0) from peps_eval_batch, averaged on the
+    device (peps_sample_stats; weights `weights`, else |rho|^(2 - alpha)
+    from `log_abs`, else uniform) and halved.  Returns (F, its standard error, per-sample local
     values); synchronises."""
     d = dataclasses.replace(desc, J1=0.0, J2=1.0, t=0.0, U=0.0, mu=0.0)
     _, _, e, status = peps_eval_batch(d, theta, configs)
+    n = configs.shape[0]
+    st = peps_sample_stats(desc, e, n if n_chains is None else n_chains, log_abs, weights)
     check(status, "nnn_spin_correlation")
-    if weights is None:
-        m = float(e.mean())
-    else:
-        w = weights.to(torch.float64)
-        m = float((w * e).sum() / w.sum())
+    m, se = st[0].cpu().tolist()
     M = 2 * (desc.L1 - 1) * (desc.L2 - 1)
-    return m / (2.0 * M), e
+    return m / (2.0 * M), se / (2.0 * M), e
 
 
 def specific_heat(betas, energies, smoothing=None, weights=None):
@@ -415,14 +484,3 @@ class PepsLogAmp(torch.autograd.Function):
         return grad, None, None
 
 
-def peps_profile_enable(on: bool):
-    """Bracket every library launch with HIP events (instrumentation)."""
-    LIB.peps_profile_enable(1 if on else 0)
-
-
-def peps_profile_read():
-    """{kernel class: (total ms, launches)} since the last read; synchronises."""
-    ms = (ctypes.c_double * len(_lib.KCLASS))()
-    cnt = (ctypes.c_int64 * len(_lib.KCLASS))()
-    _raise(LIB.peps_profile_read(ms, cnt), "peps_profile_read")
-    return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KCLASS)}

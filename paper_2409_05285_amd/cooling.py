@@ -6,48 +6,45 @@ then the SR solve on all samples with theta updated in place
 (`sr_cg_solve`).  After n steps the state approximates exp(-n tau calH)|I>,
 whose energy E = Ebar / 2 belongs to inverse temperature beta_phys =
 4 n tau.  With alpha = 1 (Appendix A) the samples are drawn from |rho| and
-every average, the SR metric included, is weighted by |rho| (Eq. A1).
+every average, the SR metric included, is weighted by |rho| (Eq. A1); the
+weights are formed on the device from the log-amplitudes.  The paper samples
+this way at high temperature only and switches to |rho|^2 sampling near
+beta = 0.3 (Benchmark section, Heisenberg paragraph): `alpha_switch_beta`
+sets that temperature.
 
 The state of a run is (theta, configurations, next global sweep index): a
 run resumed from a saved state with `gsweep0` and `step0` continues the
 same chain of states bit for bit.
 
-Host orchestration only: every contraction, factorisation and reduction
-runs in the library's kernels; the host reads back the per-sample
-log-amplitudes and local energies for the log record (and, for alpha = 1,
-forms the weights |rho| / max |rho| from the log-amplitudes).
+Host orchestration only: every contraction, factorisation, weight and
+reduction runs in the library's kernels (the means and standard errors of
+the log record by peps_sample_stats); the host reads back those few scalars.
 """
 from __future__ import annotations
 
+import dataclasses
 import json
 import time
 
-import numpy as np
 import torch
 
 from . import api
 
 
-def _mean_and_stderr(values, w):
-    """Weighted mean over all samples of [S, n] values and the standard
-    error of the per-chain weighted means."""
-    m = float((w * values).sum() / w.sum())
-    chain = (w * values).sum(axis=0) / w.sum(axis=0)
-    se = float(chain.std(ddof=1) / np.sqrt(chain.size)) if chain.size > 1 else 0.0
-    return m, se
-
-
 def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, seed, cg_iters=200, rtol=1e-10,
-         step0=0, gsweep0=0, log=None, observables=False, su_steps=0):
+         step0=0, gsweep0=0, log=None, observables=False, su_steps=0, alpha_switch_beta=None):
     """Run n_steps SR steps; theta (float64 [N_p], device) and configs (uint8
     [n_chains, N], device) are updated in place.  `log`: a text stream that
     receives one JSON line per step.  Returns the list of records:
-      step, beta_phys (of the samples of this step, 4 tau step), E_per_site
-      and its standard error from the chain means, accepted moves per chain
-      and sweep (horizontal exchange, site move, vertical exchange), CG
-      iterations and relative residual |r| / |b|, |dtheta|, samples/s of the
-      step (wall clock), and gsweep, the global sweep index the next step
-      starts from.
+      step, beta_phys (of the samples of this step, 4 tau step), alpha (the
+      sampling exponent of the step), E_per_site and its standard error
+      from the chain means, accepted moves per chain and sweep (horizontal
+      exchange, site move, vertical exchange), CG iterations, relative
+      residual |r| / |b| and whether the residual bar was met, |dtheta|,
+      samples/s of the step (wall clock), and gsweep, the global sweep index
+      the next step starts from.
+    alpha_switch_beta: with desc.alpha = 1, the steps whose beta_phys is at
+    or above this value sample |rho|^2 instead (alpha = 2, uniform weights).
     With observables=True each record also holds, from the same samples
     and weights (Benchmark section), with standard errors: <M_z^2>/N and the
     susceptibility beta_phys <M_z^2>/N, the particle number and double
@@ -81,47 +78,47 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
         step0 = step0 + su_steps
     records = []
     for step in range(step0, step0 + n_steps):
+        beta_phys = 4.0 * tau * step
+        d = desc
+        if desc.alpha == 1 and alpha_switch_beta is not None and beta_phys >= alpha_switch_beta:
+            d = dataclasses.replace(desc, alpha=2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         n_accept.zero_()
-        api.peps_sample_sweep(desc, theta, configs, seed, gsweep, S, n_accept=n_accept, status=status, out=out)
+        api.peps_sample_sweep(d, theta, configs, seed, gsweep, S, n_accept=n_accept, status=status, out=out)
         gsweep += S
-        la = out["log_abs"].cpu().numpy()
-        weights = None
-        if desc.alpha == 1:
-            w = np.exp(la - la.max())
-            weights = torch.tensor(w.reshape(S * n), device=dev)
+        la = out["log_abs"].view(S * n)
+        e = out["e_loc"].view(S * n)
+        samples = out["configs"].view(S * n, N)
+        est = api.peps_sample_stats(d, e, n, log_abs=la)
         obs = None
         if observables:
-            samples = out["configs"].view(S * n, N)
-            vals = api.peps_observables_batch(desc, samples).cpu().numpy().reshape(S, n, -1)
-            _, f_loc = api.nnn_spin_correlation(desc, theta, samples)
-            obs = (vals, f_loc.cpu().numpy().reshape(S, n))
-        dtheta, _, stats, _ = api.sr_cg_solve(desc, out["configs"].view(S * n, N), out["O"].view(S * n, nnz),
-                                              out["e_loc"].view(S * n), tau, eps, cg_iters, rtol, weights=weights,
-                                              want_g=False, theta=theta, status=status)
+            vals = api.peps_observables_batch(d, samples)
+            ost = api.peps_sample_stats(d, vals, n, log_abs=la)
+            f_mean, f_se, _ = api.nnn_spin_correlation(d, theta, samples, n_chains=n, log_abs=la)
+            obs = (ost, f_mean, f_se)
+        dtheta, _, stats, _ = api.sr_cg_solve(d, samples, out["O"].view(S * n, nnz), e, tau, eps, cg_iters, rtol,
+                                              log_abs=la, want_g=False, theta=theta, status=status)
+        dnorm = torch.linalg.vector_norm(dtheta)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         api.check(status, "cool")
-        e = out["e_loc"].cpu().numpy() / (2 * N)
-        w = np.exp(la - la.max()) if desc.alpha == 1 else np.ones_like(e)
-        chain = (w * e).sum(axis=0) / w.sum(axis=0)
-        st = stats.cpu().numpy()
-        acc = n_accept.cpu().numpy().sum(axis=0) / float(n * S)
-        rec = {"step": step, "beta_phys": 4.0 * tau * step, "E_per_site": float(st[0]) / (2 * N),
-               "E_stderr": float(chain.std(ddof=1) / np.sqrt(n)) if n > 1 else 0.0,
-               "accepted_per_sweep": {"h": float(acc[0]), "site": float(acc[1]), "v": float(acc[2])},
-               "cg_iters": int(st[2]), "cg_rel_residual": float(st[1] / st[3]) if st[3] > 0 else 0.0,
-               "dtheta_norm": float(np.linalg.norm(dtheta.cpu().numpy())), "samples_per_s": n * S / wall,
-               "gsweep": gsweep}
+        est = est.cpu().tolist()
+        st = stats.cpu().tolist()
+        acc = (n_accept.sum(dim=0).to(torch.float64) / float(n * S)).cpu().tolist()
+        rec = {"step": step, "beta_phys": beta_phys, "alpha": d.alpha,
+               "E_per_site": est[0][0] / (2 * N), "E_stderr": est[0][1] / (2 * N),
+               "accepted_per_sweep": {"h": acc[0], "site": acc[1], "v": acc[2]},
+               "cg_iters": int(st[2]), "cg_rel_residual": st[1] / st[3] if st[3] > 0 else 0.0,
+               "cg_converged": st[4] == 0.0,
+               "dtheta_norm": float(dnorm), "samples_per_s": n * S / wall, "gsweep": gsweep}
         if obs is not None:
-            vals, f_loc = obs
-            M = 2 * (desc.L1 - 1) * (desc.L2 - 1)
-            for k, name in ((1, "mz2_per_site"), (2, "n_per_site"), (3, "docc_per_site")):
-                m, se = _mean_and_stderr(vals[:, :, k] / N, w)
-                rec[name], rec[name + "_stderr"] = m, se
-            rec["chi"] = rec["beta_phys"] * rec["mz2_per_site"]
-            rec["F"], rec["F_stderr"] = _mean_and_stderr(f_loc / (2.0 * M), w)
+            ost, f_mean, f_se = obs
+            ost = ost.cpu().tolist()
+            for q, name in ((1, "mz2_per_site"), (2, "n_per_site"), (3, "docc_per_site")):
+                rec[name], rec[name + "_stderr"] = ost[q][0] / N, ost[q][1] / N
+            rec["chi"] = beta_phys * rec["mz2_per_site"]
+            rec["F"], rec["F_stderr"] = f_mean, f_se
         records.append(rec)
         if log is not None:
             log.write(json.dumps(rec) + "\n")

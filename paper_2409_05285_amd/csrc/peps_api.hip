@@ -5,10 +5,18 @@
 
 #include <vector>
 
+#include "peps_chain.hpp"
 #include "peps_common.hpp"
 #include "peps_kernels.hpp"
 
 using namespace peps;
+
+// Caller-owned instrumentation record (declared opaque in peps.h).
+struct peps_trace {
+  int capacity = 0, used = 0;
+  std::vector<hipEvent_t> a, b;
+  std::vector<int> cls;
+};
 
 namespace {
 
@@ -25,6 +33,8 @@ bool desc_ok(const peps_desc* d) {
     return false;
   }
   if (d->alpha != 1 && d->alpha != 2) return false;
+  if (d->fermionic != 0 && d->fermionic != 1) return false;
+  if (d->fermionic && d->model != PEPS_MODEL_HUBBARD) return false;
   if (d->precision != PEPS_PREC_FP64 && d->precision != PEPS_PREC_MIXED) return false;
   if (!isfinite(d->J1) || !isfinite(d->J2) || !isfinite(d->t) || !isfinite(d->U) || !isfinite(d->mu)) return false;
   return true;
@@ -42,6 +52,7 @@ Prob make_prob(const peps_desc* d) {
   P.chi = d->chi;
   P.model = d->model;
   P.alpha = d->alpha;
+  P.fermionic = d->fermionic;
   P.nb_moves = d->model == PEPS_MODEL_HEISENBERG ? 2 : 4;
   P.ns_moves = d->model == PEPS_MODEL_HEISENBERG ? 1 : 2;
   P.n_slots = P.L1 * (P.nb_moves * (P.L2 - 1) + P.ns_moves * P.L2) + (P.L1 - 1) * P.nb_moves * P.L2;
@@ -80,7 +91,7 @@ Prob make_prob(const peps_desc* d) {
     const int64_t xs = 2 * (int64_t)P.XS, cs = (int64_t)(compress_dyn_lds(P) / sizeof(double));
     P.off_X = off;   off += pad(xs > cs ? xs : cs);
   }
-  P.off_epart = off; off += pad(2 * P.L1 + 2);
+  P.off_epart = off; off += pad(epart_size(P));
   P.off_tau = off;   off += pad((int64_t)P.L2 * P.chi * P.D);
   P.off_T = off;
   if (!compress2_supported(P) && !compress_in_lds(P)) off += pad((int64_t)compress_big_T_doubles(P));
@@ -108,32 +119,19 @@ peps_status device_support(const peps_desc* d, const Prob& P) {
     if ((x) != hipSuccess) return PEPS_ERR_HIP; \
   } while (0)
 
-// Instrumentation: every launch of a kernel class bracketed by two events.
-struct ProfRec {
-  int cls;
-  hipEvent_t a, b;
-};
-bool g_prof = false;
-std::vector<ProfRec> g_recs;
-size_t g_used = 0;
-
-struct ProfScope {
+// Instrumentation: a launch bracketed by two events of the caller's trace.
+struct TraceScope {
+  peps_trace* t;
   int idx = -1;
   hipStream_t st;
-  ProfScope(int cls, hipStream_t s) : st(s) {
-    if (!g_prof) return;
-    if (g_used == g_recs.size()) {
-      ProfRec r;
-      r.cls = cls;
-      if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-      g_recs.push_back(r);
-    }
-    idx = (int)g_used++;
-    g_recs[idx].cls = cls;
-    (void)hipEventRecord(g_recs[idx].a, st);
+  TraceScope(peps_trace* t_, int cls, hipStream_t s) : t(t_), st(s) {
+    if (!t || t->used >= t->capacity) return;
+    idx = t->used++;
+    t->cls[idx] = cls;
+    (void)hipEventRecord(t->a[idx], st);
   }
-  ~ProfScope() {
-    if (idx >= 0) (void)hipEventRecord(g_recs[idx].b, st);
+  ~TraceScope() {
+    if (idx >= 0) (void)hipEventRecord(t->b[idx], st);
   }
 };
 
@@ -154,7 +152,7 @@ float* theta32_ptr(const Prob& P, double* ws, int64_t n) {
 
 #define TIMED(cls, call)            \
   do {                              \
-    ProfScope _ps((cls), st);       \
+    TraceScope _ts(trace, (cls), st); \
     HIP_TRY(call);                  \
   } while (0)
 
@@ -228,27 +226,36 @@ static peps_status common_checks(const peps_desc* d, Prob& P, int64_t n, const v
 }
 
 static peps_status compress_all_bots(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
-                                     int32_t* status, hipStream_t st) {
+                                     int32_t* status, peps_trace* trace, hipStream_t st) {
   for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 1, r, theta, configs, ws, status, st));
   return PEPS_OK;
 }
 
+// Measurement of every chain's configuration from its top and bottom
+// boundaries.  Mixed precision: the FP32 pass estimates each sample's
+// rounding error; the samples above the bar are measured again by the FP64
+// strip kernels (the others return at once), and their outputs rewritten.
 static peps_status measure(const Prob& P, int n, const double* theta, const float* t32, const uint8_t* configs,
                            double* ws, double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int64_t out_off,
-                           int32_t* status, hipStream_t st) {
+                           int32_t* status, peps_trace* trace, hipStream_t st) {
   const int want_e = e_loc != nullptr;
-  for (int r = 0; r < P.L1; ++r)
-    TIMED(PEPS_K_MEAS1, launch_meas1(P, n, r, theta, t32, configs, ws, O_rows, want_e, status, st));
-  if (want_e)
-    for (int r = 0; r < P.L1 - 1; ++r)
-      TIMED(PEPS_K_MEAS2, launch_meas2(P, n, r, theta, t32, configs, ws, status, st));
-  TIMED(PEPS_K_FINAL, launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, status, st));
+  for (int pass = 0; pass < (P.mixed ? 2 : 1); ++pass) {
+    for (int r = 0; r < P.L1; ++r)
+      TIMED(pass == 0 ? PEPS_K_MEAS1 : PEPS_K_FINAL,
+            launch_meas1(P, n, r, theta, t32, configs, ws, O_rows, want_e, pass, status, st));
+    if (want_e)
+      for (int r = 0; r < P.L1 - 1; ++r)
+        TIMED(pass == 0 ? PEPS_K_MEAS2 : PEPS_K_FINAL,
+              launch_meas2(P, n, r, theta, t32, configs, ws, pass, status, st));
+    TIMED(PEPS_K_FINAL,
+          launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, pass, status, st));
+  }
   return PEPS_OK;
 }
 
 peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
                             double* log_abs, int8_t* sign, double* e_loc, int32_t* status, void* ws,
-                            size_t ws_bytes, peps_stream_t stream) {
+                            size_t ws_bytes, peps_trace* trace, peps_stream_t stream) {
   Prob P;
   peps_status s = common_checks(d, P, n, theta, configs, ws, ws_bytes, PEPS_WS_EVAL);
   if (s != PEPS_OK || n == 0) return s;
@@ -256,16 +263,17 @@ peps_status peps_eval_batch(const peps_desc* d, const double* theta, int32_t n, 
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
   float* t32 = theta32_ptr(P, w, n);
+  HIP_TRY(launch_check_digits(P, n, configs, status, st));
   if (t32) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
-  s = compress_all_bots(P, n, theta, configs, w, status, st);
+  s = compress_all_bots(P, n, theta, configs, w, status, trace, st);
   if (s != PEPS_OK) return s;
-  return measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, nullptr, 0, status, st);
+  return measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, nullptr, 0, status, trace, st);
 }
 
 peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
                             double* O_rows, double* log_abs, int32_t* status, void* ws, size_t ws_bytes,
-                            peps_stream_t stream) {
+                            peps_trace* trace, peps_stream_t stream) {
   Prob P;
   peps_status s = common_checks(d, P, n, theta, configs, ws, ws_bytes, PEPS_WS_GRAD);
   if (s != PEPS_OK || n == 0) return s;
@@ -273,18 +281,19 @@ peps_status peps_grad_batch(const peps_desc* d, const double* theta, int32_t n, 
   hipStream_t st = (hipStream_t)stream;
   double* w = (double*)ws;
   float* t32 = theta32_ptr(P, w, n);
+  HIP_TRY(launch_check_digits(P, n, configs, status, st));
   if (t32) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int r = 0; r <= P.L1 - 2; ++r) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
-  s = compress_all_bots(P, n, theta, configs, w, status, st);
+  s = compress_all_bots(P, n, theta, configs, w, status, trace, st);
   if (s != PEPS_OK) return s;
-  return measure(P, n, theta, t32, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, st);
+  return measure(P, n, theta, t32, configs, w, log_abs, nullptr, nullptr, O_rows, 0, status, trace, st);
 }
 
 peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n_chains, uint8_t* configs,
                               uint64_t seed, uint64_t sweep0, uint64_t* sweep_counter, int32_t n_sweeps,
                               double* log_abs, int8_t* sign, double* e_loc, double* O_rows,
                               uint8_t* sample_configs, int32_t* n_accept, int32_t* status, void* ws,
-                              size_t ws_bytes, peps_stream_t stream) {
+                              size_t ws_bytes, peps_trace* trace, peps_stream_t stream) {
   Prob P;
   peps_status s = common_checks(d, P, n_chains, theta, configs, ws, ws_bytes, PEPS_WS_SWEEP);
   if (s != PEPS_OK || n_chains == 0) return s;
@@ -294,11 +303,12 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
   double* w = (double*)ws;
   const int n = n_chains;
   float* t32 = theta32_ptr(P, w, n);
+  HIP_TRY(launch_check_digits(P, n, configs, status, st));
   if (t32 && n_sweeps > 0) HIP_TRY(launch_theta32(P, theta, t32, st));
   for (int k = 0; k < n_sweeps; ++k) {
     const uint64_t g = sweep0 + (uint64_t)k;
     if (k == 0) {
-      s = compress_all_bots(P, n, theta, configs, w, status, st);
+      s = compress_all_bots(P, n, theta, configs, w, status, trace, st);
       if (s != PEPS_OK) return s;
     }
     for (int r = 0; r < P.L1; ++r) {
@@ -309,13 +319,13 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
       }
     }
     if (k + 1 < n_sweeps || measure_any) {
-      s = compress_all_bots(P, n, theta, configs, w, status, st);
+      s = compress_all_bots(P, n, theta, configs, w, status, trace, st);
       if (s != PEPS_OK) return s;
     }
     if (measure_any) {
       const int64_t off = (int64_t)k * n;
       s = measure(P, n, theta, t32, configs, w, log_abs, sign, e_loc, O_rows ? O_rows + off * P.nnz : nullptr, off,
-                  status, st);
+                  status, trace, st);
       if (s != PEPS_OK) return s;
       if (sample_configs)
         HIP_TRY(launch_copy_bytes(sample_configs + off * P.N, configs, (int64_t)n * P.N, st));
@@ -326,9 +336,9 @@ peps_status peps_sample_sweep(const peps_desc* d, const double* theta, int32_t n
 }
 
 peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs, const double* O_rows,
-                        const double* weights, const double* e_loc, double tau, double eps, int32_t max_iter,
-                        double rtol, double* dtheta, double* g_out, double* theta, double* stats,
-                        int32_t* status, void* ws, size_t ws_bytes, peps_stream_t stream) {
+                        const double* weights, const double* log_abs, const double* e_loc, double tau, double eps,
+                        int32_t max_iter, double rtol, double* dtheta, double* g_out, double* theta, double* stats,
+                        int32_t* status, void* ws, size_t ws_bytes, peps_trace* trace, peps_stream_t stream) {
   if (!desc_ok(d)) return PEPS_ERR_ARG;
   Prob P = make_prob(d);
   if (n_s < 1 || max_iter < 0 || max_iter > SR_MAX_ITER || !isfinite(tau) || !isfinite(eps) || eps < 0.0 ||
@@ -338,8 +348,20 @@ peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs,
   size_t need = sr_workspace_bytes(P, n_s);
   if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  TIMED(PEPS_K_SR, launch_sr(P, n_s, configs, O_rows, weights, e_loc, tau, eps, max_iter, rtol, dtheta, g_out, theta,
-                             stats, status, ws, st));
+  HIP_TRY(launch_check_digits(P, n_s, configs, status, st));
+  TIMED(PEPS_K_SR, launch_sr(P, n_s, configs, O_rows, weights, log_abs, e_loc, tau, eps, max_iter, rtol, dtheta,
+                             g_out, theta, stats, status, ws, st));
+  return PEPS_OK;
+}
+
+peps_status peps_sample_stats(const peps_desc* d, int32_t n_sweeps, int32_t n_chains, int32_t k,
+                              const double* values, const double* weights, const double* log_abs, double* out,
+                              peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  if (n_sweeps < 1 || n_chains < 1 || k < 1 || k > 4096) return PEPS_ERR_ARG;
+  if (!values || !out) return PEPS_ERR_ARG;
+  HIP_TRY(launch_sample_stats(make_prob(d), n_sweeps, n_chains, k, values, weights, log_abs, out,
+                              (hipStream_t)stream));
   return PEPS_OK;
 }
 
@@ -350,8 +372,7 @@ peps_status peps_vjp_batch(const peps_desc* d, int64_t n, const uint8_t* configs
   if (n < 1) return PEPS_ERR_ARG;
   if (!configs || !O_rows || !cot || !grad || !ws) return PEPS_ERR_ARG;
   if (ws_bytes < sr_workspace_bytes(P, n)) return PEPS_ERR_WORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
-  TIMED(PEPS_K_SR, launch_vjp(P, n, configs, O_rows, cot, grad, ws, st));
+  HIP_TRY(launch_vjp(P, n, configs, O_rows, cot, grad, ws, (hipStream_t)stream));
   return PEPS_OK;
 }
 
@@ -395,24 +416,45 @@ peps_status peps_su_absorb(const peps_desc* d, const double* theta, const double
   return PEPS_OK;
 }
 
-void peps_profile_enable(int32_t on) {
-  g_prof = on != 0;
-  g_used = 0;
+peps_trace* peps_trace_create(int32_t capacity) {
+  if (capacity < 1) return nullptr;
+  peps_trace* t = new peps_trace;
+  t->capacity = capacity;
+  t->a.assign(capacity, nullptr);
+  t->b.assign(capacity, nullptr);
+  t->cls.assign(capacity, 0);
+  for (int i = 0; i < capacity; ++i) {
+    if (hipEventCreate(&t->a[i]) != hipSuccess || hipEventCreate(&t->b[i]) != hipSuccess) {
+      peps_trace_destroy(t);
+      return nullptr;
+    }
+  }
+  return t;
 }
 
-peps_status peps_profile_read(double* ms, int64_t* launches) {
+void peps_trace_destroy(peps_trace* t) {
+  if (!t) return;
+  for (auto e : t->a)
+    if (e) (void)hipEventDestroy(e);
+  for (auto e : t->b)
+    if (e) (void)hipEventDestroy(e);
+  delete t;
+}
+
+peps_status peps_trace_read(peps_trace* t, double* ms, int64_t* launches) {
+  if (!t) return PEPS_ERR_ARG;
   peps_status s = PEPS_OK;
-  for (size_t i = 0; i < g_used; ++i) {
-    float t = 0.f;
-    if (hipEventSynchronize(g_recs[i].b) != hipSuccess || hipEventElapsedTime(&t, g_recs[i].a, g_recs[i].b) != hipSuccess) {
+  for (int i = 0; i < t->used; ++i) {
+    float v = 0.f;
+    if (hipEventSynchronize(t->b[i]) != hipSuccess || hipEventElapsedTime(&v, t->a[i], t->b[i]) != hipSuccess) {
       s = PEPS_ERR_HIP;
       continue;
     }
-    const int c = g_recs[i].cls;
-    if (ms) ms[c] += t;
+    const int c = t->cls[i];
+    if (ms) ms[c] += v;
     if (launches) launches[c] += 1;
   }
-  g_used = 0;
+  t->used = 0;
   return s;
 }
 

@@ -12,6 +12,21 @@ struct ChainWS {
   float *top32, *bot32;   // FP32 copies of the boundaries (mixed precision)
 };
 
+// Per-chain measurement record (epart), in doubles:
+//   [0, L1)            in-row local-energy terms of each row,
+//   [L1, 2 L1)         cross-row terms of each row pair,
+//   [2 L1], [2 L1 + 1] log|psi| and its sign,
+//   mixed precision only:
+//   [2 L1 + 2, 3 L1 + 2)  error estimate of the in-row terms of each row,
+//   [3 L1 + 2, 4 L1 + 2)  error estimate of the cross-row terms,
+//   [4 L1 + 2, 5 L1 + 2)  relative error estimate of each row's amplitude,
+//   [5 L1 + 2]            1 when the sample is re-measured in FP64.
+__host__ __device__ inline int epart_err1(const Prob& P) { return 2 * P.L1 + 2; }
+__host__ __device__ inline int epart_err2(const Prob& P) { return 3 * P.L1 + 2; }
+__host__ __device__ inline int epart_eta(const Prob& P) { return 4 * P.L1 + 2; }
+__host__ __device__ inline int epart_flag(const Prob& P) { return 5 * P.L1 + 2; }
+__host__ __device__ inline int epart_size(const Prob& P) { return 5 * P.L1 + 3; }
+
 __device__ inline ChainWS chain_ws(const Prob& P, double* ws, int ch) {
   double* base = ws + (size_t)ch * P.chain_stride;
   ChainWS w;

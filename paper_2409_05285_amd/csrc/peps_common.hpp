@@ -31,7 +31,23 @@ struct Prob {
   int64_t off_tau;                // Householder scalars of one compression [L2][chi*D]
   int64_t off_T;                  // panel T factors of the workspace-resident compression
   int mixed;                      // FP32 strip contractions
+  int fermionic;                  // Z2-graded parity-even tensors (odd total parity => rho = 0)
 };
+
+// Configuration digit of site i, read through a range check: a digit
+// outside [0, d^2) is read as 0 (the call's validation kernel records
+// PEPS_ERR_ARG for it), so that no kernel indexes a slice out of range.
+__host__ __device__ inline int digit_at(const Prob& P, const uint8_t* cfg, int i) {
+  const int v = cfg[i];
+  return v < P.d2 ? v : 0;
+}
+
+// Fermion-number parity of a Hubbard digit pair S = s d + s' (digit
+// s = n_up + 2 n_dn): the parity of n(s) + n(s').
+__host__ __device__ inline int digit_parity(const Prob& P, int S) {
+  const int x = (S / P.d) ^ (S % P.d);
+  return (x ^ (x >> 1)) & 1;
+}
 
 __host__ __device__ inline void leg_dims(const Prob& P, int r, int c, int& Dl, int& Du, int& Dr, int& Dd) {
   Dl = (c == 0) ? 1 : P.D;
@@ -169,8 +185,13 @@ __device__ inline double wg_sum(double v, double* red) {
   return out;
 }
 
+// Records `code` in the device status word: an error (negative code)
+// replaces "fine" (0) or a warning (positive code) and is never replaced; a
+// warning replaces only "fine".
 __device__ inline void set_status(int32_t* status, int code) {
-  if (status) atomicCAS(status, 0, code);
+  if (!status) return;
+  const int old = atomicCAS(status, 0, code);
+  if (code < 0 && old > 0) atomicCAS(status, old, code);
 }
 
 // Singular value from a column's squared norm, for ranking the columns of a

@@ -87,7 +87,7 @@ __device__ inline Absorb absorb_site(const Prob& P, int dir, int r, int c, const
                                      const int* pb) {
   Absorb ab;
   leg_dims(P, r, c, ab.Dl, ab.Du, ab.Dr, ab.Dd);
-  ab.W = theta + poffr[c] + (size_t)cfg[r * P.L2 + c] * (ab.Dl * ab.Du * ab.Dr * ab.Dd);
+  ab.W = theta + poffr[c] + (size_t)digit_at(P, cfg, r * P.L2 + c) * (ab.Dl * ab.Du * ab.Dr * ab.Dd);
   ab.A = has_prev ? bnd + ((size_t)rp * P.L2 + c) * P.TS : nullptr;
   ab.b = has_prev ? pb[c] : 1;
   ab.qd = has_prev ? (dir == 0 ? ab.Du : ab.Dd) : 1;

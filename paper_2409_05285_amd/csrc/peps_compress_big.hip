@@ -66,7 +66,7 @@ __device__ void absorb_site_to(const Prob& P, const Geo& geo, int dir, int r, in
   int Dl, Du, Dr, Dd;
   leg_dims(P, r, c, Dl, Du, Dr, Dd);
   const int i = r * P.L2 + c;
-  const double* W = theta + geo.poff[i] + (size_t)cfg[i] * (Dl * Du * Dr * Dd);
+  const double* W = theta + geo.poff[i] + (size_t)digit_at(P, cfg, i) * (Dl * Du * Dr * Dd);
   const double* A = has_prev ? bnd + ((size_t)rp * P.L2 + c) * P.TS : nullptr;
   const int a = has_prev ? geo.ba[dir][rp][c] : 1;
   const int b = has_prev ? geo.bb[dir][rp][c] : 1;

@@ -10,6 +10,11 @@
 
 namespace peps {
 
+// Mixed precision: a sample whose estimated relative error of a strip
+// amplitude, or of its local energy (against max(|E_loc|, 1)), exceeds this
+// is measured again with the FP64 strips.
+constexpr double REDO_TOL = 1.0e-5;
+
 // ---------------------------------------------------------------------------
 // Compression of one boundary row: top[r] = C(top[r-1] o M_r) (dir 0) or
 // bot[r] = C(M_r o bot[r+1]) (dir 1), for every chain.
@@ -46,7 +51,7 @@ __global__ void __launch_bounds__(NT) k_compress(Prob P, int dir, int r, const d
     int Dl, Du, Dr, Dd;
     leg_dims(P, r, c, Dl, Du, Dr, Dd);
     const int i = r * P.L2 + c;
-    const double* W = theta + geo.poff[i] + (size_t)cfg[i] * (Dl * Du * Dr * Dd);
+    const double* W = theta + geo.poff[i] + (size_t)digit_at(P, cfg, i) * (Dl * Du * Dr * Dd);
     const double* A;
     int a, q, b;
     if (has_prev) {
@@ -248,16 +253,42 @@ hipError_t launch_observables(const Prob& P, int64_t n, const uint8_t* configs, 
 }
 
 // Diagonal energy, sum of the parts, and the per-sample outputs.
+// Mixed precision: the first pass (redo = 0) also decides from the error
+// estimates of the FP32 strips whether the sample is measured again in FP64
+// (flag in the chain's record); the second pass (redo = 1) rewrites the
+// outputs of the flagged samples from their FP64 parts.
 __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
-                           double* e_loc, int64_t out_off, int want_e, int32_t* status) {
+                           double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status) {
   const int ch = blockIdx.x * blockDim.x + threadIdx.x;
   if (ch >= n) return;
-  const double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
+  double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
+  if (redo && ep[epart_flag(P)] == 0.0) return;
   const uint8_t* S = configs + (size_t)ch * P.N;
   const double la = ep[2 * P.L1];
-  if (log_abs) log_abs[out_off + ch] = la;
-  if (sign) sign[out_off + ch] = (int8_t)ep[2 * P.L1 + 1];
-  if (isnan(la) || la == INFINITY) set_status(status, PEPS_ERR_NONFINITE);   // -inf: a zero amplitude
+  if (P.mixed && !redo) {
+    // relative error estimate of the amplitudes (log|psi|, O rows) and
+    // absolute estimate of the local energy, against REDO_TOL
+    double eta = 0.0, err = 0.0, e = 0.0;
+    for (int r = 0; r < P.L1; ++r) eta = fmax(eta, ep[epart_eta(P) + r]);
+    if (want_e) {
+      for (int r = 0; r < P.L1; ++r) err += ep[epart_err1(P) + r];
+      for (int r = 0; r + 1 < P.L1; ++r) err += ep[epart_err2(P) + r];
+      for (int q = 0; q < 2 * P.L1 - 1; ++q) e += ep[q];
+    }
+    // 2: the amplitudes themselves (log|psi|, O rows) are re-measured; 1:
+    // only the local energy is (the decision for the amplitudes does not
+    // depend on which outputs the call asked for, so evaluation and
+    // gradient calls report the same log|psi|)
+    const bool amp_ok = eta <= REDO_TOL;                                   // false for NaN
+    const bool e_ok = err <= REDO_TOL * fmax(fabs(e), 1.0);
+    ep[epart_flag(P)] = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
+  }
+  const bool write_amp = !redo || ep[epart_flag(P)] == 2.0;
+  if (write_amp) {
+    if (log_abs) log_abs[out_off + ch] = la;
+    if (sign) sign[out_off + ch] = (int8_t)ep[2 * P.L1 + 1];
+    if (isnan(la) || la == INFINITY) set_status(status, PEPS_ERR_NONFINITE);   // -inf: a zero amplitude
+  }
   if (!want_e || !e_loc) return;
   double diag = 0.0;
   if (P.model == PEPS_MODEL_HEISENBERG) {
@@ -341,10 +372,101 @@ hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* t
 }
 
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
-                           double* e_loc, int64_t out_off, int want_e, int32_t* status, hipStream_t st) {
+                           double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status, hipStream_t st) {
   const int bs = 128;
   hipLaunchKernelGGL(k_finalize, dim3((n + bs - 1) / bs), dim3(bs), 0, st, P, n, configs, ws, log_abs, sign, e_loc,
-                     out_off, want_e, status);
+                     out_off, want_e, redo, status);
+  return hipGetLastError();
+}
+
+// Range check of the configuration digits of a call: any digit >= d^2
+// records PEPS_ERR_ARG (the kernels read such a digit as 0).
+__global__ void k_check_digits(int64_t nbytes, int d2, const uint8_t* __restrict__ configs, int32_t* status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nbytes; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= configs[i] >= d2;
+  if (bad) set_status(status, PEPS_ERR_ARG);
+}
+
+hipError_t launch_check_digits(const Prob& P, int64_t n, const uint8_t* configs, int32_t* status, hipStream_t st) {
+  const int64_t nbytes = n * P.N;
+  if (nbytes <= 0) return hipSuccess;
+  int64_t blocks = (nbytes + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_check_digits, dim3((unsigned)blocks), dim3(256), 0, st, nbytes, P.d2, configs, status);
+  return hipGetLastError();
+}
+
+// Weighted means and per-chain standard errors of k per-sample quantities
+// (one workgroup per quantity, fixed summation order).  Weights: explicit,
+// else |rho|^(2 - alpha) relative to the largest amplitude from log_abs,
+// else uniform.
+__global__ void __launch_bounds__(NT) k_sample_stats(Prob P, int n_sweeps, int n_chains, int k,
+                                                     const double* __restrict__ values,
+                                                     const double* __restrict__ weights,
+                                                     const double* __restrict__ log_abs, double* out) {
+  __shared__ double red[NT];
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t n_s = (int64_t)n_sweeps * n_chains;
+  const bool wgt = weights == nullptr && log_abs != nullptr && P.alpha != 2;
+  double lmax = -INFINITY;
+  if (wgt) {
+    for (int64_t i = tid; i < n_s; i += NT) lmax = fmax(lmax, log_abs[i]);
+    red[tid] = lmax;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+      __syncthreads();
+    }
+    lmax = red[0];
+    __syncthreads();
+  }
+  auto weight = [&](int64_t i) {
+    return weights ? weights[i] : (wgt ? exp((double)(2 - P.alpha) * (log_abs[i] - lmax)) : 1.0);
+  };
+  double sw = 0.0, sv = 0.0;
+  for (int64_t i = tid; i < n_s; i += NT) {
+    const double wi = weight(i);
+    sw += wi;
+    sv += wi * values[i * k + q];
+  }
+  sw = wg_sum(sw, red);
+  sv = wg_sum(sv, red);
+  const double mean = sv / sw;
+  // per-chain weighted means (thread-strided over chains), their mean and
+  // sample variance
+  double s1 = 0.0, s2 = 0.0;
+  for (int c = tid; c < n_chains; c += NT) {
+    double cw = 0.0, cv = 0.0;
+    for (int t = 0; t < n_sweeps; ++t) {
+      const int64_t i = (int64_t)t * n_chains + c;
+      const double wi = weight(i);
+      cw += wi;
+      cv += wi * values[i * k + q];
+    }
+    const double m = cv / cw;
+    s1 += m;
+    s2 += m * m;
+  }
+  s1 = wg_sum(s1, red);
+  s2 = wg_sum(s2, red);
+  if (tid == 0) {
+    out[2 * q] = mean;
+    double se = 0.0;
+    if (n_chains > 1) {
+      const double mc = s1 / n_chains;
+      const double var = fmax(s2 - n_chains * mc * mc, 0.0) / (n_chains - 1);
+      se = sqrt(var / n_chains);
+    }
+    out[2 * q + 1] = se;
+  }
+}
+
+hipError_t launch_sample_stats(const Prob& P, int n_sweeps, int n_chains, int k, const double* values,
+                               const double* weights, const double* log_abs, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sample_stats, dim3(k), dim3(NT), 0, st, P, n_sweeps, n_chains, k, values, weights, log_abs,
+                     out);
   return hipGetLastError();
 }
 

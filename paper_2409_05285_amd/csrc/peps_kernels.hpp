@@ -45,12 +45,19 @@ hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const
 hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
                          uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
                          int32_t* status, hipStream_t st);
+// Measurement kernels.  redo = 1: the FP64 pass over the samples that the
+// mixed path's first pass flagged (the others return at once).
 hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st);
+                        double* ws, double* O_rows, int want_e, int redo, int32_t* status, hipStream_t st);
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, int32_t* status, hipStream_t st);
+                        double* ws, int redo, int32_t* status, hipStream_t st);
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
-                           double* e_loc, int64_t out_off, int want_e, int32_t* status, hipStream_t st);
+                           double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status, hipStream_t st);
+// PEPS_ERR_ARG in status if a digit of configs [n][N] is >= d^2.
+hipError_t launch_check_digits(const Prob& P, int64_t n, const uint8_t* configs, int32_t* status, hipStream_t st);
+// Weighted means and standard errors of per-sample quantities.
+hipError_t launch_sample_stats(const Prob& P, int n_sweeps, int n_chains, int k, const double* values,
+                               const double* weights, const double* log_abs, double* out, hipStream_t st);
 
 // Simple update (spin-1/2 Heisenberg, J2 = 0, D <= MAX_SU_D): one Trotter
 // step of tau over the four bond groups; sqrt(lambda) absorbed into theta.
@@ -63,7 +70,7 @@ hipError_t launch_su_absorb(const Prob& P, const double* theta, const double* la
 
 size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
-                     const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
+                     const double* log_abs, const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
                      double* g_out, double* theta, double* stats, int32_t* status, void* ws, hipStream_t st);
 hipError_t launch_vjp(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* cot,
                       double* grad, void* ws, hipStream_t st);

@@ -58,18 +58,38 @@ __device__ inline double block_sum(double v, double* red) {
   return out;
 }
 
-// Weights and Ebar (single block).
-__global__ void __launch_bounds__(SR_NT) k_sr_weights(SrDev D, const double* weights) {
+// Weights and Ebar (single block).  Explicit weights when given; else
+// |rho_i|^(2 - alpha) from the log-amplitudes (relative to the largest)
+// when given and alpha != 2; else uniform.
+__global__ void __launch_bounds__(SR_NT) k_sr_weights(SrDev D, const double* weights, const double* log_abs,
+                                                       int alpha) {
   __shared__ double red[SR_NT];
   const int tid = threadIdx.x;
+  const bool from_la = weights == nullptr && log_abs != nullptr && alpha != 2;
+  double lmax = -INFINITY;
+  if (from_la) {
+    for (int64_t i = tid; i < D.n_s; i += SR_NT) lmax = fmax(lmax, log_abs[i]);
+    red[tid] = lmax;
+    __syncthreads();
+    for (int s = SR_NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+      __syncthreads();
+    }
+    lmax = red[0];
+    __syncthreads();
+  }
+  auto raw = [&](int64_t i) {
+    return weights ? weights[i] : exp((double)(2 - alpha) * (log_abs[i] - lmax));
+  };
+  const bool nonuniform = weights != nullptr || from_la;
   double ws = 0.0;
-  if (weights) {
-    for (int64_t i = tid; i < D.n_s; i += SR_NT) ws += weights[i];
+  if (nonuniform) {
+    for (int64_t i = tid; i < D.n_s; i += SR_NT) ws += raw(i);
     ws = block_sum(ws, red);
   }
   double es = 0.0;
   for (int64_t i = tid; i < D.n_s; i += SR_NT) {
-    double wi = weights ? weights[i] / ws : 1.0 / (double)D.n_s;
+    double wi = nonuniform ? raw(i) / ws : 1.0 / (double)D.n_s;
     D.w[i] = wi;
     es += wi * D.e[i];
   }
@@ -111,7 +131,8 @@ __global__ void __launch_bounds__(SR_NT) k_sr_gather(SrDev D, const double* v, i
   const int nr = D.n_s - row0 < GR ? (int)(D.n_s - row0) : GR;
   for (int q = tid; q < GR * D.N; q += SR_NT) {
     const int r = q / D.N, st = q % D.N;
-    const int S = r < nr ? D.configs[(row0 + r) * D.N + st] : 0;
+    const int Sv = r < nr ? D.configs[(row0 + r) * D.N + st] : 0;
+    const int S = Sv < D.d2 ? Sv : 0;   // range-checked digit (see k_check_digits)
     vb[r][st] = D.spoff[st] + S * D.sbs[st] - D.soff[st];
   }
   for (int st = tid; st < D.N; st += SR_NT) soff[st] = D.soff[st];
@@ -327,16 +348,22 @@ __global__ void __launch_bounds__(SR_NT) k_sr_direction(SrDev D, int it, double 
   }
 }
 
-// stats: Ebar, ||r||, iterations, ||b||.
-__global__ void k_sr_stats(SrDev D, int max_iter, double* stats, int32_t* status) {
+// stats: Ebar, ||r||, iterations, ||b||, and 1 when max_iter iterations
+// ended above the residual bar (also a warning in the status word).
+__global__ void k_sr_stats(SrDev D, int max_iter, double rtol, double* stats, int32_t* status) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int it = 0;
   while (it < max_iter && D.scal[it * 4 + 1] == 0.0) ++it;
+  const double rn = sqrt(D.scal[it * 4 + 0]);
+  const bool broke = D.misc[4] != 0.0;
+  const bool not_conv = max_iter > 0 && !broke && it >= max_iter && !(rn <= rtol * D.misc[1]);
   stats[0] = D.misc[0];
-  stats[1] = sqrt(D.scal[it * 4 + 0]);
+  stats[1] = rn;
   stats[2] = (double)it;
   stats[3] = D.misc[1];
+  stats[4] = not_conv ? 1.0 : 0.0;
   if (!isfinite(D.misc[0]) || !isfinite(D.misc[1])) set_status(status, PEPS_ERR_NONFINITE);
+  if (not_conv) set_status(status, PEPS_WARN_CG_NOT_CONVERGED);
 }
 
 // theta += dtheta unless the solve broke down.
@@ -432,7 +459,7 @@ size_t sr_workspace_bytes(const Prob& P, int64_t n_s) {
 }
 
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
-                     const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
+                     const double* log_abs, const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
                      double* g_out, double* theta, double* stats, int32_t* status, void* ws, hipStream_t st) {
   SrDev D;
   size_t b = 0;
@@ -445,7 +472,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
   const int cb = (int)((P.nnz + SR_NT - 1) / SR_NT);
   hipLaunchKernelGGL(k_sr_colmap, dim3(P.N < 1024 ? P.N : 1024), dim3(256), 0, st, P, (int32_t*)D.base,
                      (int32_t*)D.bsz, (int32_t*)D.site, (int32_t*)D.soff, (int32_t*)D.spoff, (int32_t*)D.sbs);
-  hipLaunchKernelGGL(k_sr_weights, dim3(1), dim3(SR_NT), 0, st, D, weights);
+  hipLaunchKernelGGL(k_sr_weights, dim3(1), dim3(SR_NT), 0, st, D, weights, log_abs, P.alpha);
   auto scatter = [&](int mode, int it) {
     if (P.d2 == 4)
       hipLaunchKernelGGL(k_sr_scatter<4>, dim3(cb, D.n_chunks), dim3(SR_NT), 0, st, D, mode, it);
@@ -464,7 +491,7 @@ hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const d
     hipLaunchKernelGGL(k_sr_update, dim3(D.n_red), dim3(SR_NT), 0, st, D, it, status);
     hipLaunchKernelGGL(k_sr_direction, dim3(D.n_red), dim3(SR_NT), 0, st, D, it, rtol, max_iter);
   }
-  hipLaunchKernelGGL(k_sr_stats, dim3(1), dim3(64), 0, st, D, max_iter, stats, status);
+  hipLaunchKernelGGL(k_sr_stats, dim3(1), dim3(64), 0, st, D, max_iter, rtol, stats, status);
   if (theta) hipLaunchKernelGGL(k_sr_apply, dim3(D.n_red), dim3(SR_NT), 0, st, D, theta);
   return hipGetLastError();
 }

@@ -12,6 +12,8 @@
 // formed in FP64 from the FP32 contraction results and those exponents.
 #include <math.h>
 
+#include <type_traits>
+
 #include "peps_chain.hpp"
 #include "peps_kernels.hpp"
 
@@ -67,6 +69,7 @@ struct StripShared {
   float wmax[NWAVE];
   int Re[MAX_L + 1];   // exponents of the right environments
   int Rs[MAX_L + 1];
+  int odd;             // fermionic tensors: the configuration has odd total parity
 };
 
 template <typename T>
@@ -76,9 +79,57 @@ __device__ inline void strip_prologue(const Prob& P, StripShared<T>& sh, const u
     build_geo(P, sh.geo);
     sh.one = T(1);
   }
-  for (int i = tid; i < P.N; i += NT) sh.S[i] = cfg[i];
+  for (int i = tid; i < P.N; i += NT) sh.S[i] = (uint8_t)digit_at(P, cfg, i);
   __syncthreads();
+  if (P.fermionic) {
+    // Z2-graded parity-even tensors: an odd total parity means rho = 0
+    // exactly, decided here in integer arithmetic
+    if (tid == 0) {
+      int par = 0;
+      for (int i = 0; i < P.N; ++i) par ^= digit_parity(P, sh.S[i]);
+      sh.odd = par;
+    }
+    __syncthreads();
+  } else if (tid == 0) {
+    sh.odd = 0;
+  }
 }
+
+// Error bookkeeping of the FP32 strips (mixed precision).  The strip
+// amplitude rho is formed once from the right environments; the left pass
+// forms it again at every column cut c as <L_c, R_{c+1}>, in a different
+// rounding order.  eta = max over the cuts of |rho_c / rho - 1| and of
+// u32 * sum|L_c R_{c+1}| / |sum L_c R_{c+1}| (the cancellation of the last
+// dot) estimates the relative error of rho and of the environments.  A local
+// energy term coef * rho(S') / rho adds |coef| (|rho(S')| + sum|tB R|) / |rho|
+// to `mag`; the row's error estimate is ERR_SAFETY (u32 + eta) mag.
+constexpr double U32 = 0x1.0p-24;
+constexpr double ERR_SAFETY = 4.0;
+
+struct ErrAcc {
+  double eta = 0.0, mag = 0.0;
+};
+
+// sum x_i y_i and sum |x_i y_i| (in FP64), identical on every thread.
+template <typename T>
+__device__ inline void wg_dot_abs(const T* x, const T* y, int n, double* red, double& dot, double& adot) {
+  double s = 0.0, a = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double p = (double)x[i] * (double)y[i];
+    s += p;
+    a += fabs(p);
+  }
+  dot = wg_sum(s, red);
+  adot = wg_sum(a, red);
+}
+
+__device__ inline void err_cut(ErrAcc& ea, double d, double ad, int dE, double rho, int rhoE) {
+  const double q = tracked_ratio(d, dE, rho, rhoE);
+  const double kap = d != 0.0 ? ad / fabs(d) : INFINITY;
+  ea.eta = fmax(ea.eta, fmax(fabs(q - 1.0), U32 * kap));
+}
+
+__device__ inline double err_row(const ErrAcc& ea) { return ERR_SAFETY * (U32 + ea.eta) * ea.mag; }
 
 // Scratch tensors of a strip kernel inside the chain workspace.
 template <typename T>
@@ -199,6 +250,10 @@ __global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restric
   strip_prologue(P, sh, cfg);
   build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
   __syncthreads();
+  if (sh.odd) {   // fermionic tensors, odd total parity: rho = 0, the chain cannot move
+    set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
+    return;
+  }
   const StripBufs<T> b = strip_bufs<T>(P, w);
   uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
@@ -300,6 +355,10 @@ __global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restric
   strip_prologue(P, sh, cfg);
   build_strip<T>(P, sh.geo, w, r, r + 2, &sh.one, sh.sc);
   __syncthreads();
+  if (sh.odd) {   // fermionic tensors, odd total parity: rho = 0, the chain cannot move
+    set_status(status, PEPS_ERR_ZERO_AMPLITUDE);
+    return;
+  }
   const StripBufs<T> b = strip_bufs<T>(P, w);
   uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
@@ -353,21 +412,27 @@ __global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restric
 // [2 L1] log|psi|, [2 L1 + 1] sign.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
-                                              double* ws, double* O_rows, int want_e, int32_t* status) {
+                                              double* ws, double* O_rows, int want_e, int redo, int32_t* status) {
   using PR = Prec<T>;
+  constexpr bool kErr = std::is_same<T, float>::value;
   __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
   ChainWS w = chain_ws(P, ws, ch);
+  if (redo && w.epart[epart_flag(P)] == 0.0) return;   // FP64 pass: flagged chains only
   strip_prologue(P, sh, configs + (size_t)ch * P.N);
   build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
   __syncthreads();
   const StripBufs<T> b = strip_bufs<T>(P, w);
   const uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
-  right_envs1(P, sh, theta, b, r);
-  const double rho = (double)b.R[0];
-  const int rhoE = sh.Re[0];
+  double rho = 0.0;
+  int rhoE = 0;
+  if (!sh.odd) {
+    right_envs1(P, sh, theta, b, r);
+    rho = (double)b.R[0];
+    rhoE = sh.Re[0];
+  }
   if (rho == 0.0 || !isfinite(rho)) {
     // a zero amplitude has log|psi| = -inf (sign 0); its local energy and O
     // row are undefined
@@ -375,6 +440,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
     if (tid == 0) {
       w.epart[r] = NAN;
       if (r == P.L1 - 1) { w.epart[2 * P.L1] = rho == 0.0 ? -INFINITY : NAN; w.epart[2 * P.L1 + 1] = 0.0; }
+      if (kErr) { w.epart[epart_err1(P) + r] = NAN; w.epart[epart_eta(P) + r] = NAN; }
     }
     return;
   }
@@ -384,6 +450,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
     w.epart[2 * P.L1 + 1] = rho > 0.0 ? 1.0 : -1.0;
   }
   double e = 0.0;
+  ErrAcc ea;
   double* Orow = O_rows ? O_rows + (size_t)ch * P.nnz : nullptr;
   const double inv = 1.0 / rho;
   const T* Lc = &sh.one;
@@ -408,17 +475,39 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
         if (!bond_proposal(P, S[i], S[i + 1], k, ni, nj)) continue;
         const Env eA = lstep1_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni);
         const Env eB = lstep1_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, nj);
-        const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env1_size(P, sh.sc, r, c + 1), sh.red);
-        e += bond_coeff(P, S, i, i + 1, k, P.J1) * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
+        const T* Rn = b.R + (size_t)(c + 2) * P.ES;
+        const int nE = eB.E + sh.Re[c + 2];
+        const double coef = bond_coeff(P, S, i, i + 1, k, P.J1);
+        if (kErr) {
+          double rn, arn;
+          wg_dot_abs<T>(b.tB, Rn, env1_size(P, sh.sc, r, c + 1), sh.red, rn, arn);
+          const double Rk = tracked_ratio(rn, nE, rho, rhoE);
+          e += coef * Rk;
+          ea.mag += fabs(coef) * (fabs(Rk) + fabs(tracked_ratio(arn, nE, rho, rhoE)));
+        } else {
+          const double rn = wg_dot<T>(b.tB, Rn, env1_size(P, sh.sc, r, c + 1), sh.red);
+          e += coef * tracked_ratio(rn, nE, rho, rhoE);
+        }
       }
     }
     if (c < P.L2 - 1) {
       eL = lstep1_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i]);
       Lc = Lb[cur];
       cur ^= 1;
+      if (kErr) {
+        double d, ad;
+        wg_dot_abs<T>(Lc, b.R + (size_t)(c + 1) * P.ES, env1_size(P, sh.sc, r, c), sh.red, d, ad);
+        err_cut(ea, d, ad, eL.E + sh.Re[c + 1], rho, rhoE);
+      }
     }
   }
-  if (tid == 0) w.epart[r] = e;
+  if (tid == 0) {
+    w.epart[r] = e;
+    if (kErr) {
+      w.epart[epart_err1(P) + r] = err_row(ea);
+      w.epart[epart_eta(P) + r] = ERR_SAFETY * (U32 + ea.eta);
+    }
+  }
 }
 
 // Cross-row local-energy terms between rows r and r+1 (two-row strip):
@@ -426,26 +515,49 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
 // the spin exchange on next-nearest-neighbour bonds when J2 != 0.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
-                                              double* ws, int32_t* status) {
+                                              double* ws, int redo, int32_t* status) {
+  constexpr bool kErr = std::is_same<T, float>::value;
   __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
   ChainWS w = chain_ws(P, ws, ch);
+  if (redo && w.epart[epart_flag(P)] == 0.0) return;   // FP64 pass: flagged chains only
   strip_prologue(P, sh, configs + (size_t)ch * P.N);
   build_strip<T>(P, sh.geo, w, r, r + 2, &sh.one, sh.sc);
   __syncthreads();
   const StripBufs<T> b = strip_bufs<T>(P, w);
   const uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
-  right_envs2(P, sh, theta, b, r);
-  const double rho = (double)b.R[0];
-  const int rhoE = sh.Re[0];
+  double rho = 0.0;
+  int rhoE = 0;
+  if (!sh.odd) {
+    right_envs2(P, sh, theta, b, r);
+    rho = (double)b.R[0];
+    rhoE = sh.Re[0];
+  }
   if (rho == 0.0 || !isfinite(rho)) {
     set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
-    if (tid == 0) w.epart[P.L1 + r] = NAN;
+    if (tid == 0) {
+      w.epart[P.L1 + r] = NAN;
+      if (kErr) w.epart[epart_err2(P) + r] = NAN;
+    }
     return;
   }
   double e = 0.0;
+  ErrAcc ea;
+  // one local-energy term coef * rho(S') / rho from the environment tX of
+  // the modified columns and the right environment Rn
+  auto term = [&](double coef, const T* tX, const T* Rn, int n, int nE) {
+    if (kErr) {
+      double rn, arn;
+      wg_dot_abs<T>(tX, Rn, n, sh.red, rn, arn);
+      const double Rk = tracked_ratio(rn, nE, rho, rhoE);
+      e += coef * Rk;
+      ea.mag += fabs(coef) * (fabs(Rk) + fabs(tracked_ratio(arn, nE, rho, rhoE)));
+    } else {
+      e += coef * tracked_ratio(wg_dot<T>(tX, Rn, n, sh.red), nE, rho, rhoE);
+    }
+  };
   const T* Lc = &sh.one;
   Env eL{0, 0};
   int cur = 0;
@@ -455,8 +567,8 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
       int ni, nj;
       if (!bond_proposal(P, S[i], S[j], k, ni, nj)) continue;
       const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, ni, nj);
-      const double rn = wg_dot<T>(b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red);
-      e += bond_coeff(P, S, i, j, k, P.J1) * tracked_ratio(rn, eA.E + sh.Re[c + 1], rho, rhoE);
+      term(bond_coeff(P, S, i, j, k, P.J1), b.tA, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c),
+           eA.E + sh.Re[c + 1]);
     }
     if (P.J2 != 0.0 && c < P.L2 - 1) {
       // spin exchange on the bonds (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c), ket
@@ -471,8 +583,7 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
           if (orient == 0) { s1c = na; s2n = nb; } else { s1n = na; s2c = nb; }
           const Env eA = lstep2_t(P, sh, b, b.tA, Lc, eL, theta, r, c, s1c, s2c);
           const Env eB = lstep2_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, s1n, s2n);
-          const double rn = wg_dot<T>(b.tB, b.R + (size_t)(c + 2) * P.ES, env2_size(P, sh.sc, r, c + 1), sh.red);
-          e += 0.5 * P.J2 * tracked_ratio(rn, eB.E + sh.Re[c + 2], rho, rhoE);
+          term(0.5 * P.J2, b.tB, b.R + (size_t)(c + 2) * P.ES, env2_size(P, sh.sc, r, c + 1), eB.E + sh.Re[c + 2]);
         }
       }
     }
@@ -480,9 +591,17 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
       eL = lstep2_t(P, sh, b, Lb[cur], Lc, eL, theta, r, c, S[i], S[j]);
       Lc = Lb[cur];
       cur ^= 1;
+      if (kErr) {
+        double d, ad;
+        wg_dot_abs<T>(Lc, b.R + (size_t)(c + 1) * P.ES, env2_size(P, sh.sc, r, c), sh.red, d, ad);
+        err_cut(ea, d, ad, eL.E + sh.Re[c + 1], rho, rhoE);
+      }
     }
   }
-  if (tid == 0) w.epart[P.L1 + r] = e;
+  if (tid == 0) {
+    w.epart[P.L1 + r] = e;
+    if (kErr) w.epart[epart_err2(P) + r] = err_row(ea);
+  }
 }
 
 // FP32 copy of theta for the mixed-precision strips.
@@ -550,20 +669,21 @@ hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const
 }
 
 hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st) {
-  if (P.mixed)
-    hipLaunchKernelGGL(k_meas1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, O_rows, want_e, status);
+                        double* ws, double* O_rows, int want_e, int redo, int32_t* status, hipStream_t st) {
+  if (P.mixed && !redo)
+    hipLaunchKernelGGL(k_meas1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, O_rows, want_e, 0, status);
   else
-    hipLaunchKernelGGL(k_meas1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, status);
+    hipLaunchKernelGGL(k_meas1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, redo,
+                       status);
   return hipGetLastError();
 }
 
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, int32_t* status, hipStream_t st) {
-  if (P.mixed)
-    hipLaunchKernelGGL(k_meas2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, status);
+                        double* ws, int redo, int32_t* status, hipStream_t st) {
+  if (P.mixed && !redo)
+    hipLaunchKernelGGL(k_meas2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, 0, status);
   else
-    hipLaunchKernelGGL(k_meas2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, status);
+    hipLaunchKernelGGL(k_meas2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, redo, status);
   return hipGetLastError();
 }
 

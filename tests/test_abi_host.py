@@ -58,24 +58,24 @@ def test_workspace_and_errors():
     assert LIB.peps_status_string(-6) == b"zero strip amplitude for a sample"
     # device entry points reject bad descriptors before touching any pointer
     bd = bad.c()
-    assert LIB.peps_eval_batch(ctypes.byref(bd), None, 1, None, None, None, None, None, None, 0, None) == -1
+    assert LIB.peps_eval_batch(ctypes.byref(bd), None, 1, None, None, None, None, None, None, 0, None, None) == -1
     # a valid call with n = 0 is a no-op that needs no device
     ok = desc.c()
-    assert LIB.peps_eval_batch(ctypes.byref(ok), None, 0, None, None, None, None, None, None, 0, None) == 0
+    assert LIB.peps_eval_batch(ctypes.byref(ok), None, 0, None, None, None, None, None, None, 0, None, None) == 0
     # shapes beyond the compiled limits (chi * D > 512, or chi > 255) are refused
     big = p.Desc(4, 4, 8, 72).c()
-    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None) == -2
+    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None, None) == -2
     big = p.Desc(4, 4, 1, 256).c()
-    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None) == -2
+    assert LIB.peps_eval_batch(ctypes.byref(big), None, 1, None, None, None, None, None, None, 0, None, None) == -2
     # chi * D = 512 is within them: with n = 0 the call is a no-op
     edge = p.Desc(4, 4, 8, 64).c()
-    assert LIB.peps_eval_batch(ctypes.byref(edge), None, 0, None, None, None, None, None, None, 0, None) == 0
+    assert LIB.peps_eval_batch(ctypes.byref(edge), None, 0, None, None, None, None, None, None, 0, None, None) == 0
     # the Hubbard model (d = 4) is accepted: with n = 0 the call is a no-op
     hub = p.Desc(2, 2, 2, 4, d=4, model=1).c()
-    assert LIB.peps_eval_batch(ctypes.byref(hub), None, 0, None, None, None, None, None, None, 0, None) == 0
+    assert LIB.peps_eval_batch(ctypes.byref(hub), None, 0, None, None, None, None, None, None, 0, None, None) == 0
     # workspace too small
     assert LIB.peps_eval_batch(ctypes.byref(ok), ctypes.c_void_p(8), 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                               ctypes.c_void_p(8), None, None, ctypes.c_void_p(8), 16, None) == -4
+                               ctypes.c_void_p(8), None, None, ctypes.c_void_p(8), 16, None, None) == -4
 
 
 def test_simple_update_entry_points_refuse_unsupported_cases():
@@ -99,3 +99,26 @@ def test_simple_update_entry_points_refuse_unsupported_cases():
     assert LIB.peps_simple_update(ctypes.byref(c), ctypes.c_void_p(8), ctypes.c_void_p(8), 0.01, 1, None,
                                   ctypes.c_void_p(8), 16, None) == -4
     assert LIB.peps_simple_update(ctypes.byref(c), None, None, float("nan"), 1, None, None, 0, None) == -1
+
+
+def test_binding_refuses_out_of_range_digits_and_bad_fermionic_flag():
+    """Configuration digits must lie in [0, d^2): the binding refuses others
+    before any launch (the device kernels check as well).  The fermionic
+    flag is 0 or 1 and only for the Hubbard model."""
+    import torch
+
+    import paper_2409_05285_amd as p
+    desc = p.Desc(4, 4, 2, 4)
+    th = torch.zeros(p.peps_param_count(desc), dtype=torch.float64)
+    cfg = torch.zeros((2, 16), dtype=torch.uint8)
+    cfg[1, 3] = 4
+    with pytest.raises(ValueError):
+        p.peps_eval_batch(desc, th, cfg)
+    hub = p.Desc(4, 4, 2, 4, d=4, model=1)
+    cfg[1, 3] = 16
+    with pytest.raises(ValueError):
+        p.peps_grad_batch(hub, torch.zeros(p.peps_param_count(hub), dtype=torch.float64), cfg)
+    assert p.peps_param_count(p.Desc(4, 4, 2, 4, d=4, model=1, fermionic=1)) > 0
+    for bad in (p.Desc(4, 4, 2, 4, fermionic=1), p.Desc(4, 4, 2, 4, d=4, model=1, fermionic=2)):
+        with pytest.raises(p.PepsError):
+            p.peps_param_count(bad)

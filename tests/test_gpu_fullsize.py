@@ -118,7 +118,8 @@ def test_fullsize_sr_solve_properties():
     O_d, e_d = res["O"][0], res["e_loc"][0]
     dth, g, stats, st = p.sr_cg_solve(desc, cfg_d, O_d, e_d, tau, eps, 200, 1e-10)
     torch.cuda.synchronize()
-    assert p.check(st) == 0
+    assert p.check(st) in (0, 1)   # 1: CG stopped at max_iter (reported, not an error)
+    assert (stats[4].item() == 1.0) == (p.check(st) == 1)
     Of = _dense_rows(cfg_d.cpu().numpy(), O_d.cpu().numpy())
     e = e_d.cpu().numpy()
     x, g, stats = dth.cpu().numpy(), g.cpu().numpy(), stats.cpu().numpy()
@@ -138,3 +139,46 @@ def test_fullsize_sr_solve_properties():
     assert true_res < 0.5 * bn
     # the step is a descent direction of the variational energy: g . x < 0
     assert float(g_ref @ x) < 0.0
+
+
+def test_fullsize_mixed_energy_every_sample():
+    """The mixed path's local energy, log|psi| and O rows on all 1024 samples
+    of the full-size sweep, against the FP64 path on the same configurations
+    and parameters: every sample within the mixed bar 1e-4 (E_loc relative to
+    max(|E_i|, mean |E|); O relative to the row's largest entry), not only
+    the mean.  The samples whose FP32 error estimate crossed the re-measure
+    bar equal the FP64 values bit for bit; the three worst remaining ones are
+    also checked against the oracle."""
+    import paper_2409_05285_amd as p
+    _say("full-size mixed vs fp64, every sample")
+    dev = _dev()
+    desc64, th, cfg, cfg_d, _ = _sweep(p, False)
+    descmx = p.Desc(L1, L2, D, CHI, precision=p.PREC_MIXED)
+    theta_d = torch.tensor(th, device=dev)
+    l64, s64, e64, st1 = p.peps_eval_batch(desc64, theta_d, cfg_d)
+    lmx, smx, emx, st2 = p.peps_eval_batch(descmx, theta_d, cfg_d)
+    O64, _, st3 = p.peps_grad_batch(desc64, theta_d, cfg_d)
+    Omx, _, st4 = p.peps_grad_batch(descmx, theta_d, cfg_d)
+    torch.cuda.synchronize()
+    for s in (st1, st2, st3, st4):
+        assert p.check(s) == 0
+    e64, emx = e64.cpu().numpy(), emx.cpu().numpy()
+    l64, lmx = l64.cpu().numpy(), lmx.cpu().numpy()
+    assert np.array_equal(s64.cpu().numpy(), smx.cpu().numpy())
+    scale = np.maximum(np.abs(e64), np.abs(e64).mean())
+    rel = np.abs(emx - e64) / scale
+    redone = emx == e64
+    print(f"[mixed] E_loc rel err median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} "
+          f"max {rel.max():.2e}; re-measured in FP64: {redone.mean():.3f}", flush=True)
+    assert rel.max() <= 1e-4, (int(rel.argmax()), rel.max())
+    assert np.all(np.abs(lmx - l64) <= 1e-4 * np.maximum(1.0, np.abs(l64)))
+    O64, Omx = O64.cpu().numpy(), Omx.cpu().numpy()
+    orel = np.abs(Omx - O64).max(axis=1) / np.abs(O64).max(axis=1)
+    print(f"[mixed] O rows: worst row error / row max {orel.max():.2e}", flush=True)
+    assert orel.max() <= 1e-4
+    lat = Lattice(L1, L2, D=D, chi=CHI)
+    worst = [int(i) for i in np.argsort(np.where(redone, -1.0, rel))[-3:]]
+    for i in worst:
+        m = measure.evaluate(lat, th, cfg_d[i].cpu().numpy().astype(np.int64), CHI)
+        assert abs(emx[i] - m["e_loc"]) <= 1e-4 * max(abs(m["e_loc"]), np.abs(e64).mean()), (i, emx[i], m["e_loc"])
+        assert abs(e64[i] - m["e_loc"]) <= 1e-10 * max(abs(m["e_loc"]), np.abs(e64).mean()), (i, e64[i], m["e_loc"])

@@ -68,7 +68,7 @@ def test_graph_replay_matches_eager(mixed):
     for _ in range(steps):
         _step(p, desc, eager, seed, tau, eps)
         torch.cuda.synchronize()
-        assert p.check(eager.status) == 0
+        assert p.check(eager.status) in (0, 1)   # 1: CG at its fixed iteration count
         ref.append(eager.snapshot())
     # the counter really advanced the random numbers: consecutive sweeps differ
     assert ref[-1][4] == steps
@@ -88,7 +88,7 @@ def test_graph_replay_matches_eager(mixed):
         side.mul_(1.0000001).add_(1e-9)
         p.peps_eval_batch(desc, side, g_state.configs.clone())
         torch.cuda.synchronize()
-        assert p.check(g_state.status) == 0
+        assert p.check(g_state.status) in (0, 1)
         got = g_state.snapshot()
         assert np.array_equal(got[0], ref[k][0]), k
         assert np.array_equal(got[1], ref[k][1]), k

@@ -85,7 +85,7 @@ def test_nnn_spin_correlation_by_enumeration():
     torch.cuda.synchronize()
     assert p.check(st) == 0
     w = torch.exp(2.0 * (la - la.max()))
-    F, e = p.nnn_spin_correlation(desc, theta_d, cfg_d, weights=w)
+    F, _, e = p.nnn_spin_correlation(desc, theta_d, cfg_d, weights=w.contiguous())
     rho = network.density_matrix(lat, th)
     A = hamiltonian.dense_H(lat)
     M = 2
@@ -95,5 +95,5 @@ def test_nnn_spin_correlation_by_enumeration():
     # the unweighted estimator on the diagonal configurations of |I> is 0
     diag = torch.tensor([[4 * s + s for s in sv] for sv in np.ndindex(4, 4, 4, 4)], dtype=torch.uint8, device=dev)
     th_id = torch.tensor(synth.theta_identity(2, 2, 2, 4), device=dev)
-    F0, _ = p.nnn_spin_correlation(desc, th_id, diag)
+    F0, _, _ = p.nnn_spin_correlation(desc, th_id, diag)
     assert abs(F0) <= 1e-14
