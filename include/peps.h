@@ -87,10 +87,12 @@ typedef struct {
                         with FP64 truncation / reductions / log-scales.  In the
                         mixed form every measurement (log|psi|, E_loc, O row)
                         also estimates its own rounding error from the FP32
-                        strips; a sample whose estimate exceeds 1e-5 (relative
-                        to its amplitudes, or to max(|E_loc|, 1)) is measured
-                        again with the FP64 strips, so its outputs equal the
-                        FP64 path's.  Metropolis ratios stay FP32.             */
+                        strips; a sample whose local-energy estimate exceeds
+                        5e-5 max(|E_loc|, mean |E_loc| of the call's batch)
+                        has its local energy measured again with the FP64
+                        strips, and one whose strip-amplitude estimate exceeds
+                        3e-5 (relative) every output, so those outputs equal
+                        the FP64 path's.  Metropolis ratios stay FP32.        */
   int32_t alpha;     /* sampling weight |rho|^alpha: 2, or 1 (Appendix A, Eq. A1)  */
   int32_t fermionic; /* 0: plain tensors.  1 (Hubbard only): the tensors are
                         Z2-graded and parity-even (Method section, fPEPS

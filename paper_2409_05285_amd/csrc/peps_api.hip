@@ -249,6 +249,7 @@ static peps_status measure(const Prob& P, int n, const double* theta, const floa
               launch_meas2(P, n, r, theta, t32, configs, ws, pass, status, st));
     TIMED(PEPS_K_FINAL,
           launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, pass, status, st));
+    if (P.mixed && pass == 0) TIMED(PEPS_K_FINAL, launch_redo_flags(P, n, ws, want_e, st));
   }
   return PEPS_OK;
 }

@@ -16,16 +16,20 @@ struct ChainWS {
 //   [0, L1)            in-row local-energy terms of each row,
 //   [L1, 2 L1)         cross-row terms of each row pair,
 //   [2 L1], [2 L1 + 1] log|psi| and its sign,
-//   mixed precision only:
-//   [2 L1 + 2, 3 L1 + 2)  error estimate of the in-row terms of each row,
-//   [3 L1 + 2, 4 L1 + 2)  error estimate of the cross-row terms,
-//   [4 L1 + 2, 5 L1 + 2)  relative error estimate of each row's amplitude,
-//   [5 L1 + 2]            1 when the sample is re-measured in FP64.
+//   mixed precision only, three values per row (epart_err1 + 3 r, one-row
+//   strips) and per row pair (epart_err2 + 3 r, two-row strips): the largest
+//   relative deviation of the strip amplitude recomputed at the column cuts,
+//   the largest u32-weighted cancellation of those cut dot products, and the
+//   sum over the row's local-energy terms of |coef rho(S') / rho|,
+//   [8 L1 + 2]            re-measure flag: 0 none, 1 the local energy, 2 the
+//                         amplitudes too (log|psi|, sign, O row),
+//   [8 L1 + 3]            the FP32 pass's local energy, [8 L1 + 4] its
+//                         error estimate.
 __host__ __device__ inline int epart_err1(const Prob& P) { return 2 * P.L1 + 2; }
-__host__ __device__ inline int epart_err2(const Prob& P) { return 3 * P.L1 + 2; }
-__host__ __device__ inline int epart_eta(const Prob& P) { return 4 * P.L1 + 2; }
-__host__ __device__ inline int epart_flag(const Prob& P) { return 5 * P.L1 + 2; }
-__host__ __device__ inline int epart_size(const Prob& P) { return 5 * P.L1 + 3; }
+__host__ __device__ inline int epart_err2(const Prob& P) { return 5 * P.L1 + 2; }
+__host__ __device__ inline int epart_flag(const Prob& P) { return 8 * P.L1 + 2; }
+__host__ __device__ inline int epart_e32(const Prob& P) { return 8 * P.L1 + 3; }
+__host__ __device__ inline int epart_size(const Prob& P) { return 8 * P.L1 + 5; }
 
 __device__ inline ChainWS chain_ws(const Prob& P, double* ws, int ch) {
   double* base = ws + (size_t)ch * P.chain_stride;

@@ -10,10 +10,20 @@
 
 namespace peps {
 
-// Mixed precision: a sample whose estimated relative error of a strip
-// amplitude, or of its local energy (against max(|E_loc|, 1)), exceeds this
-// is measured again with the FP64 strips.
-constexpr double REDO_TOL = 1.0e-5;
+// Mixed precision: bars of the error estimates above which a sample is
+// measured again with the FP64 strips (k_redo_flags): the relative error of
+// a one-row strip amplitude (O rows and log|psi| follow it: the O error
+// relative to the row's largest entry stayed below 2.1 times the estimate),
+// and the local-energy error against the scale of the precision bar (the
+// estimate never fell below 1.37 times the true error).  Set from measured
+// FP32 errors of the 8x8, D = 4, chi = 16 workload (two random states and a
+// cooled one, 3 x 1024 samples), for a worst remaining error near a third of
+// the mixed bar of 1e-4.
+#ifndef PEPS_AMP_TOL
+#define PEPS_AMP_TOL 3.0e-5
+#endif
+constexpr double AMP_TOL = PEPS_AMP_TOL;
+constexpr double E_TOL = 5.0e-5;
 
 // ---------------------------------------------------------------------------
 // Compression of one boundary row: top[r] = C(top[r-1] o M_r) (dir 0) or
@@ -253,10 +263,11 @@ hipError_t launch_observables(const Prob& P, int64_t n, const uint8_t* configs, 
 }
 
 // Diagonal energy, sum of the parts, and the per-sample outputs.
-// Mixed precision: the first pass (redo = 0) also decides from the error
-// estimates of the FP32 strips whether the sample is measured again in FP64
-// (flag in the chain's record); the second pass (redo = 1) rewrites the
-// outputs of the flagged samples from their FP64 parts.
+// Mixed precision: the first pass (redo = 0) also records the sample's local
+// energy and its error estimate from the FP32 strips, from which k_redo_flags
+// decides whether the sample is measured again in FP64; the second pass
+// (redo = 1) rewrites the outputs of the flagged samples from their FP64
+// parts.
 __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status) {
   const int ch = blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,24 +276,6 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
   if (redo && ep[epart_flag(P)] == 0.0) return;
   const uint8_t* S = configs + (size_t)ch * P.N;
   const double la = ep[2 * P.L1];
-  if (P.mixed && !redo) {
-    // relative error estimate of the amplitudes (log|psi|, O rows) and
-    // absolute estimate of the local energy, against REDO_TOL
-    double eta = 0.0, err = 0.0, e = 0.0;
-    for (int r = 0; r < P.L1; ++r) eta = fmax(eta, ep[epart_eta(P) + r]);
-    if (want_e) {
-      for (int r = 0; r < P.L1; ++r) err += ep[epart_err1(P) + r];
-      for (int r = 0; r + 1 < P.L1; ++r) err += ep[epart_err2(P) + r];
-      for (int q = 0; q < 2 * P.L1 - 1; ++q) e += ep[q];
-    }
-    // 2: the amplitudes themselves (log|psi|, O rows) are re-measured; 1:
-    // only the local energy is (the decision for the amplitudes does not
-    // depend on which outputs the call asked for, so evaluation and
-    // gradient calls report the same log|psi|)
-    const bool amp_ok = eta <= REDO_TOL;                                   // false for NaN
-    const bool e_ok = err <= REDO_TOL * fmax(fabs(e), 1.0);
-    ep[epart_flag(P)] = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
-  }
   const bool write_amp = !redo || ep[epart_flag(P)] == 2.0;
   if (write_amp) {
     if (log_abs) log_abs[out_off + ch] = la;
@@ -341,7 +334,59 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
   double e = diag;
   for (int q = 0; q < 2 * P.L1 - 1; ++q) e += ep[q];
   e_loc[out_off + ch] = e;
+  if (P.mixed && !redo) ep[epart_e32(P)] = e;
   if (!isfinite(e)) set_status(status, PEPS_ERR_NONFINITE);
+}
+
+// Mixed precision: which samples of the batch are measured again in FP64.
+// Per strip, e = max(dev, kap) estimates the relative rounding error of its
+// amplitude (see the FP32 strip kernels).  A sample whose one-row strips
+// have e > AMP_TOL gets flag 2 (every output re-measured).  Otherwise its
+// local-energy error is estimated as sum over the strips of max(e, u32) a
+// (a: the summed magnitudes of the strip's terms), and a sample whose
+// estimate exceeds E_TOL max(|E_loc|, mean |E_loc|) (the scale of the
+// precision bar, the mean over the batch's finite local energies) gets
+// flag 1 (local energy only).  One workgroup, fixed order.
+__global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, int want_e) {
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  double s = 0.0, c = 0.0;
+  if (want_e)
+    for (int ch = tid; ch < n; ch += NT) {
+      const double e = ws[(size_t)ch * P.chain_stride + P.off_epart + epart_e32(P)];
+      if (isfinite(e)) {
+        s += fabs(e);
+        c += 1.0;
+      }
+    }
+  s = wg_sum(s, red);
+  c = wg_sum(c, red);
+  const double mean_abs = c > 0.0 ? s / c : 0.0;
+  const double u32 = 0x1.0p-24;
+  for (int ch = tid; ch < n; ch += NT) {
+    double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
+    double amp = 0.0, err = 0.0;
+    for (int r = 0; r < P.L1; ++r) {
+      const double* q = ep + epart_err1(P) + 3 * r;
+      const double e = fmax(q[0], q[1]);
+      amp = fmax(amp, e);
+      err += fmax(e, u32) * q[2];
+    }
+    for (int r = 0; r + 1 < P.L1; ++r) {
+      const double* q = ep + epart_err2(P) + 3 * r;
+      err += fmax(fmax(q[0], q[1]), u32) * q[2];
+    }
+    if (isnan(amp)) err = NAN;
+    ep[epart_e32(P) + 1] = err;
+    const bool amp_ok = amp <= AMP_TOL;   // false for NaN
+    const bool e_ok = !want_e || err <= E_TOL * fmax(fabs(ep[epart_e32(P)]), mean_abs);
+    ep[epart_flag(P)] = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
+  }
+}
+
+hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, hipStream_t st) {
+  hipLaunchKernelGGL(k_redo_flags, dim3(1), dim3(NT), 0, st, P, n, ws, want_e);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,8 @@ hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const 
                         double* ws, int redo, int32_t* status, hipStream_t st);
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status, hipStream_t st);
+// Mixed precision: flags of the samples to measure again in FP64.
+hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, hipStream_t st);
 // PEPS_ERR_ARG in status if a digit of configs [n][N] is >= d^2.
 hipError_t launch_check_digits(const Prob& P, int64_t n, const uint8_t* configs, int32_t* status, hipStream_t st);
 // Weighted means and standard errors of per-sample quantities.

@@ -1,4 +1,5 @@
-// Strip kernels (one workgroup per chain): Metropolis moves inside a row and
+// Strip kernels (one workgroup per chain, at most 128 registers per lane so
+// that four workgroups share a CU): Metropolis moves inside a row and
 // between two rows, and the measurement of a configuration (log|psi|, local
 // energy, O rows), all from one-row and two-row strips between fixed top and
 // bottom boundary MPS.
@@ -98,17 +99,23 @@ __device__ inline void strip_prologue(const Prob& P, StripShared<T>& sh, const u
 // Error bookkeeping of the FP32 strips (mixed precision).  The strip
 // amplitude rho is formed once from the right environments; the left pass
 // forms it again at every column cut c as <L_c, R_{c+1}>, in a different
-// rounding order.  eta = max over the cuts of |rho_c / rho - 1| and of
-// u32 * sum|L_c R_{c+1}| / |sum L_c R_{c+1}| (the cancellation of the last
-// dot) estimates the relative error of rho and of the environments.  A local
-// energy term coef * rho(S') / rho adds |coef| (|rho(S')| + sum|tB R|) / |rho|
-// to `mag`; the row's error estimate is ERR_SAFETY (u32 + eta) mag.
+// rounding order.  The largest |rho_c / rho - 1| over the cuts samples the
+// rounding error of rho and of the environments (dev), and u32 times the
+// cancellation sum|L_c R_{c+1}| / |sum L_c R_{c+1}| of those dots bounds
+// the last step's share (kap).  Each local-energy term coef rho(S') / rho
+// adds its magnitude to `a`.  The three values go to the chain's record;
+// k_redo_flags turns them into an error estimate.
 constexpr double U32 = 0x1.0p-24;
-constexpr double ERR_SAFETY = 4.0;
 
 struct ErrAcc {
-  double eta = 0.0, mag = 0.0;
+  double dev = 0.0, kap = 0.0, a = 0.0;
 };
+
+__device__ inline void err_store(double* dst, const ErrAcc& ea) {
+  dst[0] = ea.dev;
+  dst[1] = ea.kap;
+  dst[2] = ea.a;
+}
 
 // sum x_i y_i and sum |x_i y_i| (in FP64), identical on every thread.
 template <typename T>
@@ -125,11 +132,11 @@ __device__ inline void wg_dot_abs(const T* x, const T* y, int n, double* red, do
 
 __device__ inline void err_cut(ErrAcc& ea, double d, double ad, int dE, double rho, int rhoE) {
   const double q = tracked_ratio(d, dE, rho, rhoE);
-  const double kap = d != 0.0 ? ad / fabs(d) : INFINITY;
-  ea.eta = fmax(ea.eta, fmax(fabs(q - 1.0), U32 * kap));
+  ea.dev = fmax(ea.dev, fabs(q - 1.0));
+  ea.kap = fmax(ea.kap, d != 0.0 ? U32 * ad / fabs(d) : INFINITY);
 }
 
-__device__ inline double err_row(const ErrAcc& ea) { return ERR_SAFETY * (U32 + ea.eta) * ea.mag; }
+__device__ inline void err_term(ErrAcc& ea, double term) { ea.a += fabs(term); }
 
 // Scratch tensors of a strip kernel inside the chain workspace.
 template <typename T>
@@ -237,7 +244,7 @@ __device__ inline Env lstep2_t(const Prob& P, StripShared<T>& sh, const StripBuf
 // ---------------------------------------------------------------------------
 // Metropolis passes inside row r: horizontal exchanges, then site moves.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
+__global__ void __launch_bounds__(NT, 4) k_moves1(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
                                                uint64_t seed, uint64_t gsweep0, const uint64_t* gctr, double* ws,
                                                int32_t* n_accept, int32_t* status) {
   // global sweep index: the host's base plus the device counter, if any
@@ -342,7 +349,7 @@ __global__ void __launch_bounds__(NT) k_moves1(Prob P, int r, const T* __restric
 
 // Metropolis vertical exchanges between rows r and r+1 (two-row strip).
 template <typename T>
-__global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
+__global__ void __launch_bounds__(NT, 4) k_moves2(Prob P, int r, const T* __restrict__ theta, uint8_t* configs,
                                                uint64_t seed, uint64_t gsweep0, const uint64_t* gctr, double* ws,
                                                int32_t* n_accept, int32_t* status) {
   // global sweep index: the host's base plus the device counter, if any
@@ -411,7 +418,7 @@ __global__ void __launch_bounds__(NT) k_moves2(Prob P, int r, const T* __restric
 // epart layout per chain: [0, L1) in-row terms, [L1, 2 L1) cross-row terms,
 // [2 L1] log|psi|, [2 L1 + 1] sign.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+__global__ void __launch_bounds__(NT, 4) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
                                               double* ws, double* O_rows, int want_e, int redo, int32_t* status) {
   using PR = Prec<T>;
   constexpr bool kErr = std::is_same<T, float>::value;
@@ -420,6 +427,8 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
   const int ch = blockIdx.x;
   ChainWS w = chain_ws(P, ws, ch);
   if (redo && w.epart[epart_flag(P)] == 0.0) return;   // FP64 pass: flagged chains only
+  // flag 1: only the local energy is re-measured (the O row stays)
+  if (redo && w.epart[epart_flag(P)] == 1.0) O_rows = nullptr;
   strip_prologue(P, sh, configs + (size_t)ch * P.N);
   build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
   __syncthreads();
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
     if (tid == 0) {
       w.epart[r] = NAN;
       if (r == P.L1 - 1) { w.epart[2 * P.L1] = rho == 0.0 ? -INFINITY : NAN; w.epart[2 * P.L1 + 1] = 0.0; }
-      if (kErr) { w.epart[epart_err1(P) + r] = NAN; w.epart[epart_eta(P) + r] = NAN; }
+      if (kErr) w.epart[epart_err1(P) + 3 * r] = NAN;
     }
     return;
   }
@@ -477,17 +486,10 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
         const Env eB = lstep1_t(P, sh, b, b.tB, b.tA, eA, theta, r, c + 1, nj);
         const T* Rn = b.R + (size_t)(c + 2) * P.ES;
         const int nE = eB.E + sh.Re[c + 2];
-        const double coef = bond_coeff(P, S, i, i + 1, k, P.J1);
-        if (kErr) {
-          double rn, arn;
-          wg_dot_abs<T>(b.tB, Rn, env1_size(P, sh.sc, r, c + 1), sh.red, rn, arn);
-          const double Rk = tracked_ratio(rn, nE, rho, rhoE);
-          e += coef * Rk;
-          ea.mag += fabs(coef) * (fabs(Rk) + fabs(tracked_ratio(arn, nE, rho, rhoE)));
-        } else {
-          const double rn = wg_dot<T>(b.tB, Rn, env1_size(P, sh.sc, r, c + 1), sh.red);
-          e += coef * tracked_ratio(rn, nE, rho, rhoE);
-        }
+        const double rn = wg_dot<T>(b.tB, Rn, env1_size(P, sh.sc, r, c + 1), sh.red);
+        const double term = bond_coeff(P, S, i, i + 1, k, P.J1) * tracked_ratio(rn, nE, rho, rhoE);
+        e += term;
+        if (kErr) err_term(ea, term);
       }
     }
     if (c < P.L2 - 1) {
@@ -503,10 +505,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
   }
   if (tid == 0) {
     w.epart[r] = e;
-    if (kErr) {
-      w.epart[epart_err1(P) + r] = err_row(ea);
-      w.epart[epart_eta(P) + r] = ERR_SAFETY * (U32 + ea.eta);
-    }
+    if (kErr) err_store(w.epart + epart_err1(P) + 3 * r, ea);
   }
 }
 
@@ -514,7 +513,7 @@ __global__ void __launch_bounds__(NT) k_meas1(Prob P, int r, const T* __restrict
 // vertical bonds (exchanges, or hops with their Jordan-Wigner signs), and
 // the spin exchange on next-nearest-neighbour bonds when J2 != 0.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+__global__ void __launch_bounds__(NT, 4) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
                                               double* ws, int redo, int32_t* status) {
   constexpr bool kErr = std::is_same<T, float>::value;
   __shared__ StripShared<T> sh;
@@ -539,7 +538,7 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
     set_status(status, rho == 0.0 ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
     if (tid == 0) {
       w.epart[P.L1 + r] = NAN;
-      if (kErr) w.epart[epart_err2(P) + r] = NAN;
+      if (kErr) w.epart[epart_err2(P) + 3 * r] = NAN;
     }
     return;
   }
@@ -548,15 +547,9 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
   // one local-energy term coef * rho(S') / rho from the environment tX of
   // the modified columns and the right environment Rn
   auto term = [&](double coef, const T* tX, const T* Rn, int n, int nE) {
-    if (kErr) {
-      double rn, arn;
-      wg_dot_abs<T>(tX, Rn, n, sh.red, rn, arn);
-      const double Rk = tracked_ratio(rn, nE, rho, rhoE);
-      e += coef * Rk;
-      ea.mag += fabs(coef) * (fabs(Rk) + fabs(tracked_ratio(arn, nE, rho, rhoE)));
-    } else {
-      e += coef * tracked_ratio(wg_dot<T>(tX, Rn, n, sh.red), nE, rho, rhoE);
-    }
+    const double t = coef * tracked_ratio(wg_dot<T>(tX, Rn, n, sh.red), nE, rho, rhoE);
+    e += t;
+    if (kErr) err_term(ea, t);
   };
   const T* Lc = &sh.one;
   Env eL{0, 0};
@@ -600,7 +593,7 @@ __global__ void __launch_bounds__(NT) k_meas2(Prob P, int r, const T* __restrict
   }
   if (tid == 0) {
     w.epart[P.L1 + r] = e;
-    if (kErr) w.epart[epart_err2(P) + r] = err_row(ea);
+    if (kErr) err_store(w.epart + epart_err2(P) + 3 * r, ea);
   }
 }
 
