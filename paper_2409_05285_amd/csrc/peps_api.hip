@@ -144,10 +144,18 @@ hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* thet
   return launch_compress_big(P, n, dir, r, theta, configs, ws, status, st);
 }
 
-// FP32 copy of theta (mixed precision), placed after the chain workspaces.
+// Mixed precision: the FP32 copy of theta, placed after the chain
+// workspaces, then the list of chains to measure again in FP64 (count and
+// up to n chain indices).
 size_t theta32_bytes(const Prob& P) { return P.mixed ? (size_t)((P.np + 63) & ~(int64_t)63) * sizeof(float) : 0; }
 float* theta32_ptr(const Prob& P, double* ws, int64_t n) {
   return P.mixed ? (float*)(ws + (size_t)n * P.chain_stride) : nullptr;
+}
+size_t redo_list_bytes(const Prob& P, int64_t n) {
+  return P.mixed ? (size_t)((n + 1) * sizeof(int32_t) + 255) & ~(size_t)255 : 0;
+}
+int32_t* redo_list_ptr(const Prob& P, double* ws, int64_t n) {
+  return P.mixed ? (int32_t*)((char*)(ws + (size_t)n * P.chain_stride) + theta32_bytes(P)) : nullptr;
 }
 
 #define TIMED(cls, call)            \
@@ -182,7 +190,7 @@ peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, si
     case PEPS_WS_EVAL:
     case PEPS_WS_GRAD:
     case PEPS_WS_SWEEP:
-      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P);
+      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P) + redo_list_bytes(P, n);
       return PEPS_OK;
     case PEPS_WS_SU:
       *bytes = (size_t)su_max_group(P) * ((su_bond_doubles(P) + 31) & ~(size_t)31) * sizeof(double);
@@ -233,23 +241,23 @@ static peps_status compress_all_bots(const Prob& P, int n, const double* theta, 
 
 // Measurement of every chain's configuration from its top and bottom
 // boundaries.  Mixed precision: the FP32 pass estimates each sample's
-// rounding error; the samples above the bar are measured again by the FP64
-// strip kernels (the others return at once), and their outputs rewritten.
+// rounding error; the samples above the bar are listed and measured again
+// by one persistent FP64 launch over their row strips, and their outputs
+// rewritten.
 static peps_status measure(const Prob& P, int n, const double* theta, const float* t32, const uint8_t* configs,
                            double* ws, double* log_abs, int8_t* sign, double* e_loc, double* O_rows, int64_t out_off,
                            int32_t* status, peps_trace* trace, hipStream_t st) {
   const int want_e = e_loc != nullptr;
-  for (int pass = 0; pass < (P.mixed ? 2 : 1); ++pass) {
-    for (int r = 0; r < P.L1; ++r)
-      TIMED(pass == 0 ? PEPS_K_MEAS1 : PEPS_K_FINAL,
-            launch_meas1(P, n, r, theta, t32, configs, ws, O_rows, want_e, pass, status, st));
-    if (want_e)
-      for (int r = 0; r < P.L1 - 1; ++r)
-        TIMED(pass == 0 ? PEPS_K_MEAS2 : PEPS_K_FINAL,
-              launch_meas2(P, n, r, theta, t32, configs, ws, pass, status, st));
-    TIMED(PEPS_K_FINAL,
-          launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, pass, status, st));
-    if (P.mixed && pass == 0) TIMED(PEPS_K_FINAL, launch_redo_flags(P, n, ws, want_e, st));
+  for (int r = 0; r < P.L1; ++r)
+    TIMED(PEPS_K_MEAS1, launch_meas1(P, n, r, theta, t32, configs, ws, O_rows, want_e, status, st));
+  if (want_e)
+    for (int r = 0; r < P.L1 - 1; ++r) TIMED(PEPS_K_MEAS2, launch_meas2(P, n, r, theta, t32, configs, ws, status, st));
+  TIMED(PEPS_K_FINAL, launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, 0, status, st));
+  if (P.mixed) {
+    int32_t* list = redo_list_ptr(P, ws, n);
+    TIMED(PEPS_K_FINAL, launch_redo_flags(P, n, ws, want_e, list, st));
+    TIMED(PEPS_K_FINAL, launch_remeasure(P, n, theta, configs, ws, list, O_rows, want_e, status, st));
+    TIMED(PEPS_K_FINAL, launch_finalize(P, n, configs, ws, log_abs, sign, e_loc, out_off, want_e, 1, status, st));
   }
   return PEPS_OK;
 }

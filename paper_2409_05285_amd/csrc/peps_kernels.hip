@@ -346,13 +346,19 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
 // (a: the summed magnitudes of the strip's terms), and a sample whose
 // estimate exceeds E_TOL max(|E_loc|, mean |E_loc|) (the scale of the
 // precision bar, the mean over the batch's finite local energies) gets
-// flag 1 (local energy only).  One workgroup, fixed order.
-__global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, int want_e) {
+// flag 1 (local energy only).  The flagged chains are listed in increasing
+// order: list[0] = count, list[1..count] = chains.  One workgroup, fixed
+// order; thread t owns a contiguous block of chains.
+__global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, int want_e, int32_t* list) {
   __shared__ double red[NT];
+  __shared__ int cnt[NT];
   const int tid = threadIdx.x;
+  const int per = (n + NT - 1) / NT;
+  const int c0 = tid * per < n ? tid * per : n;
+  const int c1 = c0 + per < n ? c0 + per : n;
   double s = 0.0, c = 0.0;
   if (want_e)
-    for (int ch = tid; ch < n; ch += NT) {
+    for (int ch = c0; ch < c1; ++ch) {
       const double e = ws[(size_t)ch * P.chain_stride + P.off_epart + epart_e32(P)];
       if (isfinite(e)) {
         s += fabs(e);
@@ -363,7 +369,8 @@ __global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, in
   c = wg_sum(c, red);
   const double mean_abs = c > 0.0 ? s / c : 0.0;
   const double u32 = 0x1.0p-24;
-  for (int ch = tid; ch < n; ch += NT) {
+  int mine = 0;
+  for (int ch = c0; ch < c1; ++ch) {
     double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
     double amp = 0.0, err = 0.0;
     for (int r = 0; r < P.L1; ++r) {
@@ -380,12 +387,27 @@ __global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, in
     ep[epart_e32(P) + 1] = err;
     const bool amp_ok = amp <= AMP_TOL;   // false for NaN
     const bool e_ok = !want_e || err <= E_TOL * fmax(fabs(ep[epart_e32(P)]), mean_abs);
-    ep[epart_flag(P)] = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
+    const double f = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
+    ep[epart_flag(P)] = f;
+    mine += f != 0.0;
   }
+  // inclusive scan of the per-thread counts, then each thread lists its own
+  cnt[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < NT; off <<= 1) {
+    const int v = tid >= off ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
+  }
+  int pos = cnt[tid] - mine;
+  for (int ch = c0; ch < c1; ++ch)
+    if (ws[(size_t)ch * P.chain_stride + P.off_epart + epart_flag(P)] != 0.0) list[1 + pos++] = ch;
+  if (tid == NT - 1) list[0] = cnt[NT - 1];
 }
 
-hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, hipStream_t st) {
-  hipLaunchKernelGGL(k_redo_flags, dim3(1), dim3(NT), 0, st, P, n, ws, want_e);
+hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, int32_t* list, hipStream_t st) {
+  hipLaunchKernelGGL(k_redo_flags, dim3(1), dim3(NT), 0, st, P, n, ws, want_e, list);
   return hipGetLastError();
 }
 

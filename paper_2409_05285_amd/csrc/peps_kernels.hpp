@@ -45,16 +45,20 @@ hipError_t launch_moves1(const Prob& P, int n, int r, const double* theta, const
 hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const float* t32, uint8_t* configs,
                          uint64_t seed, uint64_t gsweep, const uint64_t* gctr, double* ws, int32_t* n_accept,
                          int32_t* status, hipStream_t st);
-// Measurement kernels.  redo = 1: the FP64 pass over the samples that the
-// mixed path's first pass flagged (the others return at once).
+// Measurement kernels (FP32 strips when P.mixed, else FP64).
 hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, double* O_rows, int want_e, int redo, int32_t* status, hipStream_t st);
+                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st);
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, int redo, int32_t* status, hipStream_t st);
+                        double* ws, int32_t* status, hipStream_t st);
+// Mixed precision: FP64 measurement of the chains in `list` (device:
+// count, then chain indices), one persistent launch over their row strips.
+hipError_t launch_remeasure(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
+                            const int32_t* list, double* O_rows, int want_e, int32_t* status, hipStream_t st);
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status, hipStream_t st);
-// Mixed precision: flags of the samples to measure again in FP64.
-hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, hipStream_t st);
+// Mixed precision: flags of the samples to measure again in FP64, and their
+// list (list[0] = count, then the chains in increasing order).
+hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, int32_t* list, hipStream_t st);
 // PEPS_ERR_ARG in status if a digit of configs [n][N] is >= d^2.
 hipError_t launch_check_digits(const Prob& P, int64_t n, const uint8_t* configs, int32_t* status, hipStream_t st);
 // Weighted means and standard errors of per-sample quantities.

@@ -417,22 +417,18 @@ __global__ void __launch_bounds__(NT, 4) k_moves2(Prob P, int r, const T* __rest
 // Jordan-Wigner signs), and (last row) log|psi| and its sign.
 // epart layout per chain: [0, L1) in-row terms, [L1, 2 L1) cross-row terms,
 // [2 L1] log|psi|, [2 L1 + 1] sign.
+// One row of the measurement of chain ch, whose boundaries and record are in
+// w; b is the scratch of the calling workgroup.
 template <typename T>
-__global__ void __launch_bounds__(NT, 4) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
-                                              double* ws, double* O_rows, int want_e, int redo, int32_t* status) {
+__device__ void meas1_row(const Prob& P, StripShared<T>& sh, const ChainWS& w, const StripBufs<T>& b, int r,
+                          int ch, const T* __restrict__ theta, const uint8_t* configs, double* O_rows, int want_e,
+                          int32_t* status) {
   using PR = Prec<T>;
   constexpr bool kErr = std::is_same<T, float>::value;
-  __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
-  const int ch = blockIdx.x;
-  ChainWS w = chain_ws(P, ws, ch);
-  if (redo && w.epart[epart_flag(P)] == 0.0) return;   // FP64 pass: flagged chains only
-  // flag 1: only the local energy is re-measured (the O row stays)
-  if (redo && w.epart[epart_flag(P)] == 1.0) O_rows = nullptr;
   strip_prologue(P, sh, configs + (size_t)ch * P.N);
   build_strip<T>(P, sh.geo, w, r, r + 1, &sh.one, sh.sc);
   __syncthreads();
-  const StripBufs<T> b = strip_bufs<T>(P, w);
   const uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
   double rho = 0.0;
@@ -509,22 +505,26 @@ __global__ void __launch_bounds__(NT, 4) k_meas1(Prob P, int r, const T* __restr
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(NT, 4) k_meas1(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+                                                 double* ws, double* O_rows, int want_e, int32_t* status) {
+  __shared__ StripShared<T> sh;
+  const int ch = blockIdx.x;
+  const ChainWS w = chain_ws(P, ws, ch);
+  meas1_row<T>(P, sh, w, strip_bufs<T>(P, w), r, ch, theta, configs, O_rows, want_e, status);
+}
+
 // Cross-row local-energy terms between rows r and r+1 (two-row strip):
 // vertical bonds (exchanges, or hops with their Jordan-Wigner signs), and
 // the spin exchange on next-nearest-neighbour bonds when J2 != 0.
 template <typename T>
-__global__ void __launch_bounds__(NT, 4) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
-                                              double* ws, int redo, int32_t* status) {
+__device__ void meas2_row(const Prob& P, StripShared<T>& sh, const ChainWS& w, const StripBufs<T>& b, int r,
+                          int ch, const T* __restrict__ theta, const uint8_t* configs, int32_t* status) {
   constexpr bool kErr = std::is_same<T, float>::value;
-  __shared__ StripShared<T> sh;
   const int tid = threadIdx.x;
-  const int ch = blockIdx.x;
-  ChainWS w = chain_ws(P, ws, ch);
-  if (redo && w.epart[epart_flag(P)] == 0.0) return;   // FP64 pass: flagged chains only
   strip_prologue(P, sh, configs + (size_t)ch * P.N);
   build_strip<T>(P, sh.geo, w, r, r + 2, &sh.one, sh.sc);
   __syncthreads();
-  const StripBufs<T> b = strip_bufs<T>(P, w);
   const uint8_t* S = sh.S;
   T* Lb[2] = {b.Lb0, b.Lb1};
   double rho = 0.0;
@@ -597,6 +597,45 @@ __global__ void __launch_bounds__(NT, 4) k_meas2(Prob P, int r, const T* __restr
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(NT, 4) k_meas2(Prob P, int r, const T* __restrict__ theta, const uint8_t* configs,
+                                                 double* ws, int32_t* status) {
+  __shared__ StripShared<T> sh;
+  const int ch = blockIdx.x;
+  const ChainWS w = chain_ws(P, ws, ch);
+  meas2_row<T>(P, sh, w, strip_bufs<T>(P, w), r, ch, theta, configs, status);
+}
+
+// Mixed precision: the FP64 measurement of the samples k_redo_flags listed
+// (list[0] = count, list[1..count] = chains in increasing order).  Every
+// (chain, row strip) pair is one work item; the workgroups of the grid take
+// the items round-robin, item j = (chain list[1 + j % count], strip
+// j / count), strips 0..L1-1 one-row and L1.. two-row, so that a few
+// flagged chains cost a few strip latencies instead of one launch per
+// strip.  Workgroup g uses chain g's strip scratch (the grid has at most n
+// workgroups).  Flag 2 also re-measures the O row; flag 1 only the local
+// energy.
+__global__ void __launch_bounds__(NT, 4) k_remeasure(Prob P, const double* __restrict__ theta,
+                                                     const uint8_t* configs, double* ws, const int32_t* list,
+                                                     double* O_rows, int want_e, int32_t* status) {
+  __shared__ StripShared<double> sh;
+  const int count = list[0];
+  const int kinds = want_e ? 2 * P.L1 - 1 : P.L1;
+  const int64_t items = (int64_t)count * kinds;
+  const StripBufs<double> b = strip_bufs<double>(P, chain_ws(P, ws, blockIdx.x));
+  for (int64_t j = blockIdx.x; j < items; j += gridDim.x) {
+    const int ch = list[1 + (int)(j % count)];
+    const int kind = (int)(j / count);
+    const ChainWS w = chain_ws(P, ws, ch);
+    if (kind < P.L1)
+      meas1_row<double>(P, sh, w, b, kind, ch, theta, configs, w.epart[epart_flag(P)] == 2.0 ? O_rows : nullptr,
+                        want_e, status);
+    else
+      meas2_row<double>(P, sh, w, b, kind - P.L1, ch, theta, configs, status);
+    __syncthreads();
+  }
+}
+
 // FP32 copy of theta for the mixed-precision strips.
 __global__ void k_theta32(const double* __restrict__ theta, float* __restrict__ t32, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -662,21 +701,26 @@ hipError_t launch_moves2(const Prob& P, int n, int r, const double* theta, const
 }
 
 hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, double* O_rows, int want_e, int redo, int32_t* status, hipStream_t st) {
-  if (P.mixed && !redo)
-    hipLaunchKernelGGL(k_meas1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, O_rows, want_e, 0, status);
+                        double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_meas1<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, O_rows, want_e, status);
   else
-    hipLaunchKernelGGL(k_meas1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, redo,
-                       status);
+    hipLaunchKernelGGL(k_meas1<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, O_rows, want_e, status);
   return hipGetLastError();
 }
 
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
-                        double* ws, int redo, int32_t* status, hipStream_t st) {
-  if (P.mixed && !redo)
-    hipLaunchKernelGGL(k_meas2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, 0, status);
+                        double* ws, int32_t* status, hipStream_t st) {
+  if (P.mixed)
+    hipLaunchKernelGGL(k_meas2<float>, dim3(n), dim3(NT), 0, st, P, r, t32, configs, ws, status);
   else
-    hipLaunchKernelGGL(k_meas2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, redo, status);
+    hipLaunchKernelGGL(k_meas2<double>, dim3(n), dim3(NT), 0, st, P, r, theta, configs, ws, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_remeasure(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
+                            const int32_t* list, double* O_rows, int want_e, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_remeasure, dim3(n), dim3(NT), 0, st, P, theta, configs, ws, list, O_rows, want_e, status);
   return hipGetLastError();
 }
 
