@@ -214,6 +214,27 @@ peps_status sr_cg_solve(const peps_desc* desc, int64_t n_s, const uint8_t* confi
                         int32_t* status, void* ws, size_t ws_bytes, peps_trace* trace,
                         peps_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   sr_cg_solve without a workspace argument, same arguments, results and
+   kernels otherwise.  Its scratch is one fixed device array of
+   PEPS_SR_STATIC_BYTES per GPU, reserved when the library's code is loaded
+   on that GPU and held until the process ends; its address is resolved on
+   the first call on each device (with that device current).  A call whose
+   scratch need, peps_workspace_bytes(desc, n_s, PEPS_WS_SR), exceeds that
+   size returns PEPS_ERR_WORKSPACE before anything is enqueued (64 MiB holds
+   the 8x8, D = 4 solve on 204,800 samples and the 12x12, D = 6 one on 4096).
+   The call allocates and frees nothing.  Every call on one GPU uses that
+   GPU's array, which keeps the last call's contents (the solve writes every
+   entry it reads before reading it): calls that overlap on one GPU (other
+   streams, other threads) race and must be serialised by the caller. */
+enum { PEPS_SR_STATIC_BYTES = 64 << 20 };
+peps_status sr_cg_solve_noalloc(const peps_desc* desc, int64_t n_s, const uint8_t* configs,
+                                const double* O_rows, const double* weights, const double* log_abs,
+                                const double* e_loc, double tau, double eps, int32_t max_iter, double rtol,
+                                double* dtheta, double* g_out, double* theta, double* stats,
+                                int32_t* status, peps_stream_t stream);
+
 /* Sample statistics of k per-sample quantities (Method section: the
    averages of Eqs. 6-7 and in_en; Appendix A, Eq. A1 for alpha = 1):
    values [n_sweeps * n_chains][k] f64, sample index i = sweep * n_chains +

@@ -80,6 +80,10 @@ def _load():
     lib.peps_simple_update.restype = c_int32
     lib.peps_su_absorb.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.peps_su_absorb.restype = c_int32
+    lib.sr_cg_solve_noalloc.argtypes = [P, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                        c_double, c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p]
+    lib.sr_cg_solve_noalloc.restype = c_int32
     lib.peps_sample_stats.argtypes = [P, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]
     lib.peps_sample_stats.restype = c_int32
@@ -95,7 +99,9 @@ def _load():
 LIB = _load()
 EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_workspace_bytes",
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
+           "sr_cg_solve_noalloc",
            "peps_vjp_batch", "peps_observables_batch", "peps_sample_stats", "peps_simple_update",
            "peps_su_absorb", "peps_trace_create", "peps_trace_destroy", "peps_trace_read"]
+SR_STATIC_BYTES = 64 << 20   # scratch of sr_cg_solve_noalloc per GPU
 SR_NSTATS = 5   # sr_cg_solve stats: Ebar, |r|, iterations, |b|, not-converged flag
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]

@@ -315,6 +315,47 @@ def sr_cg_solve(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, we
     return dtheta, g, stats, status
 
 
+def sr_cg_solve_noalloc(desc: Desc, configs, O_rows, e_loc, tau, eps, max_iter, rtol, weights=None, want_g=True,
+                        theta=None, status=None, log_abs=None, out=None):
+    """sr_cg_solve for callers that cannot allocate device memory: the
+    library's fixed per-GPU scratch replaces the workspace.  `out` may
+    supply the output tensors dtheta [N_p], g [N_p] (or None) and stats [5]
+    as a dict, so that the call itself allocates nothing; otherwise they are
+    allocated here before the call.  Returns (dtheta, g, stats, status)."""
+    configs = _configs(desc, configs)
+    n_s = configs.shape[0]
+    if O_rows.dtype != torch.float64 or O_rows.shape != (n_s, peps_orow_count(desc)) or not O_rows.is_contiguous():
+        raise ValueError("O_rows must be contiguous float64 [n_s, nnz]")
+    if e_loc.dtype != torch.float64 or e_loc.shape != (n_s,) or not e_loc.is_contiguous():
+        raise ValueError("e_loc must be contiguous float64 [n_s]")
+    for name, v in (("weights", weights), ("log_abs", log_abs)):
+        if v is not None and (v.dtype != torch.float64 or v.shape != (n_s,) or not v.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 [n_s] tensor" % name)
+    _check_dev(configs, O_rows, e_loc, weights, theta, log_abs)
+    dev = O_rows.device
+    n_p = peps_param_count(desc)
+    if theta is not None and (theta.dtype != torch.float64 or theta.shape != (n_p,) or not theta.is_contiguous()):
+        raise ValueError("theta must be a contiguous float64 vector of length N_p")
+    out = {} if out is None else out
+    dtheta = out.get("dtheta")
+    if dtheta is None:
+        dtheta = torch.empty(n_p, dtype=torch.float64, device=dev)
+    g = out.get("g", None if not want_g else torch.empty(n_p, dtype=torch.float64, device=dev))
+    stats = out.get("stats")
+    if stats is None:
+        stats = torch.zeros(_lib.SR_NSTATS, dtype=torch.float64, device=dev)
+    for t, shape in ((dtheta, (n_p,)), (g, (n_p,)), (stats, (_lib.SR_NSTATS,))):
+        if t is not None and (t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous()
+                              or t.device != dev):
+            raise ValueError("outputs must be contiguous float64 device tensors of the documented shapes")
+    status = new_status(dev) if status is None else status
+    code = LIB.sr_cg_solve_noalloc(ctypes.byref(desc.c()), n_s, _ptr(configs), _ptr(O_rows), _ptr(weights),
+                                   _ptr(log_abs), _ptr(e_loc), float(tau), float(eps), int(max_iter), float(rtol),
+                                   _ptr(dtheta), _ptr(g), _ptr(theta), _ptr(stats), _ptr(status), _stream())
+    _raise(code, "sr_cg_solve_noalloc")
+    return dtheta, g, stats, status
+
+
 def peps_sample_stats(desc: Desc, values, n_chains, log_abs=None, weights=None):
     """Weighted means and standard errors of per-sample quantities:
     values [n_sweeps * n_chains, k] (or [n_sweeps * n_chains]) float64 in

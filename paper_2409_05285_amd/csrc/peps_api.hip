@@ -363,6 +363,26 @@ peps_status sr_cg_solve(const peps_desc* d, int64_t n_s, const uint8_t* configs,
   return PEPS_OK;
 }
 
+peps_status sr_cg_solve_noalloc(const peps_desc* d, int64_t n_s, const uint8_t* configs, const double* O_rows,
+                                const double* weights, const double* log_abs, const double* e_loc, double tau,
+                                double eps, int32_t max_iter, double rtol, double* dtheta, double* g_out,
+                                double* theta, double* stats, int32_t* status, peps_stream_t stream) {
+  if (!desc_ok(d)) return PEPS_ERR_ARG;
+  Prob P = make_prob(d);
+  if (n_s < 1 || max_iter < 0 || max_iter > SR_MAX_ITER || !isfinite(tau) || !isfinite(eps) || eps < 0.0 ||
+      !(rtol >= 0.0))
+    return PEPS_ERR_ARG;
+  if (!configs || !O_rows || !e_loc || !dtheta || !stats) return PEPS_ERR_ARG;
+  if (sr_workspace_bytes(P, n_s) > SR_STATIC_BYTES) return PEPS_ERR_WORKSPACE;
+  void* ws = sr_static_scratch();
+  if (!ws) return PEPS_ERR_HIP;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_check_digits(P, n_s, configs, status, st));
+  HIP_TRY(launch_sr(P, n_s, configs, O_rows, weights, log_abs, e_loc, tau, eps, max_iter, rtol, dtheta, g_out, theta,
+                    stats, status, ws, st));
+  return PEPS_OK;
+}
+
 peps_status peps_sample_stats(const peps_desc* d, int32_t n_sweeps, int32_t n_chains, int32_t k,
                               const double* values, const double* weights, const double* log_abs, double* out,
                               peps_stream_t stream) {

@@ -75,6 +75,11 @@ hipError_t launch_su_step(const Prob& P, double* theta, double* lam, double tau,
 hipError_t launch_su_absorb(const Prob& P, const double* theta, const double* lam, double* out, hipStream_t st);
 
 size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
+// Bytes of the fixed per-GPU scratch of sr_cg_solve_noalloc, and its device
+// address on the current device (resolved once per device; nullptr if the
+// symbol cannot be resolved).
+constexpr size_t SR_STATIC_BYTES = (size_t)PEPS_SR_STATIC_BYTES;
+void* sr_static_scratch();
 hipError_t launch_sr(const Prob& P, int64_t n_s, const uint8_t* configs, const double* O, const double* weights,
                      const double* log_abs, const double* e_loc, double tau, double eps, int max_iter, double rtol, double* dtheta,
                      double* g_out, double* theta, double* stats, int32_t* status, void* ws, hipStream_t st);

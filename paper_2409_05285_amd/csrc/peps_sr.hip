@@ -11,10 +11,36 @@
 // Every reduction has a fixed shape, so results are bit-identical run to run.
 #include <math.h>
 
+#include <mutex>
+
 #include "peps_common.hpp"
 #include "peps_kernels.hpp"
 
 namespace peps {
+
+// Scratch of the solve that allocates nothing (sr_cg_solve_noalloc): one
+// fixed device array per GPU, reserved when the code object is loaded.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[SR_STATIC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+void* sr_static_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 constexpr int SR_NT = 256;
 constexpr int YB = 128;   // blocks of the weighted mean of y

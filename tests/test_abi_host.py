@@ -122,3 +122,23 @@ def test_binding_refuses_out_of_range_digits_and_bad_fermionic_flag():
     for bad in (p.Desc(4, 4, 2, 4, fermionic=1), p.Desc(4, 4, 2, 4, d=4, model=1, fermionic=2)):
         with pytest.raises(p.PepsError):
             p.peps_param_count(bad)
+
+
+def test_noalloc_solve_refuses_sizes_beyond_its_scratch():
+    """sr_cg_solve_noalloc checks its fixed scratch (64 MiB per GPU) against
+    the workspace the problem needs and returns PEPS_ERR_WORKSPACE (-4)
+    before anything is enqueued or any device call is made; bad arguments
+    give PEPS_ERR_ARG (-1) the same way."""
+    import paper_2409_05285_amd as p
+    from paper_2409_05285_amd._lib import LIB, SR_STATIC_BYTES
+    desc = p.Desc(16, 16, 8, 64)
+    n_s = 512
+    assert p.peps_workspace_bytes(desc, n_s, 3) > SR_STATIC_BYTES
+    c = desc.c()
+    v = ctypes.c_void_p(8)
+    assert LIB.sr_cg_solve_noalloc(ctypes.byref(c), n_s, v, v, None, None, v, 0.01, 1e-4, 10, 0.0, v, None, None, v,
+                                   None, None) == -4
+    assert LIB.sr_cg_solve_noalloc(ctypes.byref(c), 0, v, v, None, None, v, 0.01, 1e-4, 10, 0.0, v, None, None, v,
+                                   None, None) == -1
+    assert LIB.sr_cg_solve_noalloc(ctypes.byref(c), n_s, None, v, None, None, v, 0.01, 1e-4, 10, 0.0, v, None, None,
+                                   v, None, None) == -1
