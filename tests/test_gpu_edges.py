@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from closed_forms import identity_closed_forms, identity_closed_forms_hubbard
 from oracle import measure, sampler
 from oracle.lattice import Lattice
 
@@ -92,40 +93,6 @@ def test_empty_batches_are_noops():
     assert torch.equal(cfg, before)
 
 
-def _closed_form_identity(L1, L2, D, J1, J2, cfg):
-    """beta = 0 state |I> (every site's slice (s, s) is 1 at bond index 0):
-    for a diagonal configuration rho = 1, and every off-diagonal term of
-    H (x) I + I (x) H^T leads to a configuration with s != s', where rho = 0,
-    so E_loc = 2 H_ss = 2 sum_<ij> J Sz_i Sz_j over nearest and next-nearest
-    neighbours; the derivative of rho by the slice entry with every leg at 0
-    is 1 and by every other entry 0 (method section, Eqs. 4, 8 and 9)."""
-    sz = 0.5 - (cfg // 2).astype(np.float64)          # digit 0 = spin up
-    sz = sz.reshape(cfg.shape[0], L1, L2)
-    h = J1 * ((sz[:, :, :-1] * sz[:, :, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, :] * sz[:, 1:, :]).sum(axis=(1, 2)))
-    h += J2 * ((sz[:, :-1, :-1] * sz[:, 1:, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, 1:] * sz[:, 1:, :-1]).sum(axis=(1, 2)))
-    row = []
-    for r in range(L1):
-        for c in range(L2):
-            n = (1 if c == 0 else D) * (1 if r == 0 else D) * (1 if c == L2 - 1 else D) * (1 if r == L1 - 1 else D)
-            blk = np.zeros(n)
-            blk[0] = 1.0
-            row.append(blk)
-    return 2.0 * h, np.concatenate(row)
-
-
-def _closed_form_identity_hubbard(L1, L2, D, U, mu, J2, cfg):
-    """The same for the Hubbard model (digit s = n_up + 2 n_dn): the
-    diagonal of H is U n_up n_dn - mu (n_up + n_dn) per site plus
-    J2 Sz_i Sz_j, Sz = (n_up - n_dn) / 2, on next-nearest neighbours."""
-    s = (cfg // 4).reshape(cfg.shape[0], L1, L2)
-    nu, nd = (s & 1).astype(np.float64), ((s >> 1) & 1).astype(np.float64)
-    sz = 0.5 * (nu - nd)
-    h = (U * nu * nd - mu * (nu + nd)).sum(axis=(1, 2))
-    h += J2 * ((sz[:, :-1, :-1] * sz[:, 1:, 1:]).sum(axis=(1, 2)) + (sz[:, :-1, 1:] * sz[:, 1:, :-1]).sum(axis=(1, 2)))
-    _, o = _closed_form_identity(L1, L2, D, 0.0, 0.0, cfg)
-    return 2.0 * h, o
-
-
 @pytest.mark.parametrize("mixed", [False, True])
 def test_beta0_identity_closed_forms_hubbard(mixed):
     """The exact beta = 0 state of the Hubbard model (d^2 = 16, 6 x 6, D = 4,
@@ -144,7 +111,7 @@ def test_beta0_identity_closed_forms_hubbard(mixed):
     O, la2, st2 = p.peps_grad_batch(desc, th, cfg_d)
     torch.cuda.synchronize()
     assert p.check(st) == 0 and p.check(st2) == 0
-    e_ref, o_ref = _closed_form_identity_hubbard(L1, L2, 4, 8.0, 4.0, 0.6, cfg)
+    e_ref, o_ref = identity_closed_forms_hubbard(L1, L2, 4, 8.0, 4.0, 0.6, cfg)
     la, sg, el, la2, O = la.cpu().numpy(), sg.cpu().numpy(), el.cpu().numpy(), la2.cpu().numpy(), O.cpu().numpy()
     tol = 1e-4 if mixed else 1e-10
     assert np.all(np.abs(la) <= tol) and np.all(np.abs(la2) <= tol)
@@ -173,7 +140,7 @@ def test_beta0_identity_closed_forms(L1, L2, D, chi, J2, mixed):
     O, la2, st2 = p.peps_grad_batch(desc, th, cfg_d)
     torch.cuda.synchronize()
     assert p.check(st) == 0 and p.check(st2) == 0
-    e_ref, o_ref = _closed_form_identity(L1, L2, D, 1.0, J2, cfg)
+    e_ref, o_ref = identity_closed_forms(L1, L2, D, 1.0, J2, cfg)
     la, sg, el, la2, O = la.cpu().numpy(), sg.cpu().numpy(), el.cpu().numpy(), la2.cpu().numpy(), O.cpu().numpy()
     tol = 1e-4 if mixed else 1e-10
     assert np.all(np.abs(la) <= tol) and np.all(np.abs(la2) <= tol), (np.abs(la).max(), np.abs(la2).max())
@@ -203,7 +170,7 @@ def test_beta0_sr_step_closed_form(weighted):
     desc = p.Desc(L1, L2, D, 16, alpha=1 if weighted else 2)
     cfg = synth.configs_diagonal(512, N, 2, seed=59)
     n = cfg.shape[0]
-    e_ref, o_ref = _closed_form_identity(L1, L2, D, 1.0, 0.0, cfg)
+    e_ref, o_ref = identity_closed_forms(L1, L2, D, 1.0, 0.0, cfg)
     O = torch.tensor(np.ascontiguousarray(np.tile(o_ref, (n, 1))), device=dev)
     E = torch.tensor(e_ref, device=dev)
     w = torch.ones(n, dtype=torch.float64, device=dev) if weighted else None

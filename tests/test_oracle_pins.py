@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import bmps, ed, hamiltonian, measure, network, philox, sampler, sr
+from oracle import bmps, cooling, ed, hamiltonian, measure, network, philox, sampler, sr
 from oracle.lattice import MODEL_HUBBARD, Lattice
 
 # ---------------------------------------------------------------------------
@@ -871,3 +871,54 @@ def test_simple_update_gate_closed_form():
     t, s = np.exp(-tau / 4), np.exp(3 * tau / 4)
     want = np.sort(np.outer([t, t, t, s], [t, t, t, s]).ravel())
     np.testing.assert_allclose(ev, want, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The cooling loop against exact diagonalization, and the beta = 0 closed forms
+
+
+def test_cooling_loop_tracks_ed_with_exact_expectations():
+    """The oracle's cooling loop (oracle/cooling.py) with exact expectations
+    (every configuration of a 2x2 lattice weighted by |rho|^2) and an ansatz
+    complete on 2x2 (D = 16), from the identity plus N(0, 0.05^2): after n
+    SR steps of tau the energy Ebar / 2 matches the exact thermal energy of
+    the 2x2 Heisenberg model at beta_phys = 4 n tau (Eq. in_en and
+    the text before Eq. 5) within 5% + 0.003 per site at every step up to
+    beta_phys = 1, and at the last step it is far from the thermal energy at
+    2 n tau (a factor-two error in the bookkeeping would land there)."""
+    lat = Lattice(2, 2, D=16, chi=16)
+    th0 = synth.theta_identity(2, 2, 16, 2, noise=0.05, seed=101)
+    tau, steps = 0.01, 26
+    _, _, hist = cooling.cool(lat, th0, np.zeros((1, 4), dtype=np.int64), 16, 0, steps, 1, tau, 1e-10,
+                              max_iter=1000, rtol=1e-12, exact=True)
+    ev = np.linalg.eigvalsh(hamiltonian.dense_spin_H(Lattice(2, 2, D=1, chi=1)))
+    for h in hist:
+        b = h["beta_phys"]
+        e_ed = float(ed.thermal_energy(ev, b)[0]) / lat.N
+        assert abs(h["E_per_site"] - e_ed) <= 0.05 * abs(e_ed) + 3e-3, (b, h["E_per_site"], e_ed)
+    last = hist[-1]
+    e_half = float(ed.thermal_energy(ev, last["beta_phys"] / 2)[0]) / lat.N
+    e_full = float(ed.thermal_energy(ev, last["beta_phys"])[0]) / lat.N
+    assert abs(last["E_per_site"] - e_half) > 5 * (0.05 * abs(e_full) + 3e-3)
+    assert abs(last["beta_phys"] - 4 * tau * (steps - 1)) < 1e-12
+
+
+@pytest.mark.parametrize("L1,L2,D,chi,J2", [(3, 3, 2, 4, 0.0), (3, 4, 2, 4, 0.5), (4, 4, 2, 4, 0.5),
+                                            (4, 4, 3, 9, 0.0)])
+def test_identity_state_closed_forms_on_larger_lattices(L1, L2, D, chi, J2):
+    """P1 beyond 2x2: the oracle's boundary-MPS evaluation of the exact beta = 0
+    state (whose truncations are fully degenerate: one nonzero singular value
+    per cut) equals the closed forms written from the definitions alone --
+    log|psi| = 0, sign +1, E_loc = 2 H_ss, O = 1 on each site's zero-leg entry
+    of its slice and 0 elsewhere -- on diagonal configurations."""
+    from closed_forms import identity_closed_forms
+    lat = Lattice(L1, L2, D=D, chi=chi, J1=1.0, J2=J2)
+    th = synth.theta_identity(L1, L2, D, 2)
+    cfg = synth.configs_diagonal(4, lat.N, 2, seed=L1 * 10 + L2)
+    e_ref, o_ref = identity_closed_forms(L1, L2, D, 1.0, J2, cfg)
+    for i, S in enumerate(cfg):
+        ev = measure.evaluate(lat, th, S.astype(np.int64), chi)
+        assert ev["log_abs"] == pytest.approx(0.0, abs=1e-14)
+        assert ev["sign"] == 1
+        assert ev["e_loc"] == pytest.approx(e_ref[i], abs=1e-13)
+        assert np.allclose(ev["O"], o_ref, rtol=0, atol=1e-14)
