@@ -32,7 +32,12 @@ constexpr int NTB = 512;                        // threads per workgroup (two wa
 constexpr int NBMAX = 12;                       // widest panel
 constexpr int PANEL_DOUBLES = 14 * 1024;        // LDS work array: 112 KB (QR panel, Jacobi blocks, W of Q Y)
 constexpr int NWAVE_B = NTB / 64;
-constexpr double JAC_CONV_BIG = 1.0e-8;
+// A sweep whose rotations all stay below this relative size is the last
+// one.  At the deep truncation chains of this kernel (chi D up to 512, tens
+// of truncations per boundary) the reported quantities amplify the
+// orthogonality left by the last sweep, so the stop comes one quadratic
+// step later than in the small kernel.
+constexpr double JAC_CONV_BIG = 1.0e-12;
 
 // Panel width for a QR with m rows (the panel must fit the LDS array).
 __host__ __device__ inline int panel_width(int m) {
@@ -429,16 +434,16 @@ __device__ __forceinline__ int lds_sweep(double* Gl, int mg, int n1, int n2, int
       sg = group_sum(sg, lp);
       if (sg != 0.0 && sg * sg > (JAC_TOL * JAC_TOL) * (sa * sb)) {
         // Rutishauser's angle from the double angle (d = sb - sa, e = 2 sg):
-        // (c, s) parallel to ((1 + |d|/r) / 2, sign(d) e / (2 r)).  1/r is
-        // the hardware estimate (it only sets the angle, which the next
-        // sweep corrects); the normalisation uses a refined 1/sqrt, so that
-        // c^2 + s^2 = 1 to rounding.  Outside the estimate's range of
-        // d^2 + e^2 the divisions are exact.
+        // (c, s) parallel to ((1 + |d|/r) / 2, sign(d) e / (2 r)), with 1/r
+        // refined to double precision (an inexact angle leaves its error in
+        // the pair's orthogonality); the normalisation uses a refined
+        // 1/sqrt, so that c^2 + s^2 = 1 to rounding.  Outside the
+        // estimate's range of d^2 + e^2 the divisions are exact.
         const double d = sb - sa, e = 2.0 * sg;
         const double r2 = fma(d, d, e * e);
         double h, qv;
         if (r2 < 1.0e300 && r2 > 1.0e-300) {
-          const double u = __builtin_amdgcn_rsq(r2);
+          const double u = rsqrt2(r2);
           h = fma(0.5 * fabs(d), u, 0.5);
           qv = (d >= 0.0 ? 0.5 : -0.5) * e * u;
         } else {

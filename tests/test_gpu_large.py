@@ -8,13 +8,14 @@ configurations for evaluation and gradients, and one chain for a sweep,
 each recomputed by the oracle from the same seeded inputs.
 
 Bars.  Configurations, accept counts and signs bit-exact; mixed precision
-1e-4 as elsewhere.  FP64: log|psi| and E_loc 1e-9, O 1e-8 -- ten times the
-bars of the smaller lattices, because at this depth (eleven truncations of
-216 to 36 per boundary) the quantities are conditioned at that level: the
-oracle run with LAPACK's gesvd instead of gesdd for the same SVDs (both
-exact to rounding) moves E_loc by up to 9e-11 and O by up to 7e-10 on these
-samples, and a relative 1e-15 perturbation of theta moves O by 2e-10.  The
-eval test recomputes that driver spread for its first sample and prints it.
+1e-4 as elsewhere; FP64 the bars of every other lattice: log|psi| and
+E_loc 1e-10, O 1e-9.  At this depth (eleven truncations of 216 to 36 per
+boundary) these quantities are conditioned near those bars: the oracle run
+with LAPACK's gesvd instead of gesdd for the same SVDs (both exact to
+rounding) moves O by up to 7e-10 on these samples, and the eval test
+recomputes and prints that spread for its first sample.  The device's
+Jacobi therefore refines its rotation angle to full precision and stops one
+quadratic step later than the small-shape kernel.
 """
 import sys
 
@@ -84,7 +85,12 @@ def test_large_chi_eval_and_grad(mixed):
     if not mixed:
         spread = _driver_spread(lat, th, cfg[0])
         print("[oracle] gesdd vs gesvd on sample 0: log|psi| %.2e, E_loc rel %.2e, O rel %.2e" % spread, flush=True)
-    tol = 1e-4 if mixed else 1e-9
+    tol = 1e-4 if mixed else 1e-10
+    emag0 = max(np.abs(ref["e_loc"]).mean(), 1e-300)
+    print("[err] log|psi| %.2e  E_loc %.2e  O %.2e" % (
+        (np.abs(la - ref["log_abs"]) / np.maximum(1.0, np.abs(ref["log_abs"]))).max(),
+        (np.abs(el - ref["e_loc"]) / np.maximum(np.abs(ref["e_loc"]), emag0)).max(),
+        (np.abs(O - ref["O"]) / np.maximum(1.0, np.abs(ref["O"]))).max()), flush=True)
     assert np.all(np.abs(la - ref["log_abs"]) <= tol * np.maximum(1.0, np.abs(ref["log_abs"]))), (la, ref["log_abs"])
     assert np.array_equal(sg, ref["sign"])
     emag = max(np.abs(ref["e_loc"]).mean(), 1e-300)
@@ -97,7 +103,7 @@ def test_large_chi_eval_and_grad(mixed):
         worst = np.argsort(rel.ravel())[-5:]
         print("[O] worst relative errors", rel.ravel()[worst], "values", ref["O"].ravel()[worst],
               "entries", worst % O.shape[1], flush=True)
-        assert np.all(rel <= 1e-8)
+        assert np.all(rel <= 1e-9)
 
 
 def test_large_chi_sweep_bit_exact():
@@ -121,8 +127,8 @@ def test_large_chi_sweep_bit_exact():
     m = measure.evaluate(lat, th, r["S"], CHI)
     la = float(res["log_abs"].cpu().numpy()[0, 0])
     e = float(res["e_loc"].cpu().numpy()[0, 0])
-    assert abs(la - m["log_abs"]) <= 1e-9 * max(1.0, abs(m["log_abs"]))
-    assert abs(e - m["e_loc"]) <= 1e-9 * max(abs(m["e_loc"]), 1.0)
+    assert abs(la - m["log_abs"]) <= 1e-10 * max(1.0, abs(m["log_abs"]))
+    assert abs(e - m["e_loc"]) <= 1e-10 * max(abs(m["e_loc"]), 1.0)
 
 
 def test_large_chi_last_row_O_matches_central_differences():
