@@ -68,7 +68,8 @@ typedef enum {
 
 enum { PEPS_MODEL_HEISENBERG = 0, PEPS_MODEL_HUBBARD = 1 };
 enum { PEPS_PREC_FP64 = 0, PEPS_PREC_MIXED = 1 };
-enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3, PEPS_WS_SU = 4 };
+enum { PEPS_WS_EVAL = 0, PEPS_WS_GRAD = 1, PEPS_WS_SWEEP = 2, PEPS_WS_SR = 3, PEPS_WS_SU = 4,
+       PEPS_WS_MIN = 5 };
 enum { PEPS_N_MOVE_TYPES = 3 }; /* horizontal exchange, site move, vertical exchange */
 enum { PEPS_N_OBS = 4 };        /* local values per sample of peps_observables_batch */
 
@@ -124,7 +125,15 @@ int64_t peps_orow_count(const peps_desc* desc);
 int64_t peps_slot_count(const peps_desc* desc);
 
 /* Workspace bytes for `what` = PEPS_WS_EVAL / _GRAD / _SWEEP (n = number of
-   chains or samples) or PEPS_WS_SR (n = number of samples N_s). */
+   chains or samples), PEPS_WS_SR (n = number of samples N_s), PEPS_WS_SU,
+   or PEPS_WS_MIN: the smallest workspace an evaluation, gradient or sweep
+   call on n chains accepts.  The two differ only where chi * D > 64 and the
+   QR matrices do not fit on chip: the full size keeps every site's QR
+   reflectors of a boundary compression; with less (down to PEPS_WS_MIN) the
+   compression keeps only the R factors and rebuilds each site's reflectors
+   when the truncation sweep needs them (same results bit for bit, about a
+   quarter more compression time, an eighth of that memory at 16x16,
+   chi = 64, D = 8). */
 peps_status peps_workspace_bytes(const peps_desc* desc, int64_t n, int32_t what, size_t* bytes);
 
 /* Static text for a status code. */

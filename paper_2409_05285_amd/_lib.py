@@ -23,7 +23,7 @@ STATUS = {
 STATUS_HIP = -3
 MODEL_HEISENBERG, MODEL_HUBBARD = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR, WS_SU = 0, 1, 2, 3, 4
+WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR, WS_SU, WS_MIN = 0, 1, 2, 3, 4, 5
 N_OBS = 4   # peps_observables_batch: M_z, M_z^2, particle number, double occupancy
 
 

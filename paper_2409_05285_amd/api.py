@@ -92,6 +92,7 @@ class Workspace:
     def get(self, nbytes, device):
         nbytes = max(int(nbytes), 256)
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = None   # release the old buffer before the new one is taken
             self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
         return self.buf
 
@@ -116,9 +117,30 @@ def _own_ws(ws, kind, nbytes, device):
 
 def workspace_bytes(desc: Desc, n, kind):
     """Bytes of workspace a call on n chains ("sweep", "eval", "grad") or
-    n_s samples ("sr") needs."""
-    what = {"sweep": _lib.WS_SWEEP, "eval": _lib.WS_EVAL, "grad": _lib.WS_GRAD, "sr": _lib.WS_SR}[kind]
+    n_s samples ("sr") needs; "min": the smallest workspace an evaluation,
+    gradient or sweep call on n chains accepts (the large-shape compression
+    then rebuilds its QR reflectors instead of keeping them)."""
+    what = {"sweep": _lib.WS_SWEEP, "eval": _lib.WS_EVAL, "grad": _lib.WS_GRAD, "sr": _lib.WS_SR,
+            "min": _lib.WS_MIN}[kind]
     return peps_workspace_bytes(desc, n, what)
+
+
+def _chain_ws(desc, n, what, device, ws=None):
+    """The workspace of an evaluation, gradient or sweep call: the caller's
+    (at least the smallest accepted size), else the shared cache, sized for
+    the faster layout when the device has room for it and for the smallest
+    one otherwise."""
+    full = peps_workspace_bytes(desc, n, what)
+    small = peps_workspace_bytes(desc, n, _lib.WS_MIN)
+    if ws is not None:
+        return _own_ws(ws, "chain", small, device)
+    cur = _WS.get("chain")
+    have = cur.buf.numel() if cur is not None and cur.buf is not None and cur.buf.device == device else 0
+    if full > small and have < full:
+        free, _ = torch.cuda.mem_get_info(device)
+        if full - have > free - (1 << 30):
+            return _ws("chain", small, device)
+    return _ws("chain", full, device)
 
 
 def _check_dev(*ts):
@@ -198,8 +220,7 @@ def peps_eval_batch(desc: Desc, theta, configs, want_e=True, status=None, trace=
     sign = torch.empty(n, dtype=torch.int8, device=dev)
     e_loc = torch.empty(n, dtype=torch.float64, device=dev) if want_e else None
     status = new_status(dev) if status is None else status
-    nb = peps_workspace_bytes(desc, n, _lib.WS_EVAL)
-    ws = _ws("chain", nb, dev)
+    ws = _chain_ws(desc, n, _lib.WS_EVAL, dev)
     code = LIB.peps_eval_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(log_abs), _ptr(sign),
                                _ptr(e_loc), _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_eval_batch")
@@ -216,7 +237,7 @@ def peps_grad_batch(desc: Desc, theta, configs, status=None, trace=None):
     O = torch.empty((n, peps_orow_count(desc)), dtype=torch.float64, device=dev)
     log_abs = torch.empty(n, dtype=torch.float64, device=dev)
     status = new_status(dev) if status is None else status
-    ws = _ws("chain", peps_workspace_bytes(desc, n, _lib.WS_GRAD), dev)
+    ws = _chain_ws(desc, n, _lib.WS_GRAD, dev)
     code = LIB.peps_grad_batch(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), _ptr(O), _ptr(log_abs),
                                _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_grad_batch")
@@ -268,7 +289,7 @@ def peps_sample_sweep(desc: Desc, theta, configs, seed, sweep0, n_sweeps, measur
         _check_dev(sweep_counter)
         if sweep_counter.dtype != torch.int64 or sweep_counter.numel() != 1:
             raise ValueError("sweep_counter must be a one-element int64 device tensor")
-    ws = _own_ws(ws, "chain", peps_workspace_bytes(desc, n, _lib.WS_SWEEP), dev)
+    ws = _chain_ws(desc, n, _lib.WS_SWEEP, dev, ws)
     code = LIB.peps_sample_sweep(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(seed), int(sweep0),
                                  _ptr(sweep_counter), int(n_sweeps), _ptr(res.get("log_abs")), _ptr(res.get("sign")),
                                  _ptr(res.get("e_loc")), _ptr(res.get("O")), _ptr(res.get("configs")),

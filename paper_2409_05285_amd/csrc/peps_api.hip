@@ -40,7 +40,11 @@ bool desc_ok(const peps_desc* d) {
   return true;
 }
 
-Prob make_prob(const peps_desc* d) {
+// Problem and per-chain workspace layout.  refl_store selects, for the
+// workspace-resident compression, the layout that keeps every site's QR
+// reflectors (faster) or the one that keeps only the R factors and rebuilds
+// the reflectors (smaller).
+Prob make_prob(const peps_desc* d, bool refl_store = true) {
   Prob P;
   memset(&P, 0, sizeof(P));
   P.L1 = d->L1;
@@ -81,7 +85,14 @@ Prob make_prob(const peps_desc* d) {
   P.off_lstop = off; off += pad(P.L1);
   P.off_bot = off;   off += pad((int64_t)P.L1 * P.L2 * P.TS);
   P.off_lsbot = off; off += pad(P.L1);
-  P.off_B = off;     off += pad((int64_t)P.L2 * P.BS);
+  // the workspace-resident compression keeps one QR matrix and the R factor
+  // of every site (it rebuilds a site's reflectors when it needs them); the
+  // other kernels keep every site's absorbed tensor or reflectors
+  const bool big = !compress2_supported(P) && !compress_in_lds(P);
+  const bool rebuild = big && !refl_store;
+  P.refl_store = rebuild ? 0 : 1;
+  P.off_B = off;     off += pad(rebuild ? (int64_t)P.BS : (int64_t)P.L2 * P.BS);
+  P.off_Rst = off;   if (rebuild) off += pad((int64_t)P.L2 * cd * cd);
   P.off_tmp = off;   off += pad(P.BS);
   P.off_R = off;     off += pad((int64_t)(P.L2 + 1) * P.ES);
   P.off_L = off;     off += pad(4 * (int64_t)P.ES);
@@ -94,7 +105,7 @@ Prob make_prob(const peps_desc* d) {
   P.off_epart = off; off += pad(epart_size(P));
   P.off_tau = off;   off += pad((int64_t)P.L2 * P.chi * P.D);
   P.off_T = off;
-  if (!compress2_supported(P) && !compress_in_lds(P)) off += pad((int64_t)compress_big_T_doubles(P));
+  if (big) off += pad((int64_t)compress_big_T_doubles(P));
   P.mixed = d->precision == PEPS_PREC_MIXED;
   if (P.mixed) {
     // FP32 copies of the boundaries, same element strides as the FP64 ones
@@ -183,6 +194,10 @@ int64_t peps_slot_count(const peps_desc* d) {
   return make_prob(d).n_slots;
 }
 
+static size_t chain_ws_bytes(const Prob& P, int64_t n) {
+  return (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P) + redo_list_bytes(P, n);
+}
+
 peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, size_t* bytes) {
   if (!desc_ok(d) || !bytes || n < 0) return PEPS_ERR_ARG;
   Prob P = make_prob(d);
@@ -190,7 +205,10 @@ peps_status peps_workspace_bytes(const peps_desc* d, int64_t n, int32_t what, si
     case PEPS_WS_EVAL:
     case PEPS_WS_GRAD:
     case PEPS_WS_SWEEP:
-      *bytes = (size_t)n * (size_t)P.chain_stride * sizeof(double) + theta32_bytes(P) + redo_list_bytes(P, n);
+      *bytes = chain_ws_bytes(P, n);
+      return PEPS_OK;
+    case PEPS_WS_MIN:
+      *bytes = chain_ws_bytes(make_prob(d, false), n);
       return PEPS_OK;
     case PEPS_WS_SU:
       *bytes = (size_t)su_max_group(P) * ((su_bond_doubles(P) + 31) & ~(size_t)31) * sizeof(double);
@@ -227,9 +245,11 @@ static peps_status common_checks(const peps_desc* d, Prob& P, int64_t n, const v
   if (s != PEPS_OK) return s;
   if (n == 0) return PEPS_OK;
   if (!configs || !ws || (what != PEPS_WS_SR && !theta)) return PEPS_ERR_ARG;
-  size_t need = 0;
-  peps_workspace_bytes(d, n, what, &need);
-  if (ws_bytes < need) return PEPS_ERR_WORKSPACE;
+  // the full layout when the workspace holds it, else the smaller one
+  if (ws_bytes < chain_ws_bytes(P, n)) {
+    P = make_prob(d, false);
+    if (ws_bytes < chain_ws_bytes(P, n)) return PEPS_ERR_WORKSPACE;
+  }
   return PEPS_OK;
 }
 

@@ -30,6 +30,9 @@ struct Prob {
   int64_t off_top32, off_bot32;   // FP32 boundary copies (offsets in doubles)
   int64_t off_tau;                // Householder scalars of one compression [L2][chi*D]
   int64_t off_T;                  // panel T factors of the workspace-resident compression
+  int64_t off_Rst;                // its R factors of every site [L2][chi D][chi D] (rebuild layout)
+  int refl_store;                 // workspace-resident compression: every site's reflectors kept (1)
+                                  // or rebuilt from the stored R factors (0)
   int mixed;                      // FP32 strip contractions
   int fermionic;                  // Z2-graded parity-even tensors (odd total parity => rho = 0)
 };

@@ -14,7 +14,10 @@
 //     the pairs inside every column block, then the pairs between the two
 //     blocks of every block pair, each pass in LDS (every column pair once
 //     per outer sweep), no rotation accumulation for wide matrices;
-//   * Q_{c-1} (U S) applied panel by panel from the stored reflectors and T.
+//   * Q_{c-1} (U S) applied panel by panel from the reflectors and T of the
+//     QR of X_{c-1}: kept from the first sweep, or, in the smaller workspace
+//     layout, rebuilt from the stored R_{c-2} and a new absorption of site
+//     c-1 (one QR matrix per chain instead of one per site).
 #include <math.h>
 
 #include "peps_chain.hpp"
@@ -562,6 +565,7 @@ __global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, co
   __shared__ int rnk[CD_MAX];
   __shared__ int flags[2];
   __shared__ int sa[MAX_L], sp[MAX_L], sb[MAX_L];
+  __shared__ int rst_n[MAX_L];   // columns of site c's QR matrix (R_c is sb[c] x rst_n[c])
   const int tid = threadIdx.x;
   const int ch = blockIdx.x;
   if (tid == 0) build_geo(P, geo);
@@ -592,36 +596,47 @@ __global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, co
   }
   __syncthreads();
 
-  // 2. left-to-right QR; X_{c+1} = R_c B_{c+1} by MFMA tiles
+  // 2. left-to-right QR in the one QR matrix X (w.B); X_{c+1} = R_c B_{c+1}
+  // by MFMA tiles.  R_c is kept for every site: the truncation sweep rebuilds
+  // X_{c} from it to apply Q_c again, instead of keeping every site's
+  // reflectors (which would take L2 QR matrices per chain).
+  // QR matrix of site c: its own slot when every site's reflectors are kept,
+  // else the one slot (rebuilt when needed)
+  auto xslot = [&](int c) { return P.refl_store ? w.B + (size_t)c * P.BS : w.B; };
+  double* Rst = base + P.off_Rst;
+  // B_c absorbed into dst, row-major [y][p][col]; returns its dims
+  auto absorb_rm = [&](int c, double* dst, int& a1, int& p1, int& b1) {
+    int Dl, Du, Dr, Dd;
+    leg_dims(P, r, c, Dl, Du, Dr, Dd);
+    const int pp = dir == 0 ? Dd : Du;
+    const int bb = (has_prev ? geo.bb[dir][rp][c] : 1) * Dr;
+    absorb_site_to(P, geo, dir, r, c, theta, cfg, bnd, has_prev, rp, dst, (int64_t)pp * bb, bb, 1, a1, p1, b1);
+  };
+  // X = R B (k x n times the absorbed site [n][p1][b1]) into the column-major
+  // QR layout: X[col * m' + x * p1 + q] = sum_y R[x][y] B[y][q][col], m' = k p1
+  auto rb_product = [&](double* X, const double* Rr, int k, int n, const double* Bsrc, int p1, int b1) {
+    wg_gemm<double>(X, mstride(p1), Map2{b1, 1, k * p1}, Rr, mstride(n), mid(), Bsrc, mstride(p1 * b1), mid(), k,
+                    p1 * b1, n);
+  };
   for (int c = 0; c < P.L2 - 1; ++c) {
     const int m = sa[c] * sp[c], n = sb[c];
     const int k = m < n ? m : n;
-    double* X = w.B + (size_t)c * P.BS;
+    double* X = xslot(c);
     qr_blocked(X, m, n, taus_all + (size_t)c * cd, T_all + (size_t)c * cd * NBMAX, panel, Tm, red);
-    // R (k x n, row-major, zero below the diagonal)
-    double* Rr = w.R;
+    // R_c (k x n, row-major, zero below the diagonal); kept per site only
+    // when the reflectors are rebuilt
+    double* Rr = P.refl_store ? w.R : Rst + (size_t)c * cd * cd;
     for (int idx = tid; idx < k * n; idx += NTB) {
       const int i = idx / n, j = idx % n;
       Rr[idx] = j >= i ? X[(size_t)j * m + i] : 0.0;
     }
-    // B_{c+1} absorbed, row-major [y][p][col]
     int a1, p1, b1;
-    {
-      int Dl, Du, Dr, Dd;
-      leg_dims(P, r, c + 1, Dl, Du, Dr, Dd);
-      const int pp = dir == 0 ? Dd : Du;
-      const int bb = (has_prev ? geo.bb[dir][rp][c + 1] : 1) * Dr;
-      absorb_site_to(P, geo, dir, r, c + 1, theta, cfg, bnd, has_prev, rp, w.tmp, (int64_t)pp * bb, bb, 1, a1, p1,
-                     b1);
-    }
+    absorb_rm(c + 1, w.tmp, a1, p1, b1);
     __syncthreads();
     if (a1 != n) set_status(status, PEPS_ERR_UNSUPPORTED);   // bond of the absorbed row: cannot differ
-    // X_{c+1}[col * m' + x * p + q] = sum_y R[x][y] B[y][q][col], m' = k p
-    const int mn = k * p1;
-    double* Xn = w.B + (size_t)(c + 1) * P.BS;
-    wg_gemm<double>(Xn, mstride(p1), Map2{b1, 1, mn}, Rr, mstride(n), mid(), w.tmp, mstride(p1 * b1), mid(), k,
-                    p1 * b1, n);
+    rb_product(xslot(c + 1), Rr, k, n, w.tmp, p1, b1);
     if (tid == 0) {
+      rst_n[c] = n;
       sb[c] = k;
       sa[c + 1] = k;
       sp[c + 1] = p1;
@@ -633,7 +648,7 @@ __global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, co
   {
     const int c = P.L2 - 1;
     const int a = sa[c], pp = sp[c], b = sb[c], m = a * pp;
-    const double* X = w.B + (size_t)c * P.BS;
+    const double* X = xslot(c);
     for (int idx = tid; idx < a * pp * b; idx += NTB) {
       const int i = idx / (pp * b), e = idx % (pp * b), p = e / b, col = e % b;
       w.tmp[idx] = X[(size_t)col * m + i * pp + p];
@@ -714,8 +729,27 @@ __global__ void __launch_bounds__(NTB) k_compress_big(Prob P, int dir, int r, co
       const int i = idx / k2, q = idx % k2;
       w.tmp[idx] = i < a ? US[i * k2 + q] : 0.0;
     }
+    // X_{c-1} rebuilt exactly as in the first sweep (the same absorption,
+    // product and QR, so the same reflectors), then Q_{c-1} applied
+    double* X = xslot(c - 1);
+    if (P.refl_store) {
+      // kept from the first sweep
+    } else if (c - 1 == 0) {
+      int a0, p0, b0;
+      absorb_site_to(P, geo, dir, r, 0, theta, cfg, bnd, has_prev, rp, X, sp[0], 1, (int64_t)sa[0] * sp[0], a0, p0,
+                     b0);
+    } else {
+      // X_{c-1} = R_{c-2} B_{c-1}: R_{c-2} is sa[c-1] x rst_n[c-2]
+      int a1, p1, b1;
+      absorb_rm(c - 1, w.X, a1, p1, b1);
+      __syncthreads();
+      rb_product(X, Rst + (size_t)(c - 2) * cd * cd, sa[c - 1], rst_n[c - 2], w.X, p1, b1);
+    }
     __syncthreads();
-    apply_q_blocked(w.B + (size_t)(c - 1) * P.BS, m2, kq, T_all + (size_t)(c - 1) * cd * NBMAX, w.tmp, k2, panel);
+    if (!P.refl_store)
+      qr_blocked(X, m2, rst_n[c - 1], taus_all + (size_t)(c - 1) * cd, T_all + (size_t)(c - 1) * cd * NBMAX, panel,
+                 Tm, red);
+    apply_q_blocked(X, m2, kq, T_all + (size_t)(c - 1) * cd * NBMAX, w.tmp, k2, panel);
     if (tid == 0) {
       sb[c - 1] = k2;
       sa[c] = k2;

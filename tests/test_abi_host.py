@@ -142,3 +142,21 @@ def test_noalloc_solve_refuses_sizes_beyond_its_scratch():
                                    None, None) == -1
     assert LIB.sr_cg_solve_noalloc(ctypes.byref(c), n_s, None, v, None, None, v, 0.01, 1e-4, 10, 0.0, v, None, None,
                                    v, None, None) == -1
+
+
+def test_smallest_workspace_layout():
+    """Where the QR matrices do not fit on chip (chi * D > 64) the smallest
+    accepted workspace keeps R factors instead of every site's reflectors:
+    at 16x16, D = 8, chi = 64 it is well under the full size, elsewhere the
+    two sizes are equal; a workspace between the two is accepted, one below
+    the smallest is refused (with n = 0 no size is needed)."""
+    import paper_2409_05285_amd as p
+    from paper_2409_05285_amd._lib import LIB, WS_MIN
+    big = p.Desc(16, 16, 8, 64)
+    full, small = p.peps_workspace_bytes(big, 4, 2), p.peps_workspace_bytes(big, 4, WS_MIN)
+    assert small < 0.6 * full
+    for d in (p.Desc(8, 8, 4, 16), p.Desc(4, 4, 2, 4), p.Desc(4, 4, 3, 7)):
+        assert p.peps_workspace_bytes(d, 4, WS_MIN) == p.peps_workspace_bytes(d, 4, 2)
+    c = big.c()
+    v = ctypes.c_void_p(8)
+    assert LIB.peps_eval_batch(ctypes.byref(c), v, 4, v, v, v, None, None, v, small - 8, None, None) == -4

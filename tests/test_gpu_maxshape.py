@@ -109,3 +109,31 @@ def test_largest_boundary_shape():
     th = synth.theta_random_unit(6, 6, 8, 2, seed=7)
     cfg = synth.configs_sector(2, 36, 2, seed=46)
     _check(p, lat, desc, th, cfg, 64, 1e-10, 1e-9, False)
+
+
+def test_smallest_workspace_layout_is_bit_identical():
+    """The workspace-resident compression in its two layouts -- every site's
+    QR reflectors kept (full workspace) or rebuilt from the stored R factors
+    (the smallest workspace, PEPS_WS_MIN) -- gives the same sweep, log|psi|,
+    local energies and O rows bit for bit (6x6, D = 4, chi = 20: chi D = 80,
+    past the on-chip kernels)."""
+    dev = _dev()
+    import paper_2409_05285_amd as p
+    _say("workspace layouts, 6x6 D=4 chi=20")
+    desc = p.Desc(6, 6, 4, 20, J2=0.5)
+    th = torch.tensor(synth.theta_random_unit(6, 6, 4, 2, seed=81), device=dev)
+    cfg0 = synth.configs_diagonal(8, 36, 2, seed=82)
+    n = cfg0.shape[0]
+    full, small = p.workspace_bytes(desc, n, "sweep"), p.workspace_bytes(desc, n, "min")
+    assert small < full
+    outs = []
+    for nb in (full, small):
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        cfg = torch.tensor(cfg0, device=dev)
+        res = p.peps_sample_sweep(desc, th, cfg, 77, 0, 2, ws=ws)
+        torch.cuda.synchronize()
+        assert p.check(res["status"]) == 0
+        outs.append((cfg.cpu().numpy(), res["log_abs"].cpu().numpy(), res["e_loc"].cpu().numpy(),
+                     res["O"].cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
