@@ -242,8 +242,10 @@ class Path:
         self.n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
         self.status = p.new_status(dev)
         self.gsweep = 0
-        # room for every traced launch of one full step (about 8 L1 per sweep)
-        self.trace = p.Trace(16 * desc.L1 * args.sweeps + 64)
+        # room for every traced launch of one full step (about 8 L1 per sweep
+        # and library call; one call per chunk of chains with --chunk)
+        calls = -(-n // args.chunk) if args.chunk and args.chunk < n else 1
+        self.trace = p.Trace(16 * desc.L1 * args.sweeps * calls + 64)
         self.out = None
 
     def _buffers(self, S):
@@ -262,8 +264,19 @@ class Path:
     def step(self, S, trace=None):
         p, a, n = self.p, self.args, self.n
         out = self._buffers(S)
-        p.peps_sample_sweep(self.desc, self.theta, self.configs, self.seed, self.gsweep, S, n_accept=self.n_accept,
-                            status=self.status, out=out, trace=trace)
+        if a.chunk and a.chunk < n:
+            # one library call per chunk of chains (one sweep each), a
+            # progress line after each; each chunk draws from its own seed
+            for c0 in range(0, n, a.chunk):
+                c1 = min(n, c0 + a.chunk)
+                sub = {k: v[:, c0:c1] for k, v in out.items()}
+                p.peps_sample_sweep(self.desc, self.theta, self.configs[c0:c1], self.seed + c0, self.gsweep, S,
+                                    n_accept=self.n_accept[c0:c1], status=self.status, out=sub, trace=trace)
+                self.torch.cuda.synchronize()
+                progress(f"chains {c0}..{c1 - 1} swept and measured")
+        else:
+            p.peps_sample_sweep(self.desc, self.theta, self.configs, self.seed, self.gsweep, S,
+                                n_accept=self.n_accept, status=self.status, out=out, trace=trace)
         self.gsweep += S
         _, _, stats, _ = p.sr_cg_solve(self.desc, out["configs"].view(S * n, self.desc.N),
                                        out["O"].view(S * n, self.nnz), out["e_loc"].view(S * n), a.tau, a.eps,
@@ -314,10 +327,12 @@ class Path:
                 "wall": wall, "prof": prof, "stats": stats.cpu().numpy(), "accepted_per_sweep": acc}
 
 
-def graph_rate(p, torch, desc, theta0, configs0, args, seed, k=3):
+def graph_rate(p, torch, desc, theta0, configs0, args, seed, k=3, warm=True):
     """A one-sweep step (sweep, measurement, SR on those n samples, update)
-    run eagerly and, captured once in a HIP graph (caller-owned workspaces,
-    device sweep counter), replayed: ms per step of both, k each."""
+    run eagerly and, captured once in HIP graphs (caller-owned workspaces,
+    device sweep counter), replayed: ms per step of both, k each.  With
+    --chunk the sweep of each chunk of chains is a graph of its own and the
+    SR solve another, replayed in order with a progress line after each."""
     dev = theta0.device
     n = configs0.shape[0]
     nnz = p.peps_orow_count(desc)
@@ -326,41 +341,57 @@ def graph_rate(p, torch, desc, theta0, configs0, args, seed, k=3):
     ctr = torch.zeros(1, dtype=torch.int64, device=dev)
     n_accept = torch.zeros((n, 3), dtype=torch.int32, device=dev)
     status = p.new_status(dev)
-    ws = torch.empty(p.workspace_bytes(desc, n, "sweep"), dtype=torch.uint8, device=dev)
+    chunk = args.chunk if args.chunk and args.chunk < n else n
+    bounds = [(c0, min(n, c0 + chunk)) for c0 in range(0, n, chunk)]
+    ws = torch.empty(p.workspace_bytes(desc, chunk, "sweep"), dtype=torch.uint8, device=dev)
     ws_sr = torch.empty(p.workspace_bytes(desc, n, "sr"), dtype=torch.uint8, device=dev)
     out = {"log_abs": torch.empty((1, n), dtype=torch.float64, device=dev),
            "sign": torch.empty((1, n), dtype=torch.int8, device=dev),
            "e_loc": torch.empty((1, n), dtype=torch.float64, device=dev),
            "O": torch.empty((1, n, nnz), dtype=torch.float64, device=dev)}
 
-    def step():
-        p.peps_sample_sweep(desc, theta, configs, seed, 0, 1, n_accept=n_accept, status=status, out=out,
-                            sweep_counter=ctr, ws=ws)
+    def sweep(c0, c1):
+        sub = {key: v[:, c0:c1] for key, v in out.items()}
+        p.peps_sample_sweep(desc, theta, configs[c0:c1], seed + c0, 0, 1, n_accept=n_accept[c0:c1], status=status,
+                            out=sub, sweep_counter=ctr, ws=ws)
+
+    def solve():
         p.sr_cg_solve(desc, configs, out["O"][0], out["e_loc"][0], args.tau, args.eps, args.cg_iters, 1e-10,
                       want_g=False, theta=theta, status=status, ws=ws_sr)
 
-    def timed(fn):
+    pieces = [(lambda b=b: sweep(*b)) for b in bounds] + [solve]
+
+    def run(fns, label):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(k):
-            fn()
+            for i, fn in enumerate(fns):
+                fn()
+                if len(fns) > 2:
+                    torch.cuda.synchronize()
+                    progress(f"{label}: piece {i + 1} of {len(fns)} done")
         ev1.record()
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / k
 
-    step()
+    if warm:
+        for fn in pieces:
+            fn()
+        torch.cuda.synchronize()
+    eager_ms = run(pieces, "eager step")
+    graphs = []
+    for fn in pieces:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs.append(g)
     torch.cuda.synchronize()
-    eager_ms = timed(step)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step()
-    torch.cuda.synchronize()
-    graph_ms = timed(graph.replay)
+    graph_ms = run([g.replay for g in graphs], "replayed step")
     p.check(status, "graph replays")
-    del graph
+    del graphs
     return {"eager_ms_per_step": round(eager_ms, 3), "graph_ms_per_step": round(graph_ms, 3),
-            "graph_samples_per_s": round(n / (graph_ms / 1e3), 2), "steps_each": k,
+            "graph_samples_per_s": round(n / (graph_ms / 1e3), 2), "steps_each": k, "graphs_per_step": len(pieces),
             "sweeps_run": int(ctr.item())}
 
 
@@ -461,6 +492,10 @@ def main():
     ap.add_argument("--model", choices=["heisenberg", "hubbard"], default="heisenberg",
                     help="hubbard (with --only): t = 1, U = 8, mu = 4, d^2 = 16, random parity-even tensors")
     ap.add_argument("--chains", type=int, default=1024)
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="with --only and --sweeps 1: sweep the chains in library calls of this many chains, with a "
+                         "progress line after each (large lattices), each chunk from its own seed")
+    ap.add_argument("--graph-steps", type=int, default=3, help="steps of each kind timed by --graph")
     ap.add_argument("--cg-iters", type=int, default=200)
     ap.add_argument("--tau", type=float, default=0.02)
     ap.add_argument("--eps", type=float, default=1e-4)
@@ -515,20 +550,25 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.chunk and args.sweeps != 1:
+        print("--chunk needs --sweeps 1", file=sys.stderr)
+        sys.exit(2)
     if args.only != "both":
         desc = desc64 if args.only == "fp64" else descmx
         path = Path(p, torch, desc, theta0, configs0, args, seed)
         path.warmup(args.warmup)
         r = path.timed(args.steps, args.budget_s, args.only)
         line = {"only": args.only, "model": args.model, "lattice": [L1, L2], "D": D, "chi": chi,
-                "J2": args.J2, "chains": n, "steps": r["steps"],
+                "J2": args.J2, "chains": n, "chunk": args.chunk or n, "steps": r["steps"],
+                "peak_device_GiB": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2),
                 "sweeps_per_step": args.sweeps, "samples_per_s": round(r["samples_per_s"], 2),
                 "ms_per_step": round(r["ms_per_step"], 3),
                 "kernel_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["prof"].items()},
                 "kernel_launches": {k: v[1] for k, v in r["prof"].items()}}
         if args.graph:
             progress("one-sweep step, eager and replayed graph")
-            line["graph_replay"] = graph_rate(p, torch, desc, theta0, configs0, args, seed)
+            line["graph_replay"] = graph_rate(p, torch, desc, theta0, configs0, args, seed, k=args.graph_steps,
+                                              warm=args.warmup > 0)
         print(json.dumps(line), flush=True)
         return
 
