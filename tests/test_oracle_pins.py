@@ -922,3 +922,169 @@ def test_identity_state_closed_forms_on_larger_lattices(L1, L2, D, chi, J2):
         assert ev["sign"] == 1
         assert ev["e_loc"] == pytest.approx(e_ref[i], abs=1e-13)
         assert np.allclose(ev["O"], o_ref, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Direct sampling (Appendix A, Eqs. A2-A7), pinned against the exact
+# amplitudes of the network contraction (itself pinned to brute force above)
+# and against brute-force marginals over the completions of each prefix.
+
+
+def _exact_probs(lat, th):
+    cfgs = network.all_configs(lat)
+    w = np.array([network.amplitude(lat, th, S) ** 2 for S in cfgs])
+    return cfgs, w / w.sum()
+
+
+def _brute_conditionals(lat, cfgs, p0, S, reweight, b_diag):
+    """Product of the conditionals along S from sums of p0 over the
+    completions of each prefix (Eqs. A3, A5, A6 with the normalisation of
+    the last two), in log form."""
+    lp = 0.0
+    mask = np.ones(len(cfgs), dtype=bool)
+    for i in range(lat.N):
+        q = np.array([p0[mask & (cfgs[:, i] == x)].sum() for x in range(lat.d2)])
+        p = q / q.sum()
+        if reweight:
+            b = np.array([1.0 if x // lat.d != x % lat.d else b_diag for x in range(lat.d2)])
+            p = b * np.sqrt(p)
+            p = p / p.sum()
+        lp += math.log(p[S[i]])
+        mask &= cfgs[:, i] == S[i]
+    return lp
+
+
+def test_direct_p2_equals_rho_squared_at_exact_chi():
+    """Eq. A2: with boundaries that truncate nothing, the product of the
+    conditionals is |rho(S)|^2 / Z for every configuration (2x2, D = 2)."""
+    from oracle import direct
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=81)
+    cfgs, p = _exact_probs(lat, th)
+    bdl = direct.double_layer_bottoms(lat, th, 16)
+    for S, pS in zip(cfgs, p):
+        lp = direct.log_prob(lat, th, S, 4, 16, bdl=bdl)
+        if pS == 0.0:
+            assert lp == -math.inf
+        else:
+            assert abs(lp - math.log(pS)) <= 1e-11 * max(1.0, abs(math.log(pS))), (S, lp, math.log(pS))
+
+
+def test_direct_p2_conditionals_on_a_three_row_lattice():
+    """3x2, D = 2: the double-layer bottom of two rows is compressed (exactly,
+    at chi_dl = 16); conditionals against brute-force marginals."""
+    from oracle import direct
+    lat = Lattice(3, 2, D=2, chi=4)
+    th = synth.theta_random_unit(3, 2, 2, 2, seed=82)
+    cfgs, p = _exact_probs(lat, th)
+    bdl = direct.double_layer_bottoms(lat, th, 16)
+    rng = np.random.default_rng(83)
+    for k in rng.choice(len(cfgs), 40, replace=False, p=p):
+        S = cfgs[k]
+        lp = direct.log_prob(lat, th, S, 4, 16, bdl=bdl)
+        want = _brute_conditionals(lat, cfgs, p, S, False, 1.0)
+        assert abs(lp - want) <= 1e-10 * max(1.0, abs(want)), (S, lp, want)
+        assert abs(want - math.log(p[k])) <= 1e-10 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("b_diag", [1.0, 0.3])
+def test_direct_p4_conditionals_match_brute_force(b_diag):
+    """Eqs. A4-A6: p_4c = b sqrt(p_2c), normalised, with b = 1 off the
+    diagonal digits; every configuration of a 2x2 lattice against the
+    brute-force marginals, and sum_S p_4(S) = 1."""
+    from oracle import direct
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=84)
+    cfgs, p = _exact_probs(lat, th)
+    bdl = direct.double_layer_bottoms(lat, th, 16)
+    tot = 0.0
+    for S in cfgs:
+        lp = direct.log_prob(lat, th, S, 4, 16, reweight=True, b_diag=b_diag, bdl=bdl)
+        want = _brute_conditionals(lat, cfgs, p, S, True, b_diag)
+        assert abs(lp - want) <= 1e-10 * max(1.0, abs(want)), (S, lp, want)
+        tot += math.exp(lp)
+    assert abs(tot - 1.0) <= 1e-12
+
+
+def test_direct_draws_follow_their_probabilities():
+    """Draws of the sampler: the log-probability it reports is that of the
+    drawn configuration, and the histogram of 3000 draws agrees with
+    |rho|^2 / Z (chi^2 test; draws are independent)."""
+    from oracle import direct
+    lat = Lattice(2, 2, D=2, chi=4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=85)
+    cfgs, p = _exact_probs(lat, th)
+    index = {tuple(S): k for k, S in enumerate(cfgs)}
+    bdl = direct.double_layer_bottoms(lat, th, 16)
+    counts = np.zeros(len(cfgs))
+    n = 3000
+    for ch in range(n):
+        r = direct.sample(lat, th, 4, 16, seed=17, chain=ch, draw=0, bdl=bdl)
+        k = index[tuple(r["S"])]
+        counts[k] += 1
+        if ch < 50:
+            assert abs(r["log_p"] - math.log(p[k])) <= 1e-11 * max(1.0, abs(r["log_p"]))
+    exp_ = p * n
+    mask = exp_ > 5
+    chi2 = float((((counts - exp_) ** 2)[mask] / exp_[mask]).sum())
+    dof = int(mask.sum()) - 1
+    # independent draws: 99.9% quantile of chi^2 is below dof + 4 sqrt(2 dof) + 10
+    assert chi2 < dof + 4.0 * math.sqrt(2 * dof) + 10, (chi2, dof)
+
+
+def test_direct_importance_weights_recover_rho_squared_averages():
+    """Eq. A7: averages over p_4 draws with weights r_4 = |rho|^2 / p_4
+    estimate <f>_{|rho|^2}; exactly so in expectation, checked on the full
+    enumeration (sum_S p_4 r_4 f / sum_S p_4 r_4) and statistically on draws
+    with a truncated double layer (chi_dl = 2), whose weights absorb the
+    truncation."""
+    from oracle import direct
+    lat = Lattice(2, 3, D=2, chi=4)
+    th = synth.theta_random_unit(2, 3, 2, 2, seed=86)
+    cfgs, p = _exact_probs(lat, th)
+    f = np.array([sum(1.0 for x in S if x // 2 != x % 2) for S in cfgs])    # off-diagonal sites
+    want = float((p * f).sum())
+    bdl = direct.double_layer_bottoms(lat, th, 2)
+    samp = [direct.sample(lat, th, 4, 2, seed=23, chain=ch, draw=0, reweight=True, b_diag=0.5, bdl=bdl)
+            for ch in range(1500)]
+    idx = {tuple(S): k for k, S in enumerate(cfgs)}
+    ks = np.array([idx[tuple(s["S"])] for s in samp])
+    lr = np.log(p[ks]) - np.array([s["log_p"] for s in samp])
+    w = np.exp(lr - lr.max())
+    est = float((w * f[ks]).sum() / w.sum())
+    neff = w.sum() ** 2 / (w ** 2).sum()
+    sd = math.sqrt(float((w * (f[ks] - est) ** 2).sum() / w.sum()) / neff)
+    assert abs(est - want) < 5.0 * sd + 1e-3, (est, want, sd)
+    # the drawn probabilities are those the sampler assigns
+    for s in samp[:5]:
+        lp = direct.log_prob(lat, th, s["S"], 4, 2, reweight=True, b_diag=0.5, bdl=bdl)
+        assert abs(lp - s["log_p"]) <= 1e-12 * max(1.0, abs(lp))
+
+
+def test_direct_b_update_closed_forms():
+    """The dynamic diagonal weight: unchanged at half diagonal draws, scaled
+    by (1/2)^(1/N) when every draw is diagonal, capped at 1."""
+    from oracle import direct
+    lat = Lattice(2, 2, D=1, chi=1)
+    diag = np.array([[0, 3, 0, 3]] * 4)
+    off = np.array([[1, 3, 0, 3]] * 4)
+    assert direct.update_b(lat, 0.4, np.vstack([diag[:2], off[:2]])) == pytest.approx(0.4, rel=1e-15)
+    assert direct.update_b(lat, 0.4, diag) == pytest.approx(0.4 * 0.5 ** 0.25, rel=1e-15)
+    assert direct.update_b(lat, 0.9, off) == 1.0
+
+
+def test_direct_hubbard_draws_are_parity_even_and_exact():
+    """Fermion sampler (Hubbard section, Appendix A): with Z2-even tensors
+    every odd-parity configuration has rho = 0, so the exact conditionals
+    never draw one; each draw's probability is |rho|^2 / Z (2x2, d^2 = 16,
+    Z by enumeration of all 16^4 configurations)."""
+    from oracle import direct
+    lat = Lattice(2, 2, D=2, chi=4, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    th = synth.theta_random_parity_even(2, 2, 2, 4, seed=87)
+    Z = sum(network.amplitude(lat, th, S) ** 2 for S in network.all_configs(lat))
+    bdl = direct.double_layer_bottoms(lat, th, 16)
+    for ch in range(30):
+        r = direct.sample(lat, th, 4, 16, seed=29, chain=ch, draw=0, bdl=bdl)
+        assert sum(bin(int(x)).count("1") for x in r["S"]) % 2 == 0
+        want = math.log(network.amplitude(lat, th, r["S"]) ** 2 / Z)
+        assert abs(r["log_p"] - want) <= 1e-10 * max(1.0, abs(want)), (r["S"], r["log_p"], want)
