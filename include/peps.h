@@ -314,6 +314,58 @@ peps_status peps_simple_update(const peps_desc* desc, double* theta, double* lam
 peps_status peps_su_absorb(const peps_desc* desc, const double* theta, const double* lambdas, double* theta_out,
                            peps_stream_t stream);
 
+/* ---- direct sampling (Appendix A, Eqs. A2-A7) -------------------------- */
+
+/* Workspace bytes of peps_direct_sample for n_chains chains and double-layer
+   boundary dimension chi_dl.  PEPS_ERR_UNSUPPORTED where the draw kernel's
+   per-chain intermediates (D^6 chi^2 chi_dl doubles) exceed 2^24 doubles or
+   chi_dl D^2 exceeds the compression kernels' 512. */
+peps_status peps_direct_workspace_bytes(const peps_desc* desc, int64_t n_chains, int32_t chi_dl, size_t* bytes);
+
+/* Direct (autoregressive) sampling (Appendix A, Eqs. A2-A6): every chain
+   draws one configuration, sites row-major, each from its conditional
+   probability given the sites drawn before it,
+     p_2c(S_i | S_<i) proportional to the sum of |rho(S)|^2 over S_>i
+   (reweight = 0), or p_4c = b(S_i) sqrt(p_2c) normalised over S_i
+   (reweight = 1; b = 1 where s_i != s'_i, b = *b_diag where s_i = s'_i).
+   The marginals are those of the double-layer network sum_S rho(S)^2: site
+   tensors E_i = sum_S T_i[S] (x) T_i[S] (legs of dimension D^2), whose bottom
+   boundaries are compressed to chi_dl by the row compression of the
+   single-layer path; the rows already drawn enter as their single-layer top
+   boundary (compressed to desc->chi on the drawn digits) paired with
+   itself.  A negative marginal (truncation) counts as 0.  With chi_dl and
+   chi large enough to truncate nothing, the draw is exact: p_2(S) =
+   |rho(S)|^2 / Z.  Site i of chain c takes the uniform of Philox4x64-10 with
+   counter (c, draw, i, 3) and key (seed, 0) and picks the first digit whose
+   running sum of probabilities (digit order) exceeds it.
+     configs [n_chains][N] u8 (out); log_p [n_chains] f64 (out): log of the
+   probability the sampler gave the drawn configuration (the product of the
+   conditionals it used), the denominator of the importance weight
+   r = |rho|^2 / p (Eq. A7; see peps_importance_weights).  b_diag: device
+   pointer to one f64, read when reweight = 1; with update_b = 1 it is
+   updated after the draw to min(1, b (1/2 / f)^(1/N)), f the fraction of the
+   drawn configurations with s = s' on every site (f = 0 counts as 1/4), so
+   that repeated steps hold diagonal draws near half.  Strips run in FP64
+   whatever desc->precision says.  A chain whose marginals all vanish
+   records PEPS_ERR_ZERO_AMPLITUDE (non-finite ones PEPS_ERR_NONFINITE), gets
+   log_p = -inf and zero digits from that site on.  For fermionic descs the
+   draw is not restricted to even parity: a parity-even ansatz gives odd
+   configurations zero weight by itself, and otherwise an odd draw gets
+   importance weight 0.  ws: peps_direct_workspace_bytes(desc, n_chains,
+   chi_dl). */
+peps_status peps_direct_sample(const peps_desc* desc, const double* theta, int32_t n_chains, int32_t chi_dl,
+                               uint64_t seed, uint64_t draw, int32_t reweight, double* b_diag, int32_t update_b,
+                               uint8_t* configs, double* log_p, int32_t* status, void* ws, size_t ws_bytes,
+                               peps_trace* trace, peps_stream_t stream);
+
+/* Importance weights of directly drawn samples (Eq. A7): weights[i] =
+   exp(2 log_abs[i] - log_p[i] - m), m the largest finite value of
+   2 log_abs - log_p, and 0 where log_abs or log_p is -inf.  The weights are
+   scaled so that the largest is 1; pass them as `weights` to sr_cg_solve and
+   peps_sample_stats.  n in [1, 2^30]. */
+peps_status peps_importance_weights(int64_t n, const double* log_abs, const double* log_p, double* weights,
+                                    peps_stream_t stream);
+
 /* ---- instrumentation (not part of the method) --------------------------- */
 
 /* Kernel classes of a trace. */
@@ -326,7 +378,8 @@ enum {
   PEPS_K_FINAL = 5,    /* per-sample outputs (and the FP64 re-evaluation of
                           ill-conditioned samples of the mixed path)        */
   PEPS_K_SR = 6,       /* all SR / CG kernels of one sr_cg_solve call       */
-  PEPS_N_KCLASS = 7
+  PEPS_K_DIRECT = 7,   /* direct sampling: double layer, per-row draws      */
+  PEPS_N_KCLASS = 8
 };
 
 /* Host: a trace with room for `capacity` timed launches (two HIP events

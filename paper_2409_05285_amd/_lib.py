@@ -87,6 +87,13 @@ def _load():
     lib.peps_sample_stats.argtypes = [P, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]
     lib.peps_sample_stats.restype = c_int32
+    lib.peps_direct_workspace_bytes.argtypes = [P, c_int64, c_int32, POINTER(c_size_t)]
+    lib.peps_direct_workspace_bytes.restype = c_int32
+    lib.peps_direct_sample.argtypes = [P, c_void_p, c_int32, c_int32, c_uint64, c_uint64, c_int32, c_void_p, c_int32,
+                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+    lib.peps_direct_sample.restype = c_int32
+    lib.peps_importance_weights.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.peps_importance_weights.restype = c_int32
     lib.peps_trace_create.argtypes = [c_int32]
     lib.peps_trace_create.restype = c_void_p
     lib.peps_trace_destroy.argtypes = [c_void_p]
@@ -101,7 +108,8 @@ EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_works
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
            "sr_cg_solve_noalloc",
            "peps_vjp_batch", "peps_observables_batch", "peps_sample_stats", "peps_simple_update",
-           "peps_su_absorb", "peps_trace_create", "peps_trace_destroy", "peps_trace_read"]
+           "peps_su_absorb", "peps_direct_workspace_bytes", "peps_direct_sample", "peps_importance_weights",
+           "peps_trace_create", "peps_trace_destroy", "peps_trace_read"]
 SR_STATIC_BYTES = 64 << 20   # scratch of sr_cg_solve_noalloc per GPU
 SR_NSTATS = 5   # sr_cg_solve stats: Ebar, |r|, iterations, |b|, not-converged flag
-KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr"]
+KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr", "direct"]

@@ -400,6 +400,58 @@ def peps_sample_stats(desc: Desc, values, n_chains, log_abs=None, weights=None):
     return out
 
 
+def peps_direct_workspace_bytes(desc: Desc, n_chains, chi_dl) -> int:
+    out = ctypes.c_size_t(0)
+    _raise(LIB.peps_direct_workspace_bytes(ctypes.byref(desc.c()), int(n_chains), int(chi_dl), ctypes.byref(out)),
+           "peps_direct_workspace_bytes")
+    return int(out.value)
+
+
+def peps_direct_sample(desc: Desc, theta, n_chains, chi_dl, seed, draw=0, reweight=False, b_diag=None,
+                       update_b=False, status=None, out=None, ws=None, trace=None):
+    """Direct (autoregressive) draws, one configuration per chain.  Returns
+    (configs [n, N] u8, log_p [n] f64, status).  `b_diag` (float64 [1] on the
+    device) is read when reweight and updated in place when update_b.  `out`
+    may supply (configs, log_p) tensors; `ws` a uint8 workspace of at least
+    peps_direct_workspace_bytes(desc, n_chains, chi_dl) bytes."""
+    theta = _theta(desc, theta)
+    _check_dev(theta, b_diag)
+    dev = theta.device
+    n = int(n_chains)
+    if (reweight or update_b) and (b_diag is None or b_diag.dtype != torch.float64 or b_diag.numel() != 1):
+        raise ValueError("b_diag must be a float64 device tensor with one element")
+    if out is None:
+        configs = torch.empty((n, desc.N), dtype=torch.uint8, device=dev)
+        log_p = torch.empty(n, dtype=torch.float64, device=dev)
+    else:
+        configs, log_p = out
+        if (configs.dtype != torch.uint8 or tuple(configs.shape) != (n, desc.N) or not configs.is_contiguous()
+                or log_p.dtype != torch.float64 or log_p.numel() != n or not log_p.is_contiguous()):
+            raise ValueError("out must be (uint8 [n, N], float64 [n]) contiguous tensors")
+    status = new_status(dev) if status is None else status
+    need = peps_direct_workspace_bytes(desc, n, chi_dl)
+    ws = _own_ws(ws, "direct", need, dev)
+    code = LIB.peps_direct_sample(ctypes.byref(desc.c()), _ptr(theta), n, int(chi_dl), int(seed), int(draw),
+                                  int(bool(reweight)), _ptr(b_diag), int(bool(update_b)), _ptr(configs), _ptr(log_p),
+                                  _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
+    _raise(code, "peps_direct_sample")
+    return configs, log_p, status
+
+
+def peps_importance_weights(log_abs, log_p, out=None):
+    """Eq. A7 weights |rho|^2 / p of directly drawn samples, largest = 1."""
+    for x in (log_abs, log_p):
+        if x.dtype != torch.float64 or not x.is_contiguous() or x.dim() != 1:
+            raise ValueError("log_abs and log_p must be contiguous float64 vectors")
+    if log_abs.numel() != log_p.numel() or log_abs.numel() < 1:
+        raise ValueError("log_abs and log_p must have the same nonzero length")
+    _check_dev(log_abs, log_p)
+    w = torch.empty_like(log_abs) if out is None else out
+    _raise(LIB.peps_importance_weights(log_abs.numel(), _ptr(log_abs), _ptr(log_p), _ptr(w), _stream()),
+           "peps_importance_weights")
+    return w
+
+
 def peps_vjp_batch(desc: Desc, configs, O_rows, cot):
     """grad [N_p] f64 = sum_i cot_i O_i, scattered into the parameter layout."""
     configs = _configs(desc, configs)

@@ -465,6 +465,98 @@ peps_status peps_su_absorb(const peps_desc* d, const double* theta, const double
   return PEPS_OK;
 }
 
+// ---- direct sampling (Appendix A) ------------------------------------------
+
+// The chain problem (FP64 strips), the double layer's problem (one digit,
+// bond D^2, boundary chi_dl) and the draw kernel's scratch layout.
+static peps_status direct_setup(const peps_desc* d, int32_t chi_dl, Prob& P, Prob& Q, DirectLayout& L) {
+  if (!desc_ok(d) || chi_dl < 1) return PEPS_ERR_ARG;
+  peps_desc dp = *d;
+  dp.precision = PEPS_PREC_FP64;
+  P = make_prob(&dp);
+  peps_status s = device_support(&dp, P);
+  if (s != PEPS_OK) return s;
+  peps_desc dq = dp;
+  dq.d = 1;
+  dq.D = d->D * d->D;
+  dq.chi = chi_dl;
+  dq.fermionic = 0;
+  Q = make_prob(&dq);
+  s = device_support(&dq, Q);
+  if (s != PEPS_OK) return s;
+  L = direct_layout(P, Q);
+  if ((int64_t)P.chi * P.chi > 255 * 255 || L.x1 > ((int64_t)1 << 24)) return PEPS_ERR_UNSUPPORTED;
+  return PEPS_OK;
+}
+
+// Byte offsets of the regions of a direct-sampling workspace: the chains'
+// boundary workspaces, the double-layer tensors, the double layer's
+// one-chain workspace, its all-zero configuration, the draw scratch.
+struct DirectRegions {
+  size_t eth, wsq, cfgq, dws, total;
+};
+static DirectRegions direct_regions(const Prob& P, const Prob& Q, const DirectLayout& L, int64_t n) {
+  auto pad = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  DirectRegions g;
+  size_t off = pad((size_t)n * P.chain_stride * sizeof(double));
+  g.eth = off;  off += pad((size_t)Q.np * sizeof(double));
+  g.wsq = off;  off += pad((size_t)Q.chain_stride * sizeof(double));
+  g.cfgq = off; off += pad((size_t)P.N);
+  g.dws = off;  off += (size_t)n * L.stride * sizeof(double);
+  g.total = off;
+  return g;
+}
+
+peps_status peps_direct_workspace_bytes(const peps_desc* d, int64_t n_chains, int32_t chi_dl, size_t* bytes) {
+  if (!bytes || n_chains < 0) return PEPS_ERR_ARG;
+  Prob P, Q;
+  DirectLayout L;
+  peps_status s = direct_setup(d, chi_dl, P, Q, L);
+  if (s != PEPS_OK) return s;
+  *bytes = direct_regions(P, Q, L, n_chains).total;
+  return PEPS_OK;
+}
+
+peps_status peps_direct_sample(const peps_desc* d, const double* theta, int32_t n_chains, int32_t chi_dl,
+                               uint64_t seed, uint64_t draw, int32_t reweight, double* b_diag, int32_t update_b,
+                               uint8_t* configs, double* log_p, int32_t* status, void* ws, size_t ws_bytes,
+                               peps_trace* trace, peps_stream_t stream) {
+  if (n_chains < 0 || n_chains > (1 << 24)) return PEPS_ERR_ARG;
+  if ((reweight != 0 && reweight != 1) || (update_b != 0 && update_b != 1)) return PEPS_ERR_ARG;
+  Prob P, Q;
+  DirectLayout L;
+  peps_status s = direct_setup(d, chi_dl, P, Q, L);
+  if (s != PEPS_OK) return s;
+  if (n_chains == 0) return PEPS_OK;
+  if (!theta || !configs || !log_p || !ws || ((reweight || update_b) && !b_diag)) return PEPS_ERR_ARG;
+  const DirectRegions g = direct_regions(P, Q, L, n_chains);
+  if (ws_bytes < g.total) return PEPS_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  double* w = (double*)base;
+  double* eth = (double*)(base + g.eth);
+  double* wsq = (double*)(base + g.wsq);
+  uint8_t* cfgq = (uint8_t*)(base + g.cfgq);
+  double* dws = (double*)(base + g.dws);
+  const int n = n_chains;
+  TIMED(PEPS_K_DIRECT, launch_double_layer(P, Q, theta, eth, cfgq, st));
+  for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, compress_row(Q, 1, 1, r, eth, cfgq, wsq, status, st));
+  for (int r = 0; r < P.L1; ++r) {
+    TIMED(PEPS_K_DIRECT, launch_direct_row(P, Q, L, n, r, theta, eth, configs, w, wsq, dws, seed, draw, reweight,
+                                           b_diag, log_p, status, st));
+    if (r < P.L1 - 1) TIMED(PEPS_K_COMPRESS, compress_row(P, n, 0, r, theta, configs, w, status, st));
+  }
+  if (update_b) TIMED(PEPS_K_DIRECT, launch_update_b(P, n, configs, b_diag, st));
+  return PEPS_OK;
+}
+
+peps_status peps_importance_weights(int64_t n, const double* log_abs, const double* log_p, double* weights,
+                                    peps_stream_t stream) {
+  if (n < 1 || n > ((int64_t)1 << 30) || !log_abs || !log_p || !weights) return PEPS_ERR_ARG;
+  HIP_TRY(launch_importance_weights(n, log_abs, log_p, weights, (hipStream_t)stream));
+  return PEPS_OK;
+}
+
 peps_trace* peps_trace_create(int32_t capacity) {
   if (capacity < 1) return nullptr;
   peps_trace* t = new peps_trace;

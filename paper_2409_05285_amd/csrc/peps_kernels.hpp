@@ -74,6 +74,27 @@ hipError_t launch_su_step(const Prob& P, double* theta, double* lam, double tau,
                           hipStream_t st);
 hipError_t launch_su_absorb(const Prob& P, const double* theta, const double* lam, double* out, hipStream_t st);
 
+// Direct sampling (Appendix A): per-chain scratch of the draw kernel
+// (offsets and stride in doubles), built from the chain problem P and the
+// double layer's problem Q (d^2 = 1, bond D^2, boundary chi_dl).
+struct DirectLayout {
+  int64_t TDS, ENV;   // one doubled top tensor; one left / right environment
+  int64_t off_td, off_R, off_L, off_X0, off_X1, off_env, off_Px, stride;
+  int64_t x1;         // largest strip intermediate (doubles)
+};
+DirectLayout direct_layout(const Prob& P, const Prob& Q);
+// E_i = sum_S T_i[S] (x) T_i[S] into eth (Q's parameter layout); clears cfg_q [N].
+hipError_t launch_double_layer(const Prob& P, const Prob& Q, const double* theta, double* eth, uint8_t* cfg_q,
+                               hipStream_t st);
+// Row r of every chain's draw (conditionals, inverse-CDF pick, log p).
+hipError_t launch_direct_row(const Prob& P, const Prob& Q, const DirectLayout& L, int n, int r, const double* theta,
+                             const double* eth, uint8_t* configs, double* ws, const double* wsq, double* dws,
+                             uint64_t seed, uint64_t draw, int reweight, const double* b_diag, double* log_p,
+                             int32_t* status, hipStream_t st);
+hipError_t launch_update_b(const Prob& P, int n, const uint8_t* configs, double* b_diag, hipStream_t st);
+hipError_t launch_importance_weights(int64_t n, const double* log_abs, const double* log_p, double* w,
+                                     hipStream_t st);
+
 size_t sr_workspace_bytes(const Prob& P, int64_t n_s);
 // Bytes of the fixed per-GPU scratch of sr_cg_solve_noalloc, and its device
 // address on the current device (resolved once per device; nullptr if the

@@ -160,3 +160,32 @@ def test_smallest_workspace_layout():
     c = big.c()
     v = ctypes.c_void_p(8)
     assert LIB.peps_eval_batch(ctypes.byref(c), v, 4, v, v, v, None, None, v, small - 8, None, None) == -4
+
+
+def test_direct_sampling_entry_points_check_their_arguments():
+    """peps_direct_sample / peps_direct_workspace_bytes / peps_importance_weights
+    return argument, size and support errors before enqueuing anything."""
+    import paper_2409_05285_amd as p
+    from paper_2409_05285_amd._lib import LIB
+    desc = p.Desc(4, 4, 2, 4)
+    c = desc.c()
+    a = p.peps_direct_workspace_bytes(desc, 1, 16)
+    b = p.peps_direct_workspace_bytes(desc, 9, 16)
+    assert a > 0 and b > a
+    assert p.peps_direct_workspace_bytes(desc, 0, 16) < a
+    with pytest.raises(p.PepsError):
+        p.peps_direct_workspace_bytes(desc, 1, 0)
+    with pytest.raises(p.PepsError):     # D^6 chi^2 chi_dl intermediates beyond the kernel's limit
+        p.peps_direct_workspace_bytes(p.Desc(6, 6, 4, 16), 1, 64)
+    v = ctypes.c_void_p(0x1000)
+    call = lambda n, chi_dl, rw, bd, ub, ws_bytes: LIB.peps_direct_sample(
+        ctypes.byref(c), v, n, chi_dl, 1, 0, rw, bd, ub, v, v, v, v, ws_bytes, None, None)
+    assert call(-1, 16, 0, None, 0, 1 << 40) == -1
+    assert call(4, 0, 0, None, 0, 1 << 40) == -1
+    assert call(4, 16, 2, None, 0, 1 << 40) == -1
+    assert call(4, 16, 1, None, 0, 1 << 40) == -1      # reweighting needs b_diag
+    assert call(4, 16, 0, None, 1, 1 << 40) == -1      # so does its update
+    assert call(4, 16, 0, None, 0, 1000) == -4         # workspace too small
+    assert call(0, 16, 0, None, 0, 0) == 0             # nothing to draw
+    assert LIB.peps_importance_weights(0, v, v, v, None) == -1
+    assert LIB.peps_importance_weights(5, None, v, v, None) == -1

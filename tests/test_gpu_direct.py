@@ -1,0 +1,197 @@
+"""GPU parity of direct (autoregressive) sampling (Appendix A, Eqs. A2-A7)
+through the C ABI, against the oracle's sampler on the same seeded inputs.
+
+Bars: drawn configurations bit-exact for every chain whose uniforms all stay
+1e-9 away from a running sum of its conditionals (the oracle reports that
+distance); log p within 1e-10 relative; the dynamic diagonal weight within
+1e-14; importance weights within 1e-9 relative.  With boundaries that
+truncate nothing the draws are exact, which is checked by a chi^2 test
+against |rho|^2 / Z and by importance weights that are all equal.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, measure, network
+from oracle.lattice import MODEL_HUBBARD, Lattice
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TIE = 1e-9
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(lat, th, chi, chi_dl, seed, draw, cfg, lp, reweight=False, b_diag=1.0, chains=None):
+    bdl = direct.double_layer_bottoms(lat, th, chi_dl)
+    compared = 0
+    for ch in (range(cfg.shape[0]) if chains is None else chains):
+        r = direct.sample(lat, th, chi, chi_dl, seed, ch, draw, reweight=reweight, b_diag=b_diag, bdl=bdl)
+        if r["gap"] < TIE:
+            print("near-tie, chain", ch, r["gap"], flush=True)
+            continue
+        compared += 1
+        assert np.array_equal(cfg[ch], r["S"].astype(np.uint8)), (ch, cfg[ch], r["S"])
+        assert abs(lp[ch] - r["log_p"]) <= 1e-10 * max(1.0, abs(r["log_p"])), (ch, lp[ch], r["log_p"])
+    return compared
+
+
+def test_direct_p2_matches_oracle_4x4():
+    """4x4 Heisenberg, D = 2, chi = 4, chi_dl = 16 (the double layer's
+    bottom boundaries truncate), random unit tensors, 64 chains."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct p2 4x4 D2 chi4 chi_dl16")
+    L1 = L2 = 4
+    desc = p.Desc(L1, L2, 2, 4)
+    th = synth.theta_random_unit(L1, L2, 2, 2, seed=91)
+    cfg, lp, st = p.peps_direct_sample(desc, torch.tensor(th, device=dev), 64, 16, seed=31, draw=5)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    lat = Lattice(L1, L2, D=2, chi=4)
+    n = _compare(lat, th, 4, 16, 31, 5, cfg.cpu().numpy(), lp.cpu().numpy())
+    assert n >= 61
+
+
+def test_direct_p4_ragged_lattice_and_b_update():
+    """3x5 (odd width), D = 2, chi = 3, chi_dl = 6 (both truncating, tile
+    edges ragged), reweighted draws with b = 0.4 and the update of b after
+    the draw; then a second draw with the updated b."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct p4 3x5 D2 chi3 chi_dl6")
+    L1, L2, D, chi, chi_dl = 3, 5, 2, 3, 6
+    desc = p.Desc(L1, L2, D, chi)
+    th = synth.theta_random_unit(L1, L2, D, 2, seed=92)
+    theta = torch.tensor(th, device=dev)
+    b = torch.tensor([0.4], dtype=torch.float64, device=dev)
+    lat = Lattice(L1, L2, D=D, chi=chi)
+    b_host = 0.4
+    for draw in (0, 1):
+        cfg, lp, st = p.peps_direct_sample(desc, theta, 48, chi_dl, seed=37, draw=draw, reweight=True, b_diag=b,
+                                           update_b=True)
+        torch.cuda.synchronize()
+        assert p.check(st) == 0
+        cfg_h, lp_h = cfg.cpu().numpy(), lp.cpu().numpy()
+        n = _compare(lat, th, chi, chi_dl, 37, draw, cfg_h, lp_h, reweight=True, b_diag=b_host)
+        assert n >= 45
+        b_host = direct.update_b(lat, b_host, cfg_h.astype(np.int64))
+        assert abs(b.item() - b_host) <= 1e-14 * b_host, (b.item(), b_host)
+
+
+def test_direct_importance_weights_match_oracle():
+    """Eq. A7 weights from the device log|rho| of the drawn samples and the
+    device log p, against the oracle's amplitudes and log p."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct importance weights 3x4")
+    L1, L2, D, chi, chi_dl = 3, 4, 2, 4, 4
+    desc = p.Desc(L1, L2, D, chi)
+    th = synth.theta_random_unit(L1, L2, D, 2, seed=93)
+    theta = torch.tensor(th, device=dev)
+    b = torch.tensor([0.5], dtype=torch.float64, device=dev)
+    cfg, lp, st = p.peps_direct_sample(desc, theta, 16, chi_dl, seed=41, reweight=True, b_diag=b)
+    la, _, _, st2 = p.peps_eval_batch(desc, theta, cfg, want_e=False)
+    w = p.peps_importance_weights(la, lp)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    lat = Lattice(L1, L2, D=D, chi=chi)
+    bdl = direct.double_layer_bottoms(lat, th, chi_dl)
+    lr = []
+    for S in cfg.cpu().numpy().astype(np.int64):
+        m = measure.evaluate(lat, th, S, chi, want_O=False)
+        lr.append(2.0 * m["log_abs"] - direct.log_prob(lat, th, S, chi, chi_dl, reweight=True, b_diag=0.5, bdl=bdl))
+    lr = np.array(lr)
+    want = np.exp(lr - lr.max())
+    got = w.cpu().numpy()
+    assert np.all(np.abs(got - want) <= 1e-9 * want), (got, want)
+    assert got.max() == 1.0
+
+
+def test_direct_hubbard_parity_even_draws():
+    """Fermion sampler: 3x3 Hubbard, d^2 = 16, parity-even tensors, D = 2,
+    chi = 4, chi_dl = 16, reweighted (b = 0.5): draws against the oracle on
+    32 chains, and all 256 drawn configurations of even total parity."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct hubbard 3x3 d2=16")
+    L1 = L2 = 3
+    desc = p.Desc(L1, L2, 2, 4, d=4, model=p.MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0, fermionic=1)
+    th = synth.theta_random_parity_even(L1, L2, 2, 4, seed=94)
+    b = torch.tensor([0.5], dtype=torch.float64, device=dev)
+    cfg, lp, st = p.peps_direct_sample(desc, torch.tensor(th, device=dev), 256, 16, seed=43, reweight=True, b_diag=b)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    cfg_h = cfg.cpu().numpy()
+    par = np.array([[bin(int(x)).count("1") for x in row] for row in cfg_h]).sum(axis=1) % 2
+    assert np.all(par == 0)
+    lat = Lattice(L1, L2, D=2, chi=4, d=4, model=MODEL_HUBBARD, t=1.0, U=8.0, mu=4.0)
+    n = _compare(lat, th, 4, 16, 43, 0, cfg_h, lp.cpu().numpy(), reweight=True, b_diag=0.5, chains=range(32))
+    assert n >= 30
+
+
+def test_direct_exact_draws_2x2():
+    """2x2, D = 2, chi = 4, chi_dl = 16 truncate nothing, so p_2 = |rho|^2/Z:
+    4096 device draws pass a chi^2 test against the exact distribution, every
+    log p equals log(|rho|^2 / Z), and the importance weights are all 1."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct exact 2x2, 4096 draws")
+    desc = p.Desc(2, 2, 2, 4)
+    th = synth.theta_random_unit(2, 2, 2, 2, seed=95)
+    theta = torch.tensor(th, device=dev)
+    n = 4096
+    cfg, lp, st = p.peps_direct_sample(desc, theta, n, 16, seed=47)
+    la, _, _, st2 = p.peps_eval_batch(desc, theta, cfg, want_e=False)
+    w = p.peps_importance_weights(la, lp)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    lat = Lattice(2, 2, D=2, chi=4)
+    cfgs = network.all_configs(lat)
+    pr = np.array([network.amplitude(lat, th, S) ** 2 for S in cfgs])
+    pr /= pr.sum()
+    index = {tuple(S): k for k, S in enumerate(cfgs)}
+    ks = np.array([index[tuple(S)] for S in cfg.cpu().numpy().astype(np.int64)])
+    lp_h = lp.cpu().numpy()
+    assert np.all(np.abs(lp_h - np.log(pr[ks])) <= 1e-10 * np.maximum(1.0, np.abs(lp_h)))
+    counts = np.bincount(ks, minlength=len(cfgs)).astype(float)
+    exp_ = pr * n
+    mask = exp_ > 5
+    chi2 = float((((counts - exp_) ** 2)[mask] / exp_[mask]).sum())
+    dof = int(mask.sum()) - 1
+    assert chi2 < dof + 4.0 * math.sqrt(2 * dof) + 10, (chi2, dof)
+    assert np.all(np.abs(w.cpu().numpy() - 1.0) <= 1e-9)
+
+
+def test_direct_degenerate_calls():
+    """n = 0 enqueues nothing; a second call on the same workspace with fewer
+    chains gives the same draws for those chains (draws do not depend on the
+    batch)."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct degenerate calls")
+    desc = p.Desc(3, 3, 2, 4)
+    th = synth.theta_random_unit(3, 3, 2, 2, seed=96)
+    theta = torch.tensor(th, device=dev)
+    cfg0, lp0, st0 = p.peps_direct_sample(desc, theta, 0, 16, seed=3)
+    assert cfg0.shape == (0, 9)
+    a, la_, st = p.peps_direct_sample(desc, theta, 40, 16, seed=3, draw=2)
+    b, lb_, st2 = p.peps_direct_sample(desc, theta, 7, 16, seed=3, draw=2)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0 and p.check(st2) == 0
+    assert torch.equal(a[:7], b)
+    assert torch.equal(la_[:7], lb_)
