@@ -418,6 +418,49 @@ def simple_update_rate(p, torch, desc, steps=20, tau=0.01):
                     "temperatures before SR"}
 
 
+def direct_sampling_rate(p, torch, n=1024, draws=5, chi_dl=16):
+    """Direct (autoregressive) sampling, reweighted (p_4, dynamic diagonal
+    weight), at the 4x4 D = 2 chi = 4 shape of the small cooling workload:
+    device time per draw of n chains after two untimed draws, the kernel
+    split (per-row draw kernel vs the top-boundary and double-layer
+    compressions), and the rate of the importance weights' inputs: one
+    peps_eval_batch of the drawn samples."""
+    import synth
+    dev = torch.device("cuda:0")
+    desc = p.Desc(4, 4, 2, 4)
+    theta = torch.tensor(synth.theta_identity(4, 4, 2, 2, noise=0.05, seed=98), device=dev)
+    b = torch.tensor([1.0], dtype=torch.float64, device=dev)
+    ws = torch.empty(p.peps_direct_workspace_bytes(desc, n, chi_dl), dtype=torch.uint8, device=dev)
+    st = p.new_status(dev)
+    for k in range(2):
+        cfg, lp, _ = p.peps_direct_sample(desc, theta, n, chi_dl, 11, draw=k, reweight=True, b_diag=b, update_b=True,
+                                          status=st, ws=ws)
+    tr = p.Trace(64 * draws)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for k in range(draws):
+        cfg, lp, _ = p.peps_direct_sample(desc, theta, n, chi_dl, 11, draw=2 + k, reweight=True, b_diag=b,
+                                          update_b=True, status=st, ws=ws, trace=tr)
+    ev1.record()
+    torch.cuda.synchronize()
+    p.check(st, "direct sampling")
+    ms = ev0.elapsed_time(ev1) / draws
+    prof = tr.read()
+    tr.close()
+    la, _, _, st2 = p.peps_eval_batch(desc, theta, cfg, want_e=False)
+    w = p.peps_importance_weights(la, lp)
+    torch.cuda.synchronize()
+    p.check(st2, "direct sampling weights")
+    wh = w.cpu().numpy()
+    return {"workload": f"4x4 Heisenberg, D=2, chi=4, chi_dl={chi_dl}, {n} chains, p_4 with dynamic b",
+            "ms_per_draw": round(ms, 3), "samples_per_s": round(n / (ms / 1e3), 1), "draws": draws,
+            "kernel_ms_per_draw": {k: round(v[0] / draws, 3) for k, v in prof.items() if v[1]},
+            "b_diag_after": round(float(b.item()), 4),
+            "effective_sample_fraction": round(float(wh.sum() ** 2 / (wh ** 2).sum() / n), 4)}
+
+
 def energy_error(p, torch, desc64, descmx, theta, configs):
     """Local energies of the same samples and parameters from both
     precisions: relative error of the mean energy, the same error in units
@@ -602,6 +645,7 @@ def main():
                                   "note": "one-sweep step (1024 samples, SR on them) eager vs captured once as a "
                                           "HIP graph and replayed"}
         extras["simple_update"] = simple_update_rate(p, torch, desc64)
+        extras["direct_sampling"] = direct_sampling_rate(p, torch)
         extras["eval_samples_per_s"] = {"fp64": round(eval_rate(p, torch, desc64, p64.theta, p64.configs), 1),
                                         "mixed": round(eval_rate(p, torch, descmx, p64.theta, p64.configs), 1)}
         progress(f"extras done ({time.perf_counter() - t_start:.1f} s)")

@@ -317,8 +317,9 @@ peps_status peps_su_absorb(const peps_desc* desc, const double* theta, const dou
 /* ---- direct sampling (Appendix A, Eqs. A2-A7) -------------------------- */
 
 /* Workspace bytes of peps_direct_sample for n_chains chains and double-layer
-   boundary dimension chi_dl.  PEPS_ERR_UNSUPPORTED where the draw kernel's
-   per-chain intermediates (D^6 chi^2 chi_dl doubles) exceed 2^24 doubles or
+   boundary dimension chi_dl.  PEPS_ERR_UNSUPPORTED where one of the draw
+   kernel's per-chain intermediates (sized from the actual bond dimensions;
+   up to D^6 chi^2 chi_dl doubles in the bulk) exceeds 2^24 doubles or
    chi_dl D^2 exceeds the compression kernels' 512. */
 peps_status peps_direct_workspace_bytes(const peps_desc* desc, int64_t n_chains, int32_t chi_dl, size_t* bytes);
 

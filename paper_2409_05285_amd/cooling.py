@@ -32,7 +32,8 @@ from . import api
 
 
 def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, seed, cg_iters=200, rtol=1e-10,
-         step0=0, gsweep0=0, log=None, observables=False, su_steps=0, alpha_switch_beta=None):
+         step0=0, gsweep0=0, log=None, observables=False, su_steps=0, alpha_switch_beta=None, sampler="metropolis",
+         chi_dl=None, reweight=True, b_diag0=1.0):
     """Run n_steps SR steps; theta (float64 [N_p], device) and configs (uint8
     [n_chains, N], device) are updated in place.  `log`: a text stream that
     receives one JSON line per step.  Returns the list of records:
@@ -53,7 +54,16 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
     su_steps > 0: first that many simple-update steps of tau from unit bond
     weights (the high-temperature alternative to SR; spin-1/2 Heisenberg with
     J2 = 0), the weights absorbed into theta, then n_steps SR steps numbered
-    from step0 + su_steps (so beta_phys keeps counting 4 tau per step)."""
+    from step0 + su_steps (so beta_phys keeps counting 4 tau per step).
+    sampler="direct": instead of Metropolis sweeps, every step draws
+    sweeps_per_step independent configurations per chain by direct sampling
+    (Appendix A; p_4 with the dynamic diagonal weight when reweight, else
+    p_2; double-layer boundary dimension chi_dl, default chi^2), evaluates
+    them, and weights every average and the SR metric by r = |rho|^2 / p
+    (Eq. A7).  The diagonal weight starts at b_diag0 and is updated on the
+    device after the last draw of each step; records then also hold
+    "b_diag" and "sampler", and accepted_per_sweep is None.  `configs`
+    receives the last draw."""
     n = configs.shape[0]
     S = int(sweeps_per_step)
     N = desc.N
@@ -76,6 +86,13 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
         torch.cuda.synchronize()
         api.check(status, "simple update")
         step0 = step0 + su_steps
+    direct = sampler == "direct"
+    if sampler not in ("metropolis", "direct"):
+        raise ValueError("sampler must be 'metropolis' or 'direct'")
+    if direct:
+        chi_dl = desc.chi * desc.chi if chi_dl is None else int(chi_dl)
+        b_diag = torch.tensor([float(b_diag0)], dtype=torch.float64, device=dev)
+        log_p = torch.empty(S * n, dtype=torch.float64, device=dev)
     records = []
     for step in range(step0, step0 + n_steps):
         beta_phys = 4.0 * tau * step
@@ -84,34 +101,49 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
             d = dataclasses.replace(desc, alpha=2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        n_accept.zero_()
-        api.peps_sample_sweep(d, theta, configs, seed, gsweep, S, n_accept=n_accept, status=status, out=out)
-        gsweep += S
-        la = out["log_abs"].view(S * n)
-        e = out["e_loc"].view(S * n)
         samples = out["configs"].view(S * n, N)
-        est = api.peps_sample_stats(d, e, n, log_abs=la)
+        w = None
+        if direct:
+            for k in range(S):
+                sl = slice(k * n, (k + 1) * n)
+                api.peps_direct_sample(d, theta, n, chi_dl, seed, draw=gsweep + k, reweight=reweight, b_diag=b_diag,
+                                       update_b=reweight and k == S - 1, status=status, out=(samples[sl], log_p[sl]))
+            configs.copy_(samples[(S - 1) * n:])
+            la, _, e, _ = api.peps_eval_batch(d, theta, samples, status=status)
+            O, _, _ = api.peps_grad_batch(d, theta, samples, status=status)
+            w = api.peps_importance_weights(la, log_p)
+        else:
+            n_accept.zero_()
+            api.peps_sample_sweep(d, theta, configs, seed, gsweep, S, n_accept=n_accept, status=status, out=out)
+            la = out["log_abs"].view(S * n)
+            e = out["e_loc"].view(S * n)
+            O = out["O"].view(S * n, nnz)
+        gsweep += S
+        wa = {"weights": w} if direct else {"log_abs": la}
+        est = api.peps_sample_stats(d, e, n, **wa)
         obs = None
         if observables:
             vals = api.peps_observables_batch(d, samples)
-            ost = api.peps_sample_stats(d, vals, n, log_abs=la)
-            f_mean, f_se, _ = api.nnn_spin_correlation(d, theta, samples, n_chains=n, log_abs=la)
+            ost = api.peps_sample_stats(d, vals, n, **wa)
+            f_mean, f_se, _ = api.nnn_spin_correlation(d, theta, samples, n_chains=n, **wa)
             obs = (ost, f_mean, f_se)
-        dtheta, _, stats, _ = api.sr_cg_solve(d, samples, out["O"].view(S * n, nnz), e, tau, eps, cg_iters, rtol,
-                                              log_abs=la, want_g=False, theta=theta, status=status)
+        dtheta, _, stats, _ = api.sr_cg_solve(d, samples, O, e, tau, eps, cg_iters, rtol, want_g=False, theta=theta,
+                                              status=status, **wa)
         dnorm = torch.linalg.vector_norm(dtheta)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         api.check(status, "cool")
         est = est.cpu().tolist()
         st = stats.cpu().tolist()
-        acc = (n_accept.sum(dim=0).to(torch.float64) / float(n * S)).cpu().tolist()
+        acc = None if direct else (n_accept.sum(dim=0).to(torch.float64) / float(n * S)).cpu().tolist()
         rec = {"step": step, "beta_phys": beta_phys, "alpha": d.alpha,
                "E_per_site": est[0][0] / (2 * N), "E_stderr": est[0][1] / (2 * N),
-               "accepted_per_sweep": {"h": acc[0], "site": acc[1], "v": acc[2]},
+               "accepted_per_sweep": None if acc is None else {"h": acc[0], "site": acc[1], "v": acc[2]},
                "cg_iters": int(st[2]), "cg_rel_residual": st[1] / st[3] if st[3] > 0 else 0.0,
                "cg_converged": st[4] == 0.0,
                "dtheta_norm": float(dnorm), "samples_per_s": n * S / wall, "gsweep": gsweep}
+        if direct:
+            rec["sampler"], rec["b_diag"] = "direct", float(b_diag.item())
         if obs is not None:
             ost, f_mean, f_se = obs
             ost = ost.cpu().tolist()

@@ -298,15 +298,36 @@ __global__ void __launch_bounds__(1024) k_importance_weights(int64_t n, const do
 }  // namespace
 
 DirectLayout direct_layout(const Prob& P, const Prob& Q) {
-  DirectLayout L;
-  const int64_t c2 = (int64_t)P.chi * P.chi, D2 = (int64_t)P.D * P.D, cq = Q.chi;
+  // sizes from the actual bond dimensions of every site of every row (the
+  // compressed tops of P, the compressed double-layer bottoms of Q)
+  Geo g, gq;
+  build_geo(P, g);
+  build_geo(Q, gq);
+  int64_t tds = 1, env = 1, x0 = 1, x1 = 1, bs2 = 1;
+  auto mx = [](int64_t& m, int64_t v) { m = v > m ? v : m; };
+  for (int r = 0; r < P.L1; ++r)
+    for (int c = 0; c < P.L2; ++c) {
+      const int64_t ta = r ? (int64_t)g.ba[0][r - 1][c] * g.ba[0][r - 1][c] : 1;
+      const int64_t tb = r ? (int64_t)g.bb[0][r - 1][c] * g.bb[0][r - 1][c] : 1;
+      int Dl, Du, Dr, Dd;
+      leg_dims(P, r, c, Dl, Du, Dr, Dd);
+      const int64_t nl = Dl * Dl, nu = Du * Du, nr = Dr * Dr, nd = Dd * Dd;
+      const bool below = r + 1 <= P.L1 - 1;
+      const int64_t qa = below ? gq.ba[1][r + 1][c] : 1, qb = below ? gq.bb[1][r + 1][c] : 1;
+      mx(tds, ta * nu * tb);
+      mx(env, ta * nl * qa);           // L_c and R_c
+      mx(env, tb * nr * qb);           // L_{c+1} and R_{c+1}
+      mx(x0, qa * nd * tb * nr);       // right step, first stage
+      mx(x1, nl * nu * qa * tb);       // right step, second stage
+      mx(x0, nl * qa * nu * tb);       // left step and site environment, first stage
+      mx(x1, qa * tb * nr * nd);       // left step, second stage
+      mx(x1, nl * nu * tb * nd * qb);  // site environment, second stage
+      mx(bs2, nl * nu * nr * nd);
+    }
   auto pad = [](int64_t x) { return (x + 31) & ~(int64_t)31; };
-  L.TDS = pad(c2 * D2 * c2);
-  L.ENV = pad(c2 * D2 * cq);
-  const int64_t bs2 = D2 * D2 * D2 * D2;
-  // strip intermediates: lstep1 / rstep1 need D^4 chi^2 chi_dl each, the
-  // site environment's second stage D^6 chi^2 chi_dl
-  const int64_t x0 = D2 * D2 * c2 * cq, x1 = D2 * D2 * D2 * c2 * cq;
+  DirectLayout L;
+  L.TDS = pad(tds);
+  L.ENV = pad(env);
   int64_t off = 0;
   L.off_td = off;  off += (int64_t)P.L2 * L.TDS;
   L.off_R = off;   off += (int64_t)(P.L2 + 1) * L.ENV;
@@ -316,7 +337,8 @@ DirectLayout direct_layout(const Prob& P, const Prob& Q) {
   L.off_env = off; off += pad(bs2);
   L.off_Px = off;  off += pad(bs2);
   L.stride = off;
-  L.x1 = x1;
+  L.x1 = x0 > x1 ? x0 : x1;
+  if (bs2 > L.x1) L.x1 = bs2;
   return L;
 }
 
