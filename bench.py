@@ -246,6 +246,8 @@ class Path:
         # and library call; one call per chunk of chains with --chunk)
         calls = -(-n // args.chunk) if args.chunk and args.chunk < n else 1
         self.trace = p.Trace(16 * desc.L1 * args.sweeps * calls + 64)
+        if getattr(args, "progress", False):
+            self.trace.on_progress(f"{desc.L1}x{desc.L2} D={desc.D} chi={desc.chi}")
         self.out = None
 
     def _buffers(self, S):
@@ -418,6 +420,77 @@ def simple_update_rate(p, torch, desc, steps=20, tau=0.01):
                     "temperatures before SR"}
 
 
+UNEVEN_SHAPES = [(6, 4, 16), (8, 6, 36), (10, 6, 36), (16, 8, 64)]   # L (square, OBC), D, chi
+
+
+def uneven_batch(p, torch, args, seed):
+    """The uneven batch of Heisenberg lattices 6x6 (D=4, chi=16), 8x8 and
+    10x10 (D=6, chi=36) and 16x16 (D=8, chi=64), args.chains chains each,
+    mixed precision: one step per lattice (one sweep with its measurement,
+    then SR with args.cg_iters CG iterations and the update), the four step
+    sequences enqueued at once on four HIP streams so that their kernels
+    share the GPU.  Each lattice is timed by events on its own stream, the
+    batch by the wall clock around all four; a progress line (the library's
+    stderr printer) as each traced launch completes.  The largest lattice uses the smallest workspace
+    layout (its full layout would not fit beside the others)."""
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.chains
+    jobs = []
+    for k, (L, D, chi) in enumerate(UNEVEN_SHAPES):
+        if L > args.uneven_max_L:
+            continue
+        desc = p.Desc(L, L, D, chi, precision=p.PREC_MIXED)
+        kind = "min" if chi * D > 256 else "sweep"
+        job = {"L": L, "D": D, "chi": chi, "desc": desc,
+               "theta": torch.tensor(synth.theta_random_unit(L, L, D, 2, seed=104 + k), device=dev),
+               "configs": torch.tensor(synth.configs_diagonal(n, L * L, 2, seed=7 + k), device=dev),
+               "ws": torch.empty(p.workspace_bytes(desc, n, kind), dtype=torch.uint8, device=dev),
+               "ws_sr": torch.empty(p.workspace_bytes(desc, n, "sr"), dtype=torch.uint8, device=dev),
+               "status": p.new_status(dev), "stream": torch.cuda.Stream(),
+               "ev": (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)),
+               "trace": p.Trace(64 * L + 64), "layout": kind}
+        nnz = p.peps_orow_count(desc)
+        job["out"] = {"log_abs": torch.empty((1, n), dtype=torch.float64, device=dev),
+                      "sign": torch.empty((1, n), dtype=torch.int8, device=dev),
+                      "e_loc": torch.empty((1, n), dtype=torch.float64, device=dev),
+                      "O": torch.empty((1, n, nnz), dtype=torch.float64, device=dev),
+                      "configs": torch.empty((1, n, L * L), dtype=torch.uint8, device=dev)}
+        job["trace"].on_progress(f"uneven batch {L}x{L} D={D} chi={chi}")
+        jobs.append(job)
+    torch.cuda.synchronize()
+    progress(f"uneven batch: {len(jobs)} lattices x {n} chains set up, "
+             f"{torch.cuda.memory_allocated() / 2 ** 30:.1f} GiB allocated")
+    t0 = time.perf_counter()
+    for job in jobs:
+        with torch.cuda.stream(job["stream"]):
+            d, o = job["desc"], job["out"]
+            job["ev"][0].record()
+            p.peps_sample_sweep(d, job["theta"], job["configs"], seed, 0, 1, status=job["status"], out=o,
+                                ws=job["ws"], trace=job["trace"])
+            p.sr_cg_solve(d, o["configs"][0], o["O"][0], o["e_loc"][0], args.tau, args.eps, args.cg_iters, 1e-10,
+                          want_g=False, theta=job["theta"], status=job["status"], ws=job["ws_sr"],
+                          trace=job["trace"])
+            job["ev"][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rows = []
+    for job in jobs:
+        p.check(job["status"], f"uneven batch {job['L']}x{job['L']}")
+        ms = job["ev"][0].elapsed_time(job["ev"][1])
+        job["trace"].on_progress(None)
+        prof = job["trace"].read()
+        rows.append({"lattice": [job["L"], job["L"]], "D": job["D"], "chi": job["chi"], "chains": n,
+                     "workspace_layout": "smallest" if job["layout"] == "min" else "full",
+                     "ms": round(ms, 1), "samples_per_s": round(n / (ms / 1e3), 2),
+                     "kernel_ms": {k: round(v[0], 1) for k, v in prof.items() if v[1]}})
+        job["trace"].close()
+    return {"lattices": rows, "wall_s": round(wall, 2),
+            "total_samples_per_s": round(n * len(jobs) / wall, 2),
+            "note": "one step per lattice (sweep + measurement + SR), four streams in flight at once; per-lattice "
+                    "times by events on each stream"}
+
+
 def direct_sampling_rate(p, torch, n=1024, draws=5, chi_dl=16):
     """Direct (autoregressive) sampling, reweighted (p_4, dynamic diagonal
     weight), at the 4x4 D = 2 chi = 4 shape of the small cooling workload:
@@ -539,6 +612,12 @@ def main():
                     help="with --only and --sweeps 1: sweep the chains in library calls of this many chains, with a "
                          "progress line after each (large lattices), each chunk from its own seed")
     ap.add_argument("--graph-steps", type=int, default=3, help="steps of each kind timed by --graph")
+    ap.add_argument("--uneven", action="store_true",
+                    help="only the uneven batch of lattices (6x6, 8x8, 10x10, 16x16; --chains each) on four streams")
+    ap.add_argument("--uneven-max-L", type=int, default=16,
+                    help="with --uneven: only the lattices of at most this side length")
+    ap.add_argument("--progress", action="store_true",
+                    help="a progress line as each traced launch completes (long calls on large lattices)")
     ap.add_argument("--cg-iters", type=int, default=200)
     ap.add_argument("--tau", type=float, default=0.02)
     ap.add_argument("--eps", type=float, default=1e-4)
@@ -593,6 +672,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.uneven:
+        res = uneven_batch(p, torch, args, seed)
+        res["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+        print(json.dumps(res), flush=True)
+        return
     if args.chunk and args.sweeps != 1:
         print("--chunk needs --sweeps 1", file=sys.stderr)
         sys.exit(2)

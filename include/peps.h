@@ -391,6 +391,25 @@ peps_trace* peps_trace_create(int32_t capacity);
 /* Host: releases the events and the handle (NULL is a no-op). */
 void peps_trace_destroy(peps_trace* trace);
 
+/* Progress hook of a trace: fn(user, kernel_class, launch) is called once
+   each timed launch of a call that receives the trace has completed (the
+   library enqueues it after the launch's closing event with
+   hipLaunchHostFunc on the call's stream; launch counts the trace's launches
+   from 0 since its last read).  It runs on a HIP runtime thread, holds up
+   later work of that stream while it runs, and must neither call HIP nor
+   wait for anything the caller's thread may hold while it waits on the
+   stream (an interpreter lock, say).  NULL fn removes the hook.
+   PEPS_ERR_ARG for a NULL trace.  For long calls on large lattices, where
+   one call can run for minutes. */
+typedef void (*peps_progress_fn)(void* user, int32_t kernel_class, int32_t launch);
+peps_status peps_trace_set_progress(peps_trace* trace, peps_progress_fn fn, void* user);
+
+/* A ready-made hook: writes one line "[peps] <user> class <kernel_class>
+   launch <launch> done (<t> s)" to stderr and flushes it (user: a
+   NUL-terminated label, or NULL; t: seconds since the first line the
+   process printed). */
+void peps_progress_stderr(void* user, int32_t kernel_class, int32_t launch);
+
 /* Host: synchronises the recorded events and adds, per kernel class, the
    summed duration in milliseconds to ms[PEPS_N_KCLASS] and the number of
    timed launches (one sr_cg_solve call counts as one) to

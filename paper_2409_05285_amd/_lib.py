@@ -100,6 +100,10 @@ def _load():
     lib.peps_trace_destroy.restype = None
     lib.peps_trace_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
     lib.peps_trace_read.restype = c_int32
+    lib.peps_trace_set_progress.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.peps_trace_set_progress.restype = c_int32
+    lib.peps_progress_stderr.argtypes = [c_void_p, c_int32, c_int32]
+    lib.peps_progress_stderr.restype = None
     return lib
 
 
@@ -109,7 +113,8 @@ EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_works
            "sr_cg_solve_noalloc",
            "peps_vjp_batch", "peps_observables_batch", "peps_sample_stats", "peps_simple_update",
            "peps_su_absorb", "peps_direct_workspace_bytes", "peps_direct_sample", "peps_importance_weights",
-           "peps_trace_create", "peps_trace_destroy", "peps_trace_read"]
+           "peps_trace_create", "peps_trace_destroy", "peps_trace_read", "peps_trace_set_progress",
+           "peps_progress_stderr"]
 SR_STATIC_BYTES = 64 << 20   # scratch of sr_cg_solve_noalloc per GPU
 SR_NSTATS = 5   # sr_cg_solve stats: Ebar, |r|, iterations, |b|, not-converged flag
 KCLASS = ["compress", "moves1", "moves2", "meas1", "meas2", "final", "sr", "direct"]

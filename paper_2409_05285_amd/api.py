@@ -185,13 +185,30 @@ class Trace:
         _raise(LIB.peps_trace_read(self.h, ms, cnt), "peps_trace_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KCLASS)}
 
+    def on_progress(self, label):
+        """A line "[peps] <label> class <k> launch <i> done" on stderr as
+        each traced launch completes (the library's own C printer, so the
+        hook never enters Python while a thread may be waiting on the
+        stream); None removes it."""
+        if label is None:
+            self._label = None
+            _raise(LIB.peps_trace_set_progress(self.h, None, None), "peps_trace_set_progress")
+            return
+        self._label = ctypes.create_string_buffer(str(label).encode())   # kept alive with the trace
+        fn = ctypes.cast(LIB.peps_progress_stderr, ctypes.c_void_p)
+        _raise(LIB.peps_trace_set_progress(self.h, fn, ctypes.cast(self._label, ctypes.c_void_p)),
+               "peps_trace_set_progress")
+
     def close(self):
         if self.h:
             LIB.peps_trace_destroy(self.h)
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the library may already be gone
+            pass
 
 
 def _tr(trace):

@@ -1,8 +1,10 @@
 // C ABI of the library: descriptor validation, workspace layout, and the
 // launch sequences of the device calls (declared in include/peps.h).
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <vector>
 
 #include "peps_chain.hpp"
@@ -16,6 +18,15 @@ struct peps_trace {
   int capacity = 0, used = 0;
   std::vector<hipEvent_t> a, b;
   std::vector<int> cls;
+  // progress hook: one payload per launch slot (stable addresses)
+  struct Note {
+    peps_progress_fn fn;
+    void* user;
+    int32_t cls, launch;
+  };
+  peps_progress_fn fn = nullptr;
+  void* user = nullptr;
+  std::vector<Note> notes;
 };
 
 namespace {
@@ -142,7 +153,20 @@ struct TraceScope {
     (void)hipEventRecord(t->a[idx], st);
   }
   ~TraceScope() {
-    if (idx >= 0) (void)hipEventRecord(t->b[idx], st);
+    if (idx < 0) return;
+    (void)hipEventRecord(t->b[idx], st);
+    if (t->fn) {
+      peps_trace::Note& n = t->notes[idx];
+      n.fn = t->fn;
+      n.user = t->user;
+      n.cls = t->cls[idx];
+      n.launch = idx;
+      (void)hipLaunchHostFunc(st, &TraceScope::notify, &n);
+    }
+  }
+  static void notify(void* p) {
+    const peps_trace::Note* n = (const peps_trace::Note*)p;
+    n->fn(n->user, n->cls, n->launch);
   }
 };
 
@@ -564,6 +588,7 @@ peps_trace* peps_trace_create(int32_t capacity) {
   t->a.assign(capacity, nullptr);
   t->b.assign(capacity, nullptr);
   t->cls.assign(capacity, 0);
+  t->notes.assign(capacity, peps_trace::Note{nullptr, nullptr, 0, 0});
   for (int i = 0; i < capacity; ++i) {
     if (hipEventCreate(&t->a[i]) != hipSuccess || hipEventCreate(&t->b[i]) != hipSuccess) {
       peps_trace_destroy(t);
@@ -580,6 +605,22 @@ void peps_trace_destroy(peps_trace* t) {
   for (auto e : t->b)
     if (e) (void)hipEventDestroy(e);
   delete t;
+}
+
+void peps_progress_stderr(void* user, int32_t kernel_class, int32_t launch) {
+  // seconds since the first line this process printed
+  static const auto t0 = std::chrono::steady_clock::now();
+  const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fprintf(stderr, "[peps] %s class %d launch %d done (%.1f s)\n", user ? (const char*)user : "", (int)kernel_class,
+          (int)launch, t);
+  fflush(stderr);
+}
+
+peps_status peps_trace_set_progress(peps_trace* t, peps_progress_fn fn, void* user) {
+  if (!t) return PEPS_ERR_ARG;
+  t->fn = fn;
+  t->user = user;
+  return PEPS_OK;
 }
 
 peps_status peps_trace_read(peps_trace* t, double* ms, int64_t* launches) {
