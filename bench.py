@@ -538,9 +538,10 @@ def energy_error(p, torch, desc64, descmx, theta, configs):
     """Local energies of the same samples and parameters from both
     precisions: relative error of the mean energy, the same error in units
     of the Monte Carlo standard error, per-sample relative errors (scale
-    max(|E_i|, mean |E|)), and the fraction of samples the mixed path
-    measured again in FP64 (their local energies equal the FP64 path's bit
-    for bit, the others differ by FP32 rounding)."""
+    max(|E_i|, mean |E|)), and the fraction of samples whose mixed local
+    energy equals the FP64 one bit for bit (those whose every row strip the
+    mixed path measured again in FP64, or whose FP32 rounding happened to
+    cancel)."""
     import numpy as np
     _, _, e64, s1 = p.peps_eval_batch(desc64, theta, configs)
     _, _, emx, s2 = p.peps_eval_batch(descmx, theta, configs)
@@ -558,7 +559,7 @@ def energy_error(p, torch, desc64, descmx, theta, configs):
             "sample_rel_median": float(np.median(rel)),
             "sample_rel_p99": float(np.quantile(rel, 0.99)),
             "sample_rel_max": float(rel.max()),
-            "fp64_remeasured_fraction": float(np.mean(emx == e64))}
+            "fp64_equal_fraction": float(np.mean(emx == e64))}
 
 
 def cooled_state(p, torch, L1, L2, D, chi, n, steps, sweeps, tau, eps, cg_iters, seed):

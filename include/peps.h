@@ -86,14 +86,16 @@ typedef struct {
   double t, U, mu;   /* Hubbard parameters (Benchmark section, Eq. hubbard_model)  */
   int32_t precision; /* PEPS_PREC_*: FP64 throughout, or FP32 strip contractions
                         with FP64 truncation / reductions / log-scales.  In the
-                        mixed form every measurement (log|psi|, E_loc, O row)
-                        also estimates its own rounding error from the FP32
-                        strips; a sample whose local-energy estimate exceeds
-                        5e-5 max(|E_loc|, mean |E_loc| of the call's batch)
-                        has its local energy measured again with the FP64
-                        strips, and one whose strip-amplitude estimate exceeds
-                        3e-5 (relative) every output, so those outputs equal
-                        the FP64 path's.  Metropolis ratios stay FP32.        */
+                        mixed form every row strip of a measurement also
+                        estimates its own rounding error; a one-row strip
+                        whose amplitude estimate exceeds 3e-5 (relative) is
+                        measured again with the FP64 strips together with its
+                        O rows (and log|psi| and the sign when it is the last
+                        row), and then, while a sample's local-energy estimate
+                        over its remaining FP32 strips exceeds 5e-5 max(|E_loc|,
+                        mean |E_loc| of the call's batch), its strip of largest
+                        contribution is measured again for the energy.
+                        Metropolis ratios stay FP32.                          */
   int32_t alpha;     /* sampling weight |rho|^alpha: 2, or 1 (Appendix A, Eq. A1)  */
   int32_t fermionic; /* 0: plain tensors.  1 (Hubbard only): the tensors are
                         Z2-graded and parity-even (Method section, fPEPS

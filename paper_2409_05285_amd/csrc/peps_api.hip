@@ -180,14 +180,15 @@ hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* thet
 }
 
 // Mixed precision: the FP32 copy of theta, placed after the chain
-// workspaces, then the list of chains to measure again in FP64 (count and
-// up to n chain indices).
+// workspaces, then the list of row strips to measure again in FP64 (count
+// and up to 2 L1 - 1 items per chain).
 size_t theta32_bytes(const Prob& P) { return P.mixed ? (size_t)((P.np + 63) & ~(int64_t)63) * sizeof(float) : 0; }
 float* theta32_ptr(const Prob& P, double* ws, int64_t n) {
   return P.mixed ? (float*)(ws + (size_t)n * P.chain_stride) : nullptr;
 }
 size_t redo_list_bytes(const Prob& P, int64_t n) {
-  return P.mixed ? (size_t)((n + 1) * sizeof(int32_t) + 255) & ~(size_t)255 : 0;
+  // count, then up to 2 L1 - 1 row strips per chain
+  return P.mixed ? (size_t)((n * (2 * P.L1 - 1) + 1) * sizeof(int32_t) + 255) & ~(size_t)255 : 0;
 }
 int32_t* redo_list_ptr(const Prob& P, double* ws, int64_t n) {
   return P.mixed ? (int32_t*)((char*)(ws + (size_t)n * P.chain_stride) + theta32_bytes(P)) : nullptr;

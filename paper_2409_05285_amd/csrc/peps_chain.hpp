@@ -21,15 +21,20 @@ struct ChainWS {
 //   relative deviation of the strip amplitude recomputed at the column cuts,
 //   the largest u32-weighted cancellation of those cut dot products, and the
 //   sum over the row's local-energy terms of |coef rho(S') / rho|,
-//   [8 L1 + 2]            re-measure flag: 0 none, 1 the local energy, 2 the
-//                         amplitudes too (log|psi|, sign, O row),
+//   [8 L1 + 2]            re-measure flag: 0 none, 1 some strips for the
+//                         local energy only, 2 some one-row strips with
+//                         their O rows too,
 //   [8 L1 + 3]            the FP32 pass's local energy, [8 L1 + 4] its
-//                         error estimate.
+//                         error estimate,
+//   [8 L1 + 5 .. 8 L1 + 7] bit masks of the strips measured again in FP64:
+//                         one-row strips with their O rows (bit r), one-row
+//                         strips, two-row strips (bit r: rows r, r + 1).
 __host__ __device__ inline int epart_err1(const Prob& P) { return 2 * P.L1 + 2; }
 __host__ __device__ inline int epart_err2(const Prob& P) { return 5 * P.L1 + 2; }
 __host__ __device__ inline int epart_flag(const Prob& P) { return 8 * P.L1 + 2; }
 __host__ __device__ inline int epart_e32(const Prob& P) { return 8 * P.L1 + 3; }
-__host__ __device__ inline int epart_size(const Prob& P) { return 8 * P.L1 + 5; }
+__host__ __device__ inline int epart_mask(const Prob& P) { return 8 * P.L1 + 5; }
+__host__ __device__ inline int epart_size(const Prob& P) { return 8 * P.L1 + 8; }
 
 __device__ inline ChainWS chain_ws(const Prob& P, double* ws, int ch) {
   double* base = ws + (size_t)ch * P.chain_stride;

@@ -276,7 +276,10 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
   if (redo && ep[epart_flag(P)] == 0.0) return;
   const uint8_t* S = configs + (size_t)ch * P.N;
   const double la = ep[2 * P.L1];
-  const bool write_amp = !redo || ep[epart_flag(P)] == 2.0;
+  // log|psi| and the sign come from the last row's strip: rewritten when that
+  // strip was measured again for its amplitude (never for the energy alone,
+  // so that they do not depend on whether the energy was asked for)
+  const bool write_amp = !redo || ((((uint32_t)ep[epart_mask(P)]) >> (P.L1 - 1)) & 1u);
   if (write_amp) {
     if (log_abs) log_abs[out_off + ch] = la;
     if (sign) sign[out_off + ch] = (int8_t)ep[2 * P.L1 + 1];
@@ -338,17 +341,20 @@ __global__ void k_finalize(Prob P, int n, const uint8_t* configs, double* ws, do
   if (!isfinite(e)) set_status(status, PEPS_ERR_NONFINITE);
 }
 
-// Mixed precision: which samples of the batch are measured again in FP64.
-// Per strip, e = max(dev, kap) estimates the relative rounding error of its
-// amplitude (see the FP32 strip kernels).  A sample whose one-row strips
-// have e > AMP_TOL gets flag 2 (every output re-measured).  Otherwise its
-// local-energy error is estimated as sum over the strips of max(e, u32) a
-// (a: the summed magnitudes of the strip's terms), and a sample whose
-// estimate exceeds E_TOL max(|E_loc|, mean |E_loc|) (the scale of the
-// precision bar, the mean over the batch's finite local energies) gets
-// flag 1 (local energy only).  The flagged chains are listed in increasing
-// order: list[0] = count, list[1..count] = chains.  One workgroup, fixed
-// order; thread t owns a contiguous block of chains.
+// Mixed precision: which row strips of which samples are measured again in
+// FP64.  Per strip, e = max(dev, kap) estimates the relative rounding error
+// of its amplitude (see the FP32 strip kernels).  Every one-row strip with
+// e > AMP_TOL is measured again with its O rows (its amplitude sets those
+// rows, its in-row energy terms and, for the last row, log|psi|).  With the
+// local energy wanted, the sample's energy error is then estimated as the
+// sum over the strips not yet listed of max(e, u32) a (a: the summed
+// magnitudes of the strip's terms), and while it exceeds E_TOL max(|E_loc|,
+// mean |E_loc|) (the scale of the precision bar, the mean over the batch's
+// finite local energies) the strip of largest contribution is listed too
+// (energy only).  Items are listed per chain in increasing chain order, as
+// chain * 64 + kind (kind r < L1: one-row strip r; L1 + r: two-row strip
+// r): list[0] = count, then the items.  One workgroup, fixed order; thread
+// t owns a contiguous block of chains.
 __global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, int want_e, int32_t* list) {
   __shared__ double red[NT];
   __shared__ int cnt[NT];
@@ -372,26 +378,69 @@ __global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, in
   int mine = 0;
   for (int ch = c0; ch < c1; ++ch) {
     double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
-    double amp = 0.0, err = 0.0;
+    uint32_t m_amp = 0, m1 = 0, m2 = 0;
+    double err = 0.0;
+    bool bad = false;
     for (int r = 0; r < P.L1; ++r) {
       const double* q = ep + epart_err1(P) + 3 * r;
       const double e = fmax(q[0], q[1]);
-      amp = fmax(amp, e);
+      if (!(e <= AMP_TOL)) m_amp |= 1u << r;   // NaN included
       err += fmax(e, u32) * q[2];
+      bad = bad || isnan(e) || isnan(q[2]);
     }
     for (int r = 0; r + 1 < P.L1; ++r) {
       const double* q = ep + epart_err2(P) + 3 * r;
       err += fmax(fmax(q[0], q[1]), u32) * q[2];
+      bad = bad || isnan(q[0]) || isnan(q[1]) || isnan(q[2]);
     }
-    if (isnan(amp)) err = NAN;
+    if (bad) err = NAN;
     ep[epart_e32(P) + 1] = err;
-    const bool amp_ok = amp <= AMP_TOL;   // false for NaN
-    const bool e_ok = !want_e || err <= E_TOL * fmax(fabs(ep[epart_e32(P)]), mean_abs);
-    const double f = !amp_ok ? 2.0 : (e_ok ? 0.0 : 1.0);
-    ep[epart_flag(P)] = f;
-    mine += f != 0.0;
+    m1 = m_amp;
+    if (want_e) {
+      const double bar = E_TOL * fmax(fabs(ep[epart_e32(P)]), mean_abs);
+      if (bad) {
+        m1 = (P.L1 >= 32) ? 0xffffffffu : ((1u << P.L1) - 1u);
+        m2 = (P.L1 - 1 >= 32) ? 0xffffffffu : ((1u << (P.L1 - 1)) - 1u);
+      } else {
+        // the remaining estimate, then the largest remaining contributions
+        double rem = 0.0;
+        for (int r = 0; r < P.L1; ++r) {
+          const double* q = ep + epart_err1(P) + 3 * r;
+          if (!((m1 >> r) & 1u)) rem += fmax(fmax(q[0], q[1]), u32) * q[2];
+        }
+        for (int r = 0; r + 1 < P.L1; ++r) {
+          const double* q = ep + epart_err2(P) + 3 * r;
+          rem += fmax(fmax(q[0], q[1]), u32) * q[2];
+        }
+        while (!(rem <= bar)) {
+          double best = -1.0;
+          int bk = -1;
+          for (int r = 0; r < P.L1; ++r) {
+            if ((m1 >> r) & 1u) continue;
+            const double* q = ep + epart_err1(P) + 3 * r;
+            const double v = fmax(fmax(q[0], q[1]), u32) * q[2];
+            if (v > best) { best = v; bk = r; }
+          }
+          for (int r = 0; r + 1 < P.L1; ++r) {
+            if ((m2 >> r) & 1u) continue;
+            const double* q = ep + epart_err2(P) + 3 * r;
+            const double v = fmax(fmax(q[0], q[1]), u32) * q[2];
+            if (v > best) { best = v; bk = P.L1 + r; }
+          }
+          if (bk < 0) break;
+          if (bk < P.L1) m1 |= 1u << bk;
+          else m2 |= 1u << (bk - P.L1);
+          rem -= best;
+        }
+      }
+    }
+    ep[epart_mask(P)] = (double)m_amp;
+    ep[epart_mask(P) + 1] = (double)m1;
+    ep[epart_mask(P) + 2] = (double)m2;
+    ep[epart_flag(P)] = m_amp ? 2.0 : ((m1 | m2) ? 1.0 : 0.0);
+    mine += __popc(m1) + __popc(m2);
   }
-  // inclusive scan of the per-thread counts, then each thread lists its own
+  // inclusive scan of the per-thread item counts, then each thread lists its own
   cnt[tid] = mine;
   __syncthreads();
   for (int off = 1; off < NT; off <<= 1) {
@@ -401,8 +450,14 @@ __global__ void __launch_bounds__(NT) k_redo_flags(Prob P, int n, double* ws, in
     __syncthreads();
   }
   int pos = cnt[tid] - mine;
-  for (int ch = c0; ch < c1; ++ch)
-    if (ws[(size_t)ch * P.chain_stride + P.off_epart + epart_flag(P)] != 0.0) list[1 + pos++] = ch;
+  for (int ch = c0; ch < c1; ++ch) {
+    const double* ep = ws + (size_t)ch * P.chain_stride + P.off_epart;
+    const uint32_t m1 = (uint32_t)ep[epart_mask(P) + 1], m2 = (uint32_t)ep[epart_mask(P) + 2];
+    for (int r = 0; r < P.L1; ++r)
+      if ((m1 >> r) & 1u) list[1 + pos++] = ch * 64 + r;
+    for (int r = 0; r + 1 < P.L1; ++r)
+      if ((m2 >> r) & 1u) list[1 + pos++] = ch * 64 + P.L1 + r;
+  }
   if (tid == NT - 1) list[0] = cnt[NT - 1];
 }
 

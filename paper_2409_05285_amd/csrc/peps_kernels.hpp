@@ -50,14 +50,14 @@ hipError_t launch_meas1(const Prob& P, int n, int r, const double* theta, const 
                         double* ws, double* O_rows, int want_e, int32_t* status, hipStream_t st);
 hipError_t launch_meas2(const Prob& P, int n, int r, const double* theta, const float* t32, const uint8_t* configs,
                         double* ws, int32_t* status, hipStream_t st);
-// Mixed precision: FP64 measurement of the chains in `list` (device:
-// count, then chain indices), one persistent launch over their row strips.
+// Mixed precision: FP64 measurement of the row strips in `list` (device:
+// count, then items chain * 64 + kind), one persistent launch.
 hipError_t launch_remeasure(const Prob& P, int n, const double* theta, const uint8_t* configs, double* ws,
                             const int32_t* list, double* O_rows, int want_e, int32_t* status, hipStream_t st);
 hipError_t launch_finalize(const Prob& P, int n, const uint8_t* configs, double* ws, double* log_abs, int8_t* sign,
                            double* e_loc, int64_t out_off, int want_e, int redo, int32_t* status, hipStream_t st);
-// Mixed precision: flags of the samples to measure again in FP64, and their
-// list (list[0] = count, then the chains in increasing order).
+// Mixed precision: the row strips of the samples to measure again in FP64
+// (masks per sample) and their list (list[0] = count, then the items).
 hipError_t launch_redo_flags(const Prob& P, int n, double* ws, int want_e, int32_t* list, hipStream_t st);
 // PEPS_ERR_ARG in status if a digit of configs [n][N] is >= d^2.
 hipError_t launch_check_digits(const Prob& P, int64_t n, const uint8_t* configs, int32_t* status, hipStream_t st);

@@ -606,30 +606,26 @@ __global__ void __launch_bounds__(NT, 4) k_meas2(Prob P, int r, const T* __restr
   meas2_row<T>(P, sh, w, strip_bufs<T>(P, w), r, ch, theta, configs, status);
 }
 
-// Mixed precision: the FP64 measurement of the samples k_redo_flags listed
-// (list[0] = count, list[1..count] = chains in increasing order).  Every
-// (chain, row strip) pair is one work item; the workgroups of the grid take
-// the items round-robin, item j = (chain list[1 + j % count], strip
-// j / count), strips 0..L1-1 one-row and L1.. two-row, so that a few
-// flagged chains cost a few strip latencies instead of one launch per
-// strip.  Workgroup g uses chain g's strip scratch (the grid has at most n
-// workgroups).  Flag 2 also re-measures the O row; flag 1 only the local
-// energy.
+// Mixed precision: the FP64 measurement of the row strips k_redo_flags
+// listed (list[0] = count, then items chain * 64 + kind, kind r < L1 the
+// one-row strip r, L1 + r the two-row strip r).  The workgroups of the grid
+// take the items round-robin, so that a few listed strips cost a few strip
+// latencies instead of one launch per strip.  Workgroup g uses chain g's
+// strip scratch (the grid has at most n workgroups).  A one-row strip whose
+// amplitude estimate was above the bar also rewrites its O rows.
 __global__ void __launch_bounds__(NT, 4) k_remeasure(Prob P, const double* __restrict__ theta,
                                                      const uint8_t* configs, double* ws, const int32_t* list,
                                                      double* O_rows, int want_e, int32_t* status) {
   __shared__ StripShared<double> sh;
-  const int count = list[0];
-  const int kinds = want_e ? 2 * P.L1 - 1 : P.L1;
-  const int64_t items = (int64_t)count * kinds;
+  const int64_t items = list[0];
   const StripBufs<double> b = strip_bufs<double>(P, chain_ws(P, ws, blockIdx.x));
   for (int64_t j = blockIdx.x; j < items; j += gridDim.x) {
-    const int ch = list[1 + (int)(j % count)];
-    const int kind = (int)(j / count);
+    const int item = list[1 + j];
+    const int ch = item >> 6, kind = item & 63;
     const ChainWS w = chain_ws(P, ws, ch);
+    const bool with_O = ((((uint32_t)w.epart[epart_mask(P)]) >> kind) & 1u) != 0;
     if (kind < P.L1)
-      meas1_row<double>(P, sh, w, b, kind, ch, theta, configs, w.epart[epart_flag(P)] == 2.0 ? O_rows : nullptr,
-                        want_e, status);
+      meas1_row<double>(P, sh, w, b, kind, ch, theta, configs, with_O ? O_rows : nullptr, want_e, status);
     else
       meas2_row<double>(P, sh, w, b, kind - P.L1, ch, theta, configs, status);
     __syncthreads();

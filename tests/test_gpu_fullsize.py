@@ -146,9 +146,8 @@ def test_fullsize_mixed_energy_every_sample():
     of the full-size sweep, against the FP64 path on the same configurations
     and parameters: every sample within the mixed bar 1e-4 (E_loc relative to
     max(|E_i|, mean |E|); O relative to the row's largest entry), not only
-    the mean.  The samples whose FP32 error estimate crossed the re-measure
-    bar equal the FP64 values bit for bit; the three worst remaining ones are
-    also checked against the oracle."""
+    the mean.  The three worst samples not equal to the FP64 values bit for
+    bit are also checked against the oracle."""
     import paper_2409_05285_amd as p
     _say("full-size mixed vs fp64, every sample")
     dev = _dev()
@@ -169,7 +168,7 @@ def test_fullsize_mixed_energy_every_sample():
     rel = np.abs(emx - e64) / scale
     redone = emx == e64
     print(f"[mixed] E_loc rel err median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} "
-          f"max {rel.max():.2e}; re-measured in FP64: {redone.mean():.3f}", flush=True)
+          f"max {rel.max():.2e}; equal to FP64 bit for bit: {redone.mean():.3f}", flush=True)
     assert rel.max() <= 1e-4, (int(rel.argmax()), rel.max())
     assert np.all(np.abs(lmx - l64) <= 1e-4 * np.maximum(1.0, np.abs(l64)))
     O64, Omx = O64.cpu().numpy(), Omx.cpu().numpy()
