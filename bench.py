@@ -615,6 +615,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=3, help="steps of each kind timed by --graph")
     ap.add_argument("--uneven", action="store_true",
                     help="only the uneven batch of lattices (6x6, 8x8, 10x10, 16x16; --chains each) on four streams")
+    ap.add_argument("--direct", action="store_true",
+                    help="only the direct-sampling rate (4x4, D=2, chi=4, chi_dl=16, --chains draws per call)")
     ap.add_argument("--uneven-max-L", type=int, default=16,
                     help="with --uneven: only the lattices of at most this side length")
     ap.add_argument("--progress", action="store_true",
@@ -673,6 +675,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.direct:
+        res = direct_sampling_rate(p, torch, n=args.chains)
+        res["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+        print(json.dumps(res), flush=True)
+        return
     if args.uneven:
         res = uneven_batch(p, torch, args, seed)
         res["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
