@@ -242,3 +242,46 @@ def test_direct_sampling_cooling_2x2_matches_ed():
     print(f"[cool] p_2 at beta {last['beta_phys']:.2f}: E/N {last['E_per_site']:.5f} +- {last['E_stderr']:.5f} "
           f"ED {e_ed:.5f}", flush=True)
     assert last["E_per_site"] - e_ed > 10 * last["E_stderr"]
+
+
+def test_direct_product_state_closed_form_and_tiny_chi_dl():
+    """D = 1 (a product state, 3x4): the conditionals are the single-site
+    distributions T_i[x]^2 / sum_x T_i[x]^2 (p_2) or b(x) |T_i[x]| normalised
+    (p_4), so log p has a closed form; draws against the oracle.  Then the
+    smallest double-layer boundary, chi_dl = 1, on 3x3 D = 2 (every
+    double-layer bond truncated to one value): draws and log p against the
+    oracle, all finite."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct D=1 closed form, chi_dl=1")
+    L1, L2 = 3, 4
+    desc = p.Desc(L1, L2, 1, 1)
+    th = synth.theta_random_unit(L1, L2, 1, 2, seed=98)
+    lat = Lattice(L1, L2, D=1, chi=1)
+    for reweight, bd in ((False, 1.0), (True, 0.3)):
+        b = torch.tensor([bd], dtype=torch.float64, device=dev)
+        cfg, lp, st = p.peps_direct_sample(desc, torch.tensor(th, device=dev), 40, 1, seed=51, reweight=reweight,
+                                           b_diag=b)
+        torch.cuda.synchronize()
+        assert p.check(st) == 0
+        cfg_h, lp_h = cfg.cpu().numpy().astype(np.int64), lp.cpu().numpy()
+        for ch in range(40):
+            want = 0.0
+            for i in range(lat.N):
+                t = lat.site_tensor(th, i // L2, i % L2).reshape(4)
+                q = t * t / (t * t).sum()
+                if reweight:
+                    w = np.array([1.0 if x // 2 != x % 2 else bd for x in range(4)]) * np.sqrt(q)
+                    q = w / w.sum()
+                want += math.log(q[cfg_h[ch, i]])
+            assert abs(lp_h[ch] - want) <= 1e-12 * max(1.0, abs(want)), (ch, lp_h[ch], want)
+        n = _compare(lat, th, 1, 1, 51, 0, cfg.cpu().numpy(), lp_h, reweight=reweight, b_diag=bd)
+        assert n >= 38
+    desc = p.Desc(3, 3, 2, 4)
+    th = synth.theta_random_unit(3, 3, 2, 2, seed=99)
+    cfg, lp, st = p.peps_direct_sample(desc, torch.tensor(th, device=dev), 32, 1, seed=53)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    assert np.all(np.isfinite(lp.cpu().numpy()))
+    n = _compare(Lattice(3, 3, D=2, chi=4), th, 4, 1, 53, 0, cfg.cpu().numpy(), lp.cpu().numpy())
+    assert n >= 30

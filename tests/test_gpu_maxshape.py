@@ -7,7 +7,8 @@
   kernel's streamed paths (QR columns and Jacobi columns longer than its
   register batches) run; evaluation and O rows of two samples in FP64 against
   the oracle, at the FP64 bars of every other lattice (1e-10 on log|psi| and
-  E_loc, 1e-9 on O).
+  E_loc, 1e-9 on O); the same for the Hubbard model (d^2 = 16, parity-even
+  tensors).
 """
 import sys
 import time
@@ -108,6 +109,23 @@ def test_largest_boundary_shape():
     desc = p.Desc(6, 6, 8, 64)
     th = synth.theta_random_unit(6, 6, 8, 2, seed=7)
     cfg = synth.configs_sector(2, 36, 2, seed=46)
+    _check(p, lat, desc, th, cfg, 64, 1e-10, 1e-9, False)
+
+
+def test_hubbard_largest_boundary_shape():
+    """The Hubbard lattice at the largest boundary shape: 6x6, d^2 = 16, D =
+    8, chi = 64 (chi D = 512), t = 1, U = 8, mu = 4, Z2-graded parity-even
+    tensors declared (fermionic = 1), two even-parity configurations (equal
+    particle numbers in s and s'): FP64 evaluation and O rows against the
+    oracle at the FP64 bars, Jordan-Wigner hop signs included."""
+    import paper_2409_05285_amd as p
+    from oracle.lattice import MODEL_HUBBARD
+    _say("6x6 Hubbard D=8 chi=64 (chi D = 512)")
+    hub = dict(t=1.0, U=8.0, mu=4.0)
+    lat = Lattice(6, 6, D=8, chi=64, d=4, model=MODEL_HUBBARD, **hub)
+    desc = p.Desc(6, 6, 8, 64, d=4, model=p.MODEL_HUBBARD, fermionic=1, **hub)
+    th = synth.theta_random_parity_even(6, 6, 8, 4, seed=47)
+    cfg = synth.configs_sector(2, 36, 4, seed=48)
     _check(p, lat, desc, th, cfg, 64, 1e-10, 1e-9, False)
 
 
