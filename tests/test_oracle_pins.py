@@ -1088,3 +1088,89 @@ def test_direct_hubbard_draws_are_parity_even_and_exact():
         assert sum(bin(int(x)).count("1") for x in r["S"]) % 2 == 0
         want = math.log(network.amplitude(lat, th, r["S"]) ** 2 / Z)
         assert abs(r["log_p"] - want) <= 1e-10 * max(1.0, abs(want)), (r["S"], r["log_p"], want)
+
+
+def _bond_of_leg(lat, r, c, leg):
+    """Bond index on leg (0 l, 1 u, 2 r, 3 d) of site (r, c) in the storage
+    order of the bond weights (horizontal bonds row-major, then vertical
+    bonds row-major), or -1 on the open boundary."""
+    H = lat.L1 * (lat.L2 - 1)
+    if leg == 0:
+        return r * (lat.L2 - 1) + c - 1 if c > 0 else -1
+    if leg == 2:
+        return r * (lat.L2 - 1) + c if c < lat.L2 - 1 else -1
+    if leg == 1:
+        return H + (r - 1) * lat.L2 + c if r > 0 else -1
+    return H + r * lat.L2 + c if r < lat.L1 - 1 else -1
+
+
+def _weighted_site(lat, th, lam, r, c, skip):
+    T = np.array(lat.site_tensor(th, r, c))
+    for leg in range(4):
+        k = _bond_of_leg(lat, r, c, leg)
+        if k < 0 or leg == skip:
+            continue
+        shape = [1] * 5
+        shape[1 + leg] = T.shape[1 + leg]
+        T = T * lam[k][:T.shape[1 + leg]].reshape(shape)
+    return T
+
+
+def _cluster(lat, th, lam, a, b, horizontal):
+    """The two sites of a bond with the weights of every leg (their own
+    bond's once), as a matrix (S_a and a's other legs) x (S_b and b's)."""
+    (ra, ca), (rb, cb) = a, b
+    if horizontal:
+        k = _bond_of_leg(lat, ra, ca, 2)
+        Ta = _weighted_site(lat, th, lam, ra, ca, 2)
+        Tb = _weighted_site(lat, th, lam, rb, cb, 0)
+        X = np.einsum("slubd,b,tbURD->sludtURD", Ta, lam[k][:Ta.shape[3]], Tb)
+    else:
+        k = _bond_of_leg(lat, ra, ca, 3)
+        Ta = _weighted_site(lat, th, lam, ra, ca, 3)
+        Tb = _weighted_site(lat, th, lam, rb, cb, 1)
+        X = np.einsum("slurb,b,tLbRD->slurtLRD", Ta, lam[k][:Ta.shape[4]], Tb)
+    return X
+
+
+@pytest.mark.parametrize("start", ["random", "product_with_zero_weights"])
+def test_simple_update_truncation_is_eckart_young(start):
+    """The truncating branch of a bond update (and, in the second case, the
+    cut of zero weights): the two sites of the bond with every leg weighted
+    by its bond weights, after the update, times the largest singular value,
+    equal the best rank-D approximation of the gate applied to the same
+    weighted two-site tensor before it (Eckart-Young, by numpy's SVD of the
+    matrix built here from the definitions); the new weights are the kept
+    singular values over the largest.  2x3 lattice, D = 2, one horizontal and
+    one vertical bond."""
+    from oracle import simple_update as su
+    lat = Lattice(2, 3, D=2, chi=4)
+    rng = np.random.default_rng(88)
+    if start == "random":
+        th = synth.theta_random_unit(2, 3, 2, 2, seed=88)
+        lam = rng.uniform(0.2, 1.0, size=(su.n_bonds(lat), 2))
+        lam /= lam.max(axis=1, keepdims=True)
+    else:
+        th = _su_product_state(lat, 2, 89)
+        lam = np.ones((su.n_bonds(lat), 2))
+        su.su_step(lat, th, lam, 0.0)        # rank-1 bonds: weights (1, ~1e-16), below the cut
+        assert np.all(lam[:, 1] < su.LAMBDA_CUT)
+    G = su.gate(lat, 0.2, lat.J1).reshape(4, 4, 4, 4)
+    legbond = su._leg_bonds(lat)
+    for (i, j, li, lj, k) in su.bonds(lat):
+        a, b = divmod(i, lat.L2), divmod(j, lat.L2)
+        horizontal = a[0] == b[0]
+        X = _cluster(lat, th, lam, a, b, horizontal)
+        nd = X.ndim // 2
+        Y = np.tensordot(G, X, axes=([2, 3], [0, nd]))           # [S_a', S_b', a-legs..., b-legs...]
+        Y = np.moveaxis(Y, 1, nd)                                # [S_a', a-legs..., S_b', b-legs...]
+        M = Y.reshape(int(np.prod(Y.shape[:nd])), -1)
+        U, s, Vt = np.linalg.svd(M, full_matrices=False)
+        XD = (U[:, :2] * s[:2]) @ Vt[:2]
+        su.update_bond(lat, th, lam, i, j, li, lj, k, su.gate(lat, 0.2, lat.J1), legbond)
+        Z = _cluster(lat, th, lam, a, b, horizontal).reshape(M.shape) * s[0]
+        assert np.linalg.norm(Z - XD) <= 1e-12 * np.linalg.norm(XD), (i, j, np.linalg.norm(Z - XD))
+        np.testing.assert_allclose(lam[k], s[:2] / s[0], rtol=1e-12, atol=1e-15)
+        assert s[2] > 1e-6 * s[0]            # the branch truncated something
+        if k == 1:
+            break
