@@ -483,11 +483,12 @@ bool compress_in_lds(const Prob& P) { return compress_lds_bytes(P) <= COMPRESS_D
 hipError_t launch_compress(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                            double* ws, int32_t* status, hipStream_t st) {
   const size_t lds = compress_lds_bytes(P);
-  static size_t configured = 0;
-  if (lds > configured) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // beyond the default 64 KB of dynamic LDS the kernel's limit is raised on
+  // the current device, at every such launch (no state kept between calls)
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)COMPRESS_DYN_LDS_MAX);
     if (e != hipSuccess) return e;
-    configured = lds;
   }
   hipLaunchKernelGGL(k_compress, dim3(n), dim3(NT), lds, st, P, dir, r, theta, configs, ws, status);
   return hipGetLastError();
