@@ -106,7 +106,20 @@ typedef struct {
                         total parity then has amplitude exactly 0; the device
                         decides it from the digits in integer arithmetic and
                         reports it as a zero amplitude without contracting     */
+  int32_t compress_kernel; /* PEPS_COMPRESS_*: which kernel runs the boundary
+                        row compression.  AUTO (0): the register-resident one
+                        where its limits allow (chi D <= 64, D in {1, 2, 4}),
+                        else the LDS-resident one where its matrices fit
+                        128 KB, else the workspace-resident one.  REGISTER,
+                        LDS or WORKSPACE force one; a kernel whose limits the
+                        shape exceeds is PEPS_ERR_UNSUPPORTED.  All compute
+                        the same compression (Method section, boundary MPS
+                        with D_c = chi) and agree to rounding; the workspace
+                        layout (peps_workspace_bytes) follows the choice.
+                        See peps_autotune_compression.                        */
 } peps_desc;
+
+enum { PEPS_COMPRESS_AUTO = 0, PEPS_COMPRESS_REGISTER = 1, PEPS_COMPRESS_LDS = 2, PEPS_COMPRESS_WORKSPACE = 3 };
 
 /* Instrumentation handle (not part of the method): a caller-owned record of
    HIP event pairs around the kernel launches of the device calls that
@@ -315,6 +328,23 @@ peps_status peps_simple_update(const peps_desc* desc, double* theta, double* lam
    sampling and SR).  theta_out [N_p] may not alias theta. */
 peps_status peps_su_absorb(const peps_desc* desc, const double* theta, const double* lambdas, double* theta_out,
                            peps_stream_t stream);
+
+/* ---- launch tuning -------------------------------------------------------- */
+
+/* Host call (synchronises `stream`): times the boundary compression of n
+   chains' configurations with every compression kernel valid for desc's
+   shape (desc->compress_kernel is ignored): per candidate one untimed pass,
+   then `repeats` passes, each computing the top and the bottom boundaries
+   of every row, timed by HIP events.  ms[k] for k = PEPS_COMPRESS_REGISTER,
+   _LDS, _WORKSPACE (ms[0] unused) receives the mean milliseconds per pass,
+   or -1 where the kernel does not apply; *best the fastest.  ms [4] and
+   best are host pointers.  theta, configs, status, ws: as for
+   peps_eval_batch, with ws_bytes at least the largest of
+   peps_workspace_bytes(desc with compress_kernel = k, n, PEPS_WS_EVAL) over
+   the valid k (PEPS_ERR_WORKSPACE otherwise).  repeats in [1, 100]. */
+peps_status peps_autotune_compression(const peps_desc* desc, const double* theta, int32_t n, const uint8_t* configs,
+                                      int32_t repeats, double* ms, int32_t* best, int32_t* status, void* ws,
+                                      size_t ws_bytes, peps_stream_t stream);
 
 /* ---- direct sampling (Appendix A, Eqs. A2-A7) -------------------------- */
 

@@ -24,6 +24,8 @@ STATUS_HIP = -3
 MODEL_HEISENBERG, MODEL_HUBBARD = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 WS_EVAL, WS_GRAD, WS_SWEEP, WS_SR, WS_SU, WS_MIN = 0, 1, 2, 3, 4, 5
+COMPRESS_AUTO, COMPRESS_REGISTER, COMPRESS_LDS, COMPRESS_WORKSPACE = 0, 1, 2, 3
+COMPRESS_NAMES = {1: "register", 2: "lds", 3: "workspace"}
 N_OBS = 4   # peps_observables_batch: M_z, M_z^2, particle number, double occupancy
 
 
@@ -32,7 +34,7 @@ class PepsDesc(ctypes.Structure):
         ("L1", c_int32), ("L2", c_int32), ("d", c_int32), ("D", c_int32), ("chi", c_int32),
         ("model", c_int32),
         ("J1", c_double), ("J2", c_double), ("t", c_double), ("U", c_double), ("mu", c_double),
-        ("precision", c_int32), ("alpha", c_int32), ("fermionic", c_int32),
+        ("precision", c_int32), ("alpha", c_int32), ("fermionic", c_int32), ("compress_kernel", c_int32),
     ]
 
 
@@ -94,6 +96,9 @@ def _load():
     lib.peps_direct_sample.restype = c_int32
     lib.peps_importance_weights.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.peps_importance_weights.restype = c_int32
+    lib.peps_autotune_compression.argtypes = [P, c_void_p, c_int32, c_void_p, c_int32, POINTER(c_double),
+                                              POINTER(c_int32), c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.peps_autotune_compression.restype = c_int32
     lib.peps_trace_create.argtypes = [c_int32]
     lib.peps_trace_create.restype = c_void_p
     lib.peps_trace_destroy.argtypes = [c_void_p]
@@ -112,7 +117,7 @@ EXPORTS = ["peps_param_count", "peps_orow_count", "peps_slot_count", "peps_works
            "peps_status_string", "peps_eval_batch", "peps_grad_batch", "peps_sample_sweep", "sr_cg_solve",
            "sr_cg_solve_noalloc",
            "peps_vjp_batch", "peps_observables_batch", "peps_sample_stats", "peps_simple_update",
-           "peps_su_absorb", "peps_direct_workspace_bytes", "peps_direct_sample", "peps_importance_weights",
+           "peps_su_absorb", "peps_autotune_compression", "peps_direct_workspace_bytes", "peps_direct_sample", "peps_importance_weights",
            "peps_trace_create", "peps_trace_destroy", "peps_trace_read", "peps_trace_set_progress",
            "peps_progress_stderr"]
 SR_STATIC_BYTES = 64 << 20   # scratch of sr_cg_solve_noalloc per GPU

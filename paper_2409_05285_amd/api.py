@@ -35,10 +35,11 @@ class Desc:
     precision: int = _lib.PREC_FP64
     alpha: int = 2
     fermionic: int = 0
+    compress_kernel: int = _lib.COMPRESS_AUTO
 
     def c(self):
         return PepsDesc(self.L1, self.L2, self.d, self.D, self.chi, self.model, self.J1, self.J2, self.t,
-                        self.U, self.mu, self.precision, self.alpha, self.fermionic)
+                        self.U, self.mu, self.precision, self.alpha, self.fermionic, self.compress_kernel)
 
     @property
     def N(self):
@@ -415,6 +416,32 @@ def peps_sample_stats(desc: Desc, values, n_chains, log_abs=None, weights=None):
     _raise(LIB.peps_sample_stats(ctypes.byref(desc.c()), n_s // n_chains, int(n_chains), k, _ptr(v), _ptr(weights),
                                  _ptr(log_abs), _ptr(out), _stream()), "peps_sample_stats")
     return out
+
+
+def peps_autotune_compression(desc: Desc, theta, configs, repeats=2, status=None):
+    """Times the boundary compression of these configurations with every
+    compression kernel valid for desc's shape (a host call: synchronises).
+    Returns (best kernel, {kernel name: ms per full boundary pass})."""
+    theta = _theta(desc, theta)
+    configs = _configs(desc, configs)
+    _check_dev(theta, configs)
+    n = configs.shape[0]
+    dev = theta.device
+    need = 0
+    for k in (_lib.COMPRESS_REGISTER, _lib.COMPRESS_LDS, _lib.COMPRESS_WORKSPACE):
+        try:
+            need = max(need, peps_workspace_bytes(dataclasses.replace(desc, compress_kernel=k), n, _lib.WS_EVAL))
+        except PepsError:
+            pass
+    ws = _ws("chain", need, dev)
+    status = new_status(dev) if status is None else status
+    ms = (ctypes.c_double * 4)()
+    best = ctypes.c_int32(0)
+    code = LIB.peps_autotune_compression(ctypes.byref(desc.c()), _ptr(theta), n, _ptr(configs), int(repeats), ms,
+                                         ctypes.byref(best), _ptr(status), _ptr(ws), ws.numel(), _stream())
+    _raise(code, "peps_autotune_compression")
+    check(status, "peps_autotune_compression")
+    return int(best.value), {_lib.COMPRESS_NAMES[k]: ms[k] for k in (1, 2, 3) if ms[k] >= 0.0}
 
 
 def peps_direct_workspace_bytes(desc: Desc, n_chains, chi_dl) -> int:

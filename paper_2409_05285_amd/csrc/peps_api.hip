@@ -47,6 +47,7 @@ bool desc_ok(const peps_desc* d) {
   if (d->fermionic != 0 && d->fermionic != 1) return false;
   if (d->fermionic && d->model != PEPS_MODEL_HUBBARD) return false;
   if (d->precision != PEPS_PREC_FP64 && d->precision != PEPS_PREC_MIXED) return false;
+  if (d->compress_kernel < PEPS_COMPRESS_AUTO || d->compress_kernel > PEPS_COMPRESS_WORKSPACE) return false;
   if (!isfinite(d->J1) || !isfinite(d->J2) || !isfinite(d->t) || !isfinite(d->U) || !isfinite(d->mu)) return false;
   return true;
 }
@@ -99,7 +100,11 @@ Prob make_prob(const peps_desc* d, bool refl_store = true) {
   // the workspace-resident compression keeps one QR matrix and the R factor
   // of every site (it rebuilds a site's reflectors when it needs them); the
   // other kernels keep every site's absorbed tensor or reflectors
-  const bool big = !compress2_supported(P) && !compress_in_lds(P);
+  P.ckernel = d->compress_kernel != PEPS_COMPRESS_AUTO
+                  ? d->compress_kernel
+                  : (compress2_supported(P) ? PEPS_COMPRESS_REGISTER
+                                            : (compress_in_lds(P) ? PEPS_COMPRESS_LDS : PEPS_COMPRESS_WORKSPACE));
+  const bool big = P.ckernel == PEPS_COMPRESS_WORKSPACE;
   const bool rebuild = big && !refl_store;
   P.refl_store = rebuild ? 0 : 1;
   P.off_B = off;     off += pad(rebuild ? (int64_t)P.BS : (int64_t)P.L2 * P.BS);
@@ -133,6 +138,8 @@ peps_status device_support(const peps_desc* d, const Prob& P) {
   (void)d;
   if ((int64_t)P.chi * P.D > CD_MAX) return PEPS_ERR_UNSUPPORTED;   // compression column arrays
   if (P.chi > 255) return PEPS_ERR_UNSUPPORTED;                    // compressed bond table (8 bits)
+  if (P.ckernel == PEPS_COMPRESS_REGISTER && !compress2_supported(P)) return PEPS_ERR_UNSUPPORTED;
+  if (P.ckernel == PEPS_COMPRESS_LDS && !compress_in_lds(P)) return PEPS_ERR_UNSUPPORTED;
   return PEPS_OK;
 }
 
@@ -170,12 +177,11 @@ struct TraceScope {
   }
 };
 
-// Row compression: the register-resident kernel where its tile limits
-// allow, else the LDS kernel.
+// Row compression by the kernel the problem selected (make_prob).
 hipError_t compress_row(const Prob& P, int n, int dir, int r, const double* theta, const uint8_t* configs,
                         double* ws, int32_t* status, hipStream_t st) {
-  if (compress2_supported(P)) return launch_compress2(P, n, dir, r, theta, configs, ws, status, st);
-  if (compress_in_lds(P)) return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
+  if (P.ckernel == PEPS_COMPRESS_REGISTER) return launch_compress2(P, n, dir, r, theta, configs, ws, status, st);
+  if (P.ckernel == PEPS_COMPRESS_LDS) return launch_compress(P, n, dir, r, theta, configs, ws, status, st);
   return launch_compress_big(P, n, dir, r, theta, configs, ws, status, st);
 }
 
@@ -490,6 +496,73 @@ peps_status peps_su_absorb(const peps_desc* d, const double* theta, const double
   return PEPS_OK;
 }
 
+// ---- launch tuning ----------------------------------------------------------
+
+peps_status peps_autotune_compression(const peps_desc* d, const double* theta, int32_t n, const uint8_t* configs,
+                                      int32_t repeats, double* ms, int32_t* best, int32_t* status, void* ws,
+                                      size_t ws_bytes, peps_stream_t stream) {
+  if (!desc_ok(d) || n < 1 || n > (1 << 24) || repeats < 1 || repeats > 100) return PEPS_ERR_ARG;
+  if (!theta || !configs || !ms || !best || !ws) return PEPS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Prob cand[4];
+  bool ok[4] = {false, false, false, false};
+  for (int k = PEPS_COMPRESS_REGISTER; k <= PEPS_COMPRESS_WORKSPACE; ++k) {
+    peps_desc dk = *d;
+    dk.compress_kernel = k;
+    cand[k] = make_prob(&dk);
+    ok[k] = device_support(&dk, cand[k]) == PEPS_OK;
+    if (ok[k] && ws_bytes < chain_ws_bytes(cand[k], n)) return PEPS_ERR_WORKSPACE;
+  }
+  ms[0] = -1.0;
+  *best = 0;
+  double best_ms = 0.0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PEPS_ERR_HIP;
+  }
+  peps_status s = PEPS_OK;
+  double* w = (double*)ws;
+  for (int k = PEPS_COMPRESS_REGISTER; k <= PEPS_COMPRESS_WORKSPACE && s == PEPS_OK; ++k) {
+    ms[k] = -1.0;
+    if (!ok[k]) continue;
+    const Prob& P = cand[k];
+    auto pass = [&]() -> hipError_t {
+      for (int r = 0; r <= P.L1 - 2; ++r) {
+        hipError_t e = compress_row(P, n, 0, r, theta, configs, w, status, st);
+        if (e != hipSuccess) return e;
+      }
+      for (int r = P.L1 - 1; r >= 1; --r) {
+        hipError_t e = compress_row(P, n, 1, r, theta, configs, w, status, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    float t = 0.f;
+    if (launch_check_digits(P, n, configs, status, st) != hipSuccess || pass() != hipSuccess ||
+        hipEventRecord(e0, st) != hipSuccess) {
+      s = PEPS_ERR_HIP;
+      break;
+    }
+    for (int i = 0; i < repeats && s == PEPS_OK; ++i)
+      if (pass() != hipSuccess) s = PEPS_ERR_HIP;
+    if (s != PEPS_OK || hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      s = PEPS_ERR_HIP;
+      break;
+    }
+    ms[k] = (double)t / repeats;
+    if (*best == 0 || ms[k] < best_ms) {
+      *best = k;
+      best_ms = ms[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return s;
+}
+
 // ---- direct sampling (Appendix A) ------------------------------------------
 
 // The chain problem (FP64 strips), the double layer's problem (one digit,
@@ -506,6 +579,7 @@ static peps_status direct_setup(const peps_desc* d, int32_t chi_dl, Prob& P, Pro
   dq.D = d->D * d->D;
   dq.chi = chi_dl;
   dq.fermionic = 0;
+  dq.compress_kernel = PEPS_COMPRESS_AUTO;
   Q = make_prob(&dq);
   s = device_support(&dq, Q);
   if (s != PEPS_OK) return s;

@@ -33,6 +33,7 @@ struct Prob {
   int64_t off_Rst;                // its R factors of every site [L2][chi D][chi D] (rebuild layout)
   int refl_store;                 // workspace-resident compression: every site's reflectors kept (1)
                                   // or rebuilt from the stored R factors (0)
+  int ckernel;                    // boundary compression kernel: 1 register, 2 LDS, 3 workspace resident
   int mixed;                      // FP32 strip contractions
   int fermionic;                  // Z2-graded parity-even tensors (odd total parity => rho = 0)
 };

@@ -189,3 +189,23 @@ def test_direct_sampling_entry_points_check_their_arguments():
     assert call(0, 16, 0, None, 0, 0) == 0             # nothing to draw
     assert LIB.peps_importance_weights(0, v, v, v, None) == -1
     assert LIB.peps_importance_weights(5, None, v, v, None) == -1
+
+
+def test_compression_kernel_choice_is_validated():
+    """peps_desc.compress_kernel: values outside 0..3 make the descriptor
+    invalid; a forced kernel whose limits the shape exceeds is refused with
+    PEPS_ERR_UNSUPPORTED before anything is enqueued; the workspace size
+    follows the chosen kernel."""
+    import paper_2409_05285_amd as p
+    from paper_2409_05285_amd._lib import LIB
+    with pytest.raises(p.PepsError):
+        p.peps_param_count(p.Desc(4, 4, 2, 4, compress_kernel=4))
+    a = p.peps_workspace_bytes(p.Desc(4, 4, 2, 4, compress_kernel=1), 8, 0)
+    b = p.peps_workspace_bytes(p.Desc(4, 4, 2, 4, compress_kernel=3), 8, 0)
+    assert a == p.peps_workspace_bytes(p.Desc(4, 4, 2, 4), 8, 0) and b > a
+    v = ctypes.c_void_p(0x1000)
+    for desc in (p.Desc(4, 4, 3, 5, compress_kernel=1),      # D = 3: no register kernel
+                 p.Desc(6, 6, 4, 20, compress_kernel=2),     # chi D = 80 at D = 4: beyond the LDS kernel
+                 p.Desc(6, 6, 4, 20, compress_kernel=1)):    # and beyond the register kernel
+        c = desc.c()
+        assert LIB.peps_eval_batch(ctypes.byref(c), v, 4, v, v, v, v, v, v, 1 << 40, None, None) == -2
