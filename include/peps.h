@@ -109,8 +109,10 @@ typedef struct {
   int32_t compress_kernel; /* PEPS_COMPRESS_*: which kernel runs the boundary
                         row compression.  AUTO (0): the register-resident one
                         where its limits allow (chi D <= 64, D in {1, 2, 4}),
-                        else the LDS-resident one where its matrices fit
-                        128 KB, else the workspace-resident one.  REGISTER,
+                        except for calls on 512 or more chains with
+                        chi D^2 <= 64, which take the LDS-resident one; else
+                        the LDS-resident one where its matrices fit 128 KB,
+                        else the workspace-resident one.  REGISTER,
                         LDS or WORKSPACE force one; a kernel whose limits the
                         shape exceeds is PEPS_ERR_UNSUPPORTED.  All compute
                         the same compression (Method section, boundary MPS

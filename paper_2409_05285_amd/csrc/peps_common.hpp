@@ -34,6 +34,7 @@ struct Prob {
   int refl_store;                 // workspace-resident compression: every site's reflectors kept (1)
                                   // or rebuilt from the stored R factors (0)
   int ckernel;                    // boundary compression kernel: 1 register, 2 LDS, 3 workspace resident
+  int cauto;                      // the kernel was chosen automatically (the launch may refine it by batch size)
   int mixed;                      // FP32 strip contractions
   int fermionic;                  // Z2-graded parity-even tensors (odd total parity => rho = 0)
 };
