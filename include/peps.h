@@ -381,9 +381,11 @@ peps_status peps_direct_workspace_bytes(const peps_desc* desc, int64_t n_chains,
    updated after the draw to min(1, b (1/2 / f)^(1/N)), f the fraction of the
    drawn configurations with s = s' on every site (f = 0 counts as 1/4), so
    that repeated steps hold diagonal draws near half.  Strips run in FP64
-   whatever desc->precision says.  A chain whose marginals all vanish
-   records PEPS_ERR_ZERO_AMPLITUDE (non-finite ones PEPS_ERR_NONFINITE), gets
-   log_p = -inf and zero digits from that site on.  For fermionic descs the
+   whatever desc->precision says.  A chain whose marginals at a site all
+   vanish (or, with reweighting, whose only digits of nonzero marginal are
+   diagonal while *b_diag = 0) records PEPS_ERR_ZERO_AMPLITUDE (non-finite
+   marginals or b_diag PEPS_ERR_NONFINITE), gets log_p = -inf and zero
+   digits from that site on.  For fermionic descs the
    draw is not restricted to even parity: a parity-even ansatz gives odd
    configurations zero weight by itself, and otherwise an odd draw gets
    importance weight 0.  ws: peps_direct_workspace_bytes(desc, n_chains,

@@ -209,7 +209,8 @@ __global__ void __launch_bounds__(NT) k_direct_row(Prob P, Prob Q, DirectLayout 
         tot += p[x];
       }
       int x_pick = -1;
-      if (tot > 0.0 && isfinite(tot)) {
+      bool ok = tot > 0.0 && isfinite(tot);
+      if (ok) {
         for (int x = 0; x < P.d2; ++x) p[x] /= tot;
         if (reweight) {
           double s = 0.0;
@@ -217,8 +218,12 @@ __global__ void __launch_bounds__(NT) k_direct_row(Prob P, Prob Q, DirectLayout 
             p[x] = (ket_of(P, x) != bra_of(P, x) ? 1.0 : bd) * sqrt(p[x]);
             s += p[x];
           }
-          for (int x = 0; x < P.d2; ++x) p[x] /= s;
+          ok = s > 0.0 && isfinite(s);   // false when b = 0 leaves no digit
+          if (ok)
+            for (int x = 0; x < P.d2; ++x) p[x] /= s;
         }
+      }
+      if (ok) {
         const U64x4 rw = philox4x64_10((uint64_t)ch, draw, (uint64_t)i, 3ull, seed, 0ull);
         const double u = (double)(rw.v[0] >> 11) * 0x1.0p-53;
         double cum = 0.0;
@@ -232,7 +237,7 @@ __global__ void __launch_bounds__(NT) k_direct_row(Prob P, Prob Q, DirectLayout 
         lp += log(p[x_pick]);
         S[i] = (uint8_t)x_pick;
       } else {
-        set_status(status, isfinite(tot) ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
+        set_status(status, isfinite(tot) && isfinite(bd) ? PEPS_ERR_ZERO_AMPLITUDE : PEPS_ERR_NONFINITE);
         lp = -INFINITY;
         for (int k = i; k < P.N; ++k) S[k] = 0;
       }

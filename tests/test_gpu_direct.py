@@ -285,3 +285,28 @@ def test_direct_product_state_closed_form_and_tiny_chi_dl():
     assert np.all(np.isfinite(lp.cpu().numpy()))
     n = _compare(Lattice(3, 3, D=2, chi=4), th, 4, 1, 53, 0, cfg.cpu().numpy(), lp.cpu().numpy())
     assert n >= 30
+
+
+def test_direct_zero_diagonal_weight():
+    """b_diag = 0 excludes diagonal digits (s = s') from p_4: on random
+    tensors no drawn digit is diagonal; on the exact beta = 0 identity, where
+    only diagonal digits have nonzero marginals, no digit is left, and every
+    chain reports a zero amplitude with log p = -inf and zero digits."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct b_diag = 0")
+    desc = p.Desc(3, 3, 2, 4)
+    b = torch.zeros(1, dtype=torch.float64, device=dev)
+    th = torch.tensor(synth.theta_random_unit(3, 3, 2, 2, seed=131), device=dev)
+    cfg, lp, st = p.peps_direct_sample(desc, th, 64, 16, seed=61, reweight=True, b_diag=b)
+    torch.cuda.synchronize()
+    assert p.check(st) == 0
+    c = cfg.cpu().numpy()
+    assert np.all(c // 2 != c % 2)
+    assert np.all(np.isfinite(lp.cpu().numpy()))
+    th0 = torch.tensor(synth.theta_identity(3, 3, 2, 2, noise=0.0, seed=0), device=dev)
+    cfg, lp, st = p.peps_direct_sample(desc, th0, 16, 16, seed=61, reweight=True, b_diag=b)
+    torch.cuda.synchronize()
+    assert st.item() == -6
+    assert np.all(lp.cpu().numpy() == -np.inf)
+    assert np.all(cfg.cpu().numpy() == 0)
