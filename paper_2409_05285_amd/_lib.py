@@ -92,7 +92,7 @@ def _load():
     lib.peps_direct_workspace_bytes.argtypes = [P, c_int64, c_int32, POINTER(c_size_t)]
     lib.peps_direct_workspace_bytes.restype = c_int32
     lib.peps_direct_sample.argtypes = [P, c_void_p, c_int32, c_int32, c_uint64, c_uint64, c_int32, c_void_p, c_int32,
-                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+                                       c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
     lib.peps_direct_sample.restype = c_int32
     lib.peps_importance_weights.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.peps_importance_weights.restype = c_int32

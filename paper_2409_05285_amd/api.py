@@ -452,12 +452,16 @@ def peps_direct_workspace_bytes(desc: Desc, n_chains, chi_dl) -> int:
 
 
 def peps_direct_sample(desc: Desc, theta, n_chains, chi_dl, seed, draw=0, reweight=False, b_diag=None,
-                       update_b=False, status=None, out=None, ws=None, trace=None):
+                       update_b=False, reuse_double_layer=False, status=None, out=None, ws=None, trace=None):
     """Direct (autoregressive) draws, one configuration per chain.  Returns
     (configs [n, N] u8, log_p [n] f64, status).  `b_diag` (float64 [1] on the
     device) is read when reweight and updated in place when update_b.  `out`
     may supply (configs, log_p) tensors; `ws` a uint8 workspace of at least
-    peps_direct_workspace_bytes(desc, n_chains, chi_dl) bytes."""
+    peps_direct_workspace_bytes(desc, n_chains, chi_dl) bytes.  With
+    reuse_double_layer the double layer of the previous call on the same
+    workspace is reused (theta unchanged since; needs an explicit `ws`)."""
+    if reuse_double_layer and ws is None:
+        raise ValueError("reuse_double_layer needs the workspace of the previous call (ws=)")
     theta = _theta(desc, theta)
     _check_dev(theta, b_diag)
     dev = theta.device
@@ -476,7 +480,8 @@ def peps_direct_sample(desc: Desc, theta, n_chains, chi_dl, seed, draw=0, reweig
     need = peps_direct_workspace_bytes(desc, n, chi_dl)
     ws = _own_ws(ws, "direct", need, dev)
     code = LIB.peps_direct_sample(ctypes.byref(desc.c()), _ptr(theta), n, int(chi_dl), int(seed), int(draw),
-                                  int(bool(reweight)), _ptr(b_diag), int(bool(update_b)), _ptr(configs), _ptr(log_p),
+                                  int(bool(reweight)), _ptr(b_diag), int(bool(update_b)),
+                                  int(bool(reuse_double_layer)), _ptr(configs), _ptr(log_p),
                                   _ptr(status), _ptr(ws), ws.numel(), _tr(trace), _stream())
     _raise(code, "peps_direct_sample")
     return configs, log_p, status

@@ -93,6 +93,7 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
         chi_dl = desc.chi * desc.chi if chi_dl is None else int(chi_dl)
         b_diag = torch.tensor([float(b_diag0)], dtype=torch.float64, device=dev)
         log_p = torch.empty(S * n, dtype=torch.float64, device=dev)
+        dws = torch.empty(api.peps_direct_workspace_bytes(desc, n, chi_dl), dtype=torch.uint8, device=dev)
     records = []
     for step in range(step0, step0 + n_steps):
         beta_phys = 4.0 * tau * step
@@ -106,8 +107,10 @@ def cool(desc: api.Desc, theta, configs, n_steps, sweeps_per_step, tau, eps, see
         if direct:
             for k in range(S):
                 sl = slice(k * n, (k + 1) * n)
+                # the draws of one step share theta: the double layer is built by the first
                 api.peps_direct_sample(d, theta, n, chi_dl, seed, draw=gsweep + k, reweight=reweight, b_diag=b_diag,
-                                       update_b=reweight and k == S - 1, status=status, out=(samples[sl], log_p[sl]))
+                                       update_b=reweight and k == S - 1, reuse_double_layer=k > 0, status=status,
+                                       out=(samples[sl], log_p[sl]), ws=dws)
             configs.copy_(samples[(S - 1) * n:])
             la, _, e, _ = api.peps_eval_batch(d, theta, samples, status=status)
             O, _, _ = api.peps_grad_batch(d, theta, samples, status=status)

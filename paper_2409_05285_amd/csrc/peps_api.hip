@@ -600,16 +600,19 @@ static peps_status direct_setup(const peps_desc* d, int32_t chi_dl, Prob& P, Pro
 // Byte offsets of the regions of a direct-sampling workspace: the chains'
 // boundary workspaces, the double-layer tensors, the double layer's
 // one-chain workspace, its all-zero configuration, the draw scratch.
+// The double layer (theta only) comes first, at offsets that do not depend
+// on the number of chains, so that a later call may reuse it.
 struct DirectRegions {
-  size_t eth, wsq, cfgq, dws, total;
+  size_t eth, wsq, cfgq, w, dws, total;
 };
 static DirectRegions direct_regions(const Prob& P, const Prob& Q, const DirectLayout& L, int64_t n) {
   auto pad = [](size_t x) { return (x + 255) & ~(size_t)255; };
   DirectRegions g;
-  size_t off = pad((size_t)n * P.chain_stride * sizeof(double));
+  size_t off = 0;
   g.eth = off;  off += pad((size_t)Q.np * sizeof(double));
   g.wsq = off;  off += pad((size_t)Q.chain_stride * sizeof(double));
   g.cfgq = off; off += pad((size_t)P.N);
+  g.w = off;    off += pad((size_t)n * P.chain_stride * sizeof(double));
   g.dws = off;  off += (size_t)n * L.stride * sizeof(double);
   g.total = off;
   return g;
@@ -627,10 +630,11 @@ peps_status peps_direct_workspace_bytes(const peps_desc* d, int64_t n_chains, in
 
 peps_status peps_direct_sample(const peps_desc* d, const double* theta, int32_t n_chains, int32_t chi_dl,
                                uint64_t seed, uint64_t draw, int32_t reweight, double* b_diag, int32_t update_b,
-                               uint8_t* configs, double* log_p, int32_t* status, void* ws, size_t ws_bytes,
-                               peps_trace* trace, peps_stream_t stream) {
+                               int32_t reuse_double_layer, uint8_t* configs, double* log_p, int32_t* status,
+                               void* ws, size_t ws_bytes, peps_trace* trace, peps_stream_t stream) {
   if (n_chains < 0 || n_chains > (1 << 24)) return PEPS_ERR_ARG;
   if ((reweight != 0 && reweight != 1) || (update_b != 0 && update_b != 1)) return PEPS_ERR_ARG;
+  if (reuse_double_layer != 0 && reuse_double_layer != 1) return PEPS_ERR_ARG;
   Prob P, Q;
   DirectLayout L;
   peps_status s = direct_setup(d, chi_dl, P, Q, L);
@@ -641,14 +645,16 @@ peps_status peps_direct_sample(const peps_desc* d, const double* theta, int32_t 
   if (ws_bytes < g.total) return PEPS_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
-  double* w = (double*)base;
+  double* w = (double*)(base + g.w);
   double* eth = (double*)(base + g.eth);
   double* wsq = (double*)(base + g.wsq);
   uint8_t* cfgq = (uint8_t*)(base + g.cfgq);
   double* dws = (double*)(base + g.dws);
   const int n = n_chains;
-  TIMED(PEPS_K_DIRECT, launch_double_layer(P, Q, theta, eth, cfgq, st));
-  for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, compress_row(Q, 1, 1, r, eth, cfgq, wsq, status, st));
+  if (!reuse_double_layer) {
+    TIMED(PEPS_K_DIRECT, launch_double_layer(P, Q, theta, eth, cfgq, st));
+    for (int r = P.L1 - 1; r >= 1; --r) TIMED(PEPS_K_COMPRESS, compress_row(Q, 1, 1, r, eth, cfgq, wsq, status, st));
+  }
   for (int r = 0; r < P.L1; ++r) {
     TIMED(PEPS_K_DIRECT, launch_direct_row(P, Q, L, n, r, theta, eth, configs, w, wsq, dws, seed, draw, reweight,
                                            b_diag, log_p, status, st));

@@ -178,14 +178,15 @@ def test_direct_sampling_entry_points_check_their_arguments():
     with pytest.raises(p.PepsError):     # D^6 chi^2 chi_dl intermediates beyond the kernel's limit
         p.peps_direct_workspace_bytes(p.Desc(6, 6, 4, 16), 1, 64)
     v = ctypes.c_void_p(0x1000)
-    call = lambda n, chi_dl, rw, bd, ub, ws_bytes: LIB.peps_direct_sample(
-        ctypes.byref(c), v, n, chi_dl, 1, 0, rw, bd, ub, v, v, v, v, ws_bytes, None, None)
+    call = lambda n, chi_dl, rw, bd, ub, ws_bytes, reuse=0: LIB.peps_direct_sample(
+        ctypes.byref(c), v, n, chi_dl, 1, 0, rw, bd, ub, reuse, v, v, v, v, ws_bytes, None, None)
     assert call(-1, 16, 0, None, 0, 1 << 40) == -1
     assert call(4, 0, 0, None, 0, 1 << 40) == -1
     assert call(4, 16, 2, None, 0, 1 << 40) == -1
     assert call(4, 16, 1, None, 0, 1 << 40) == -1      # reweighting needs b_diag
     assert call(4, 16, 0, None, 1, 1 << 40) == -1      # so does its update
     assert call(4, 16, 0, None, 0, 1000) == -4         # workspace too small
+    assert call(4, 16, 0, None, 0, 1 << 40, 2) == -1   # reuse flag is 0 or 1
     assert call(0, 16, 0, None, 0, 0) == 0             # nothing to draw
     assert LIB.peps_importance_weights(0, v, v, v, None) == -1
     assert LIB.peps_importance_weights(5, None, v, v, None) == -1

@@ -197,6 +197,33 @@ def test_direct_degenerate_calls():
     assert torch.equal(la_[:7], lb_)
 
 
+def test_direct_reuse_double_layer_is_bit_identical():
+    """reuse_double_layer: draws on a workspace whose double layer an earlier
+    call with the same theta built (and with another number of chains) are
+    bit-identical to draws that build it themselves."""
+    import paper_2409_05285_amd as p
+    dev = _dev()
+    _say("direct reuse of the double layer, 4x3 D=2 chi=4 chi_dl=9")
+    desc = p.Desc(4, 3, 2, 4)
+    th = synth.theta_random_unit(4, 3, 2, 2, seed=97)
+    theta = torch.tensor(th, device=dev)
+    ws = torch.empty(p.peps_direct_workspace_bytes(desc, 64, 9), dtype=torch.uint8, device=dev)
+    b1 = torch.tensor([0.6], dtype=torch.float64, device=dev)
+    b2 = b1.clone()
+    p.peps_direct_sample(desc, theta, 64, 9, seed=5, draw=0, ws=ws)
+    for n, draw in ((23, 1), (64, 2)):
+        a, la_, st = p.peps_direct_sample(desc, theta, n, 9, seed=5, draw=draw, reweight=True, b_diag=b1,
+                                          update_b=True, reuse_double_layer=True, ws=ws)
+        b, lb_, st2 = p.peps_direct_sample(desc, theta, n, 9, seed=5, draw=draw, reweight=True, b_diag=b2,
+                                           update_b=True)
+        torch.cuda.synchronize()
+        assert p.check(st) == 0 and p.check(st2) == 0
+        assert torch.equal(a, b) and torch.equal(la_, lb_)
+        assert torch.equal(b1, b2)
+    with pytest.raises(ValueError):
+        p.peps_direct_sample(desc, theta, 4, 9, seed=5, reuse_double_layer=True)
+
+
 def test_direct_sampling_cooling_2x2_matches_ed():
     """The cooling loop with direct sampling (Appendix A): p_4 draws with the
     dynamic diagonal weight, Eq. A7 importance weights in every average and
