@@ -50,19 +50,38 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// Whether a k-map is unit-stride inside every aligned group of four indices
+// (offset(4g + u) = offset(4g) + u) with offset(4g) a multiple of 4, and
+// whether a row / column map gives multiples of 4 only.
+__device__ inline bool map_unit4(Map2 mk) {
+  return (mk.n2 == 1 && mk.s1 == 1) || (mk.n2 % 4 == 0 && mk.s2 == 1 && mk.s1 % 4 == 0);
+}
+__device__ inline bool map_mult4(Map2 mm) { return mm.s1 % 4 == 0 && (mm.n2 == 1 || mm.s2 % 4 == 0); }
+
 // C(m, n) = sum_k A(m, k) B(k, n) for m < M, n < N, k < K, with
 //   A(m, k) = A[am(m) + ak(k)], B(k, n) = B[bk(k) + bn(n)], C at cm(m) + cn(n).
 // Tiles of 16 x 16 are dealt round-robin to the waves of the workgroup.
 // The stored value is the accumulator times `osc`; when `wmax` is given,
 // wave w writes the largest stored magnitude of its tiles to wmax[w].
 // Ends with a workgroup barrier.
+//
+// Inside each block of 16 k, lane group q (lanes 16q..16q+15) takes the
+// four consecutive indices 16 j + 4 q + u, u = 0..3, one per MFMA step, so
+// that an operand whose k-map is unit-stride in aligned groups of four
+// (and K a multiple of 4) is read with one vector load per lane instead of
+// four scalar ones: the address unit, which the gathers keep busy, then
+// handles a quarter of the load instructions for that operand.
 template <typename T>
 __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn,
                                int M, int N, int K, T osc = T(1), float* wmax = nullptr) {
   using MF = Mfma<T>;
+  typedef T V4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  constexpr uintptr_t VAL = 4 * sizeof(T) - 1;
+  const bool vecA = (K & 3) == 0 && map_unit4(ak) && map_mult4(am) && ((uintptr_t)A & VAL) == 0;
+  const bool vecB = (K & 3) == 0 && map_unit4(bk) && map_mult4(bn) && ((uintptr_t)B & VAL) == 0;
   float mx = 0.0f;
   for (int t = wave; t < tm * tn; t += nw) {
     const int m0 = (t / tn) << 4, n0 = (t % tn) << 4;
@@ -70,20 +89,30 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
     const bool mv = m < M, nv = n < N;
     const int ao = mv ? am(m) : 0, bo = nv ? bn(n) : 0;
     typename MF::acc c = {0, 0, 0, 0};
-    // KU k-steps per batch: all their operand loads are issued before the
-    // first MFMA of the batch, so the loads of a wave overlap
-    constexpr int KU = 4;
-    for (int k0 = 0; k0 < K; k0 += 4 * KU) {
-      T a[KU], b[KU];
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      const int kg = k0 + 4 * lk;   // this lane group's four k
+      T a[4], b[4];
+      // all operand loads of the block are issued before its first MFMA
+      if (vecA) {
+        const bool ok = mv && kg < K;
+        const V4 v = *(const V4*)(A + (ok ? ao + ak(kg) : 0));   // A[0..3] exist: K >= 4
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int k = k0 + 4 * u + lk;
-        const bool kv = k < K;
-        a[u] = (mv && kv) ? A[ao + ak(k)] : T(0);
-        b[u] = (nv && kv) ? B[bk(k) + bo] : T(0);
+        for (int u = 0; u < 4; ++u) a[u] = ok ? v[u] : T(0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (mv && kg + u < K) ? A[ao + ak(kg + u)] : T(0);
+      }
+      if (vecB) {
+        const bool ok = nv && kg < K;
+        const V4 v = *(const V4*)(B + (ok ? bo + bk(kg) : 0));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = ok ? v[u] : T(0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = (nv && kg + u < K) ? B[bk(kg + u) + bo] : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < KU; ++u) c = MF::run(a[u], b[u], c);
+      for (int u = 0; u < 4; ++u) c = MF::run(a[u], b[u], c);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
