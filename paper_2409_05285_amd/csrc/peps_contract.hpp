@@ -65,12 +65,14 @@ __device__ inline bool map_mult4(Map2 mm) { return mm.s1 % 4 == 0 && (mm.n2 == 1
 // wave w writes the largest stored magnitude of its tiles to wmax[w].
 // Ends with a workgroup barrier.
 //
-// Inside each block of 16 k, lane group q (lanes 16q..16q+15) takes the
-// four consecutive indices 16 j + 4 q + u, u = 0..3, one per MFMA step, so
-// that an operand whose k-map is unit-stride in aligned groups of four
-// (and K a multiple of 4) is read with one vector load per lane instead of
-// four scalar ones: the address unit, which the gathers keep busy, then
-// handles a quarter of the load instructions for that operand.
+// When an operand's k-map is unit-stride in aligned groups of four (and K
+// is a multiple of 4), lane group q (lanes 16q..16q+15) takes, inside each
+// block of 16 k, the four consecutive indices 16 j + 4 q + u (u = 0..3, one
+// per MFMA step), so that operand is read with one vector load per lane
+// instead of four scalar ones: the address unit, which the gathers keep
+// busy, then handles a quarter of the load instructions for it.  Otherwise
+// step u takes 16 j + 4 u + q, which keeps the four lane groups of a
+// scalar load on neighbouring k.
 template <typename T>
 __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2 ak, const T* B, Map2 bk, Map2 bn,
                                int M, int N, int K, T osc = T(1), float* wmax = nullptr) {
@@ -82,6 +84,7 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
   constexpr uintptr_t VAL = 4 * sizeof(T) - 1;
   const bool vecA = (K & 3) == 0 && map_unit4(ak) && map_mult4(am) && ((uintptr_t)A & VAL) == 0;
   const bool vecB = (K & 3) == 0 && map_unit4(bk) && map_mult4(bn) && ((uintptr_t)B & VAL) == 0;
+  const bool grouped = vecA || vecB;
   float mx = 0.0f;
   for (int t = wave; t < tm * tn; t += nw) {
     const int m0 = (t / tn) << 4, n0 = (t % tn) << 4;
@@ -90,7 +93,7 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
     const int ao = mv ? am(m) : 0, bo = nv ? bn(n) : 0;
     typename MF::acc c = {0, 0, 0, 0};
     for (int k0 = 0; k0 < K; k0 += 16) {
-      const int kg = k0 + 4 * lk;   // this lane group's four k
+      const int kg = k0 + 4 * lk;   // this lane group's four k (grouped order)
       T a[4], b[4];
       // all operand loads of the block are issued before its first MFMA
       if (vecA) {
@@ -100,7 +103,10 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
         for (int u = 0; u < 4; ++u) a[u] = ok ? v[u] : T(0);
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = (mv && kg + u < K) ? A[ao + ak(kg + u)] : T(0);
+        for (int u = 0; u < 4; ++u) {
+          const int k = grouped ? kg + u : k0 + 4 * u + lk;
+          a[u] = (mv && k < K) ? A[ao + ak(k)] : T(0);
+        }
       }
       if (vecB) {
         const bool ok = nv && kg < K;
@@ -109,7 +115,10 @@ __device__ inline void wg_gemm(T* C, Map2 cm, Map2 cn, const T* A, Map2 am, Map2
         for (int u = 0; u < 4; ++u) b[u] = ok ? v[u] : T(0);
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) b[u] = (nv && kg + u < K) ? B[bk(kg + u) + bo] : T(0);
+        for (int u = 0; u < 4; ++u) {
+          const int k = grouped ? kg + u : k0 + 4 * u + lk;
+          b[u] = (nv && k < K) ? B[bk(k) + bo] : T(0);
+        }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) c = MF::run(a[u], b[u], c);
